@@ -1,0 +1,153 @@
+/*
+ * gsvd.h -- C-ABI of the MI355X (gfx950) mixed precision Gram-based thin SVD.
+ *
+ * Method: Carson, Ma, Shao, "Mixed precision thin SVD algorithms based on the
+ * Gram matrix" (arXiv 2603.11953).  For a full-column-rank tall-and-skinny A
+ * (m >= n) stored in a working precision u (FP32 or FP64), Algorithm 1 computes
+ *   M_h = A^T A in a higher precision u_h            (Alg. 1 steps 1-2, eq. (ATA))
+ *   M_h = V Sigma^2 V^T with a Jacobi method        (Alg. 1 step 3 / Alg. 2)
+ *   Sigma, V rounded to the working precision       (Alg. 1 steps 4-5)
+ *   U = A (V Sigma^{-1}) in the working precision    (Alg. 1 step 6, eq. (AV-0))
+ * Higher precision: FP64 for FP32 A; double-double (an unevaluated sum hi + lo
+ * of two FP64 numbers, unit roundoff ~2^-104) for FP64 A.
+ *
+ * Conventions for every entry point
+ *  - Matrices are column-major (element (i, j) at ptr[i + j * ld]), ld >= rows.
+ *  - Every data pointer is a DEVICE pointer owned by the caller; the library
+ *    never allocates device memory, never frees caller memory, and never
+ *    synchronises the host.  Work is enqueued on `stream` (a hipStream_t passed
+ *    as void*; NULL = the default stream) and completes asynchronously.
+ *  - Scratch memory is the caller's `work` buffer (device, 256-byte aligned,
+ *    at least the size the matching *_workspace_size call returns).
+ *  - Return value (synchronous): GSVD_OK (0) when the work was enqueued;
+ *    -k when argument k (1-based) is invalid; GSVD_ERR_* below otherwise.
+ *    Nothing is enqueued when the return value is not GSVD_OK.
+ *  - Numerical outcome (asynchronous): an int written to device memory `info`
+ *    per matrix: GSVD_INFO_* below.  On info != 0 the numeric outputs are
+ *    unspecified (but finite writes stay inside the caller's buffers).
+ */
+#ifndef GSVD_H
+#define GSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* working precision u of A, Sigma, V, U */
+enum { GSVD_F32 = 0, GSVD_F64 = 1 };
+
+/* how the Gram M_h = A^T A is formed */
+enum {
+    GSVD_GRAM_AUTO = 0,   /* library choice (currently PLAIN) */
+    GSVD_GRAM_PLAIN = 1,  /* FP32 A: exact FP64 products, FP64 sums; FP64 A: double-double */
+    GSVD_GRAM_SPLIT = 2   /* reserved for the operand-split MFMA form */
+};
+
+/* eigensolver of Alg. 1 step 3 */
+enum {
+    GSVD_EIG_AUTO = 0,       /* library choice (currently CHOL_JACOBI1) */
+    GSVD_EIG_JACOBI2 = 1,    /* two-sided Jacobi on M_h (Sec. 2.1, Remark 1); reserved */
+    GSVD_EIG_CHOL_JACOBI1 = 2 /* Algorithm 2: Cholesky of M_h at u_h, R cast to u,
+                                 one-sided Jacobi SVD of R (Thm. 2, Lemma 1) */
+};
+
+/* flags */
+#define GSVD_WANT_U 1u /* form U (otherwise only Sigma and V; dU may be NULL) */
+
+/* synchronous status codes (besides 0 and -k) */
+#define GSVD_OK 0
+#define GSVD_ERR_HIP (-100)         /* a HIP launch or runtime call failed */
+#define GSVD_ERR_UNSUPPORTED (-101) /* valid but not implemented combination */
+
+/* asynchronous per-matrix info codes */
+#define GSVD_INFO_OK 0
+#define GSVD_INFO_NOT_SPD 1       /* M_h not positive definite at u_h: A not of full rank */
+#define GSVD_INFO_NO_CONVERGE 2   /* Jacobi did not converge within max_sweeps */
+#define GSVD_INFO_NONFINITE 3     /* A (hence M_h) holds a NaN or Inf */
+
+#define GSVD_MAX_N 128            /* largest n the current kernels accept */
+#define GSVD_MAX_N_EIG_F64 96     /* FP64 working: largest n of the eigensolver stage
+                                     (larger n returns GSVD_ERR_UNSUPPORTED) */
+
+typedef struct {
+    int working;        /* GSVD_F32 or GSVD_F64 */
+    int gram;           /* GSVD_GRAM_* */
+    int eig;            /* GSVD_EIG_* */
+    int n_slices;       /* split Gram only; 0 = library choice */
+    double jacobi_tol;  /* rotation threshold: a pair p, q is rotated when
+                           |g_pq| > tol * sqrt(g_pp g_qq); 0 = sqrt(n) * u */
+    int max_sweeps;     /* 0 = 30 */
+    unsigned flags;     /* GSVD_WANT_U ... */
+} gsvd_opts;
+
+/* Fill *o with the defaults for the given working precision (WANT_U set). */
+void gsvd_opts_default(gsvd_opts *o, int working);
+
+/* Human-readable text for a return value or an info code (static storage). */
+const char *gsvd_status_string(int code);
+
+/* ---------------------------------------------------------------------------
+ * Whole method (Alg. 1 steps 1-6).
+ *
+ * gsvd_thin: thin SVD A = U diag(S) V^T of the m x n matrix dA (lda >= m,
+ * m >= n >= 1, n <= GSVD_MAX_N), all in the working precision o->working.
+ * Outputs: dS (n, descending), dV (n x n, ldv >= n), dU (m x n, ldu >= m, only
+ * with GSVD_WANT_U), *dInfo (one int).  Column j of V has its entry of largest
+ * magnitude positive; U = A (V diag(S)^{-1}) inherits that sign.
+ * Arguments: 1 m, 2 n, 3 dA, 4 lda, 5 dS, 6 dV, 7 ldv, 8 dU, 9 ldu, 10 work,
+ * 11 work_bytes, 12 dInfo, 13 o, 14 stream.
+ * ------------------------------------------------------------------------- */
+size_t gsvd_thin_workspace_size(int64_t m, int64_t n, const gsvd_opts *o);
+int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda,
+              void *dS, void *dV, int64_t ldv, void *dU, int64_t ldu,
+              void *work, size_t work_bytes, int *dInfo,
+              const gsvd_opts *o, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * The steps one at a time (same conventions).
+ *
+ * gsvd_gram (Alg. 1 steps 1-2, eq. (ATA)): M_h = A^T A in the higher precision,
+ * written full and symmetric to dMhi (n x n, ldm >= n) and, for FP64 A, the
+ * low parts of the double-double entries to dMlo (required for FP64 A; for
+ * FP32 A it may be NULL, else it receives the rounding error of each FP64
+ * entry as a second plane).  The split-m partial sums are combined by a
+ * fixed-shape tree, so the result is bitwise reproducible for given (m, n).
+ * Arguments: 1 m, 2 n, 3 dA, 4 lda, 5 dMhi, 6 dMlo, 7 ldm, 8 work, 9 work_bytes,
+ * 10 o, 11 stream.
+ * ------------------------------------------------------------------------- */
+size_t gsvd_gram_workspace_size(int64_t m, int64_t n, const gsvd_opts *o);
+int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda,
+              double *dMhi, double *dMlo, int64_t ldm,
+              void *work, size_t work_bytes, const gsvd_opts *o, void *stream);
+
+/*
+ * gsvd_eig (Alg. 1 steps 3-5; Algorithm 2 for GSVD_EIG_CHOL_JACOBI1): from the
+ * higher precision Gram (dMhi, dMlo as written by gsvd_gram; dMlo may be NULL
+ * for FP32 working) compute S (n, descending, working precision), V (n x n,
+ * ldv >= n, working precision) and W = fl(V diag(S)^{-1}) (n x n, ldw >= n,
+ * working precision, the matrix that Alg. 1 step 6 multiplies A by), and *dInfo.
+ * Arguments: 1 n, 2 dMhi, 3 dMlo, 4 ldm, 5 dS, 6 dV, 7 ldv, 8 dW, 9 ldw,
+ * 10 dInfo, 11 work, 12 work_bytes, 13 o, 14 stream.
+ */
+size_t gsvd_eig_workspace_size(int64_t n, const gsvd_opts *o);
+int gsvd_eig(int64_t n, const double *dMhi, const double *dMlo, int64_t ldm,
+             void *dS, void *dV, int64_t ldv, void *dW, int64_t ldw, int *dInfo,
+             void *work, size_t work_bytes, const gsvd_opts *o, void *stream);
+
+/*
+ * gsvd_u_recover (Alg. 1 step 6, eq. (AV-0)): dU = dA * dW in the working
+ * precision (m x n times n x n; ldu >= m, ldw >= n).  No workspace.
+ * Arguments: 1 m, 2 n, 3 dA, 4 lda, 5 dW, 6 ldw, 7 dU, 8 ldu, 9 o, 10 stream.
+ */
+int gsvd_u_recover(int64_t m, int64_t n, const void *dA, int64_t lda,
+                   const void *dW, int64_t ldw, void *dU, int64_t ldu,
+                   const gsvd_opts *o, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSVD_H */

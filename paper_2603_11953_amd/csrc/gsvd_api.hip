@@ -1,0 +1,219 @@
+// Host entry points of the C-ABI declared in include/gsvd.h.
+//
+// Every call validates its arguments synchronously, carves its workspace, and
+// enqueues kernels on the caller's stream; nothing allocates device memory or
+// synchronises the host.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "gsvd.h"
+#include "gsvd_internal.hpp"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+double unit_roundoff(int working) { return working == GSVD_F64 ? 0x1p-53 : 0x1p-24; }
+
+// Checks shared by every entry point that takes options.
+int check_opts(const gsvd_opts *o, int argpos) {
+    if (o == nullptr) return -argpos;
+    if (o->working != GSVD_F32 && o->working != GSVD_F64) return -argpos;
+    if (o->gram != GSVD_GRAM_AUTO && o->gram != GSVD_GRAM_PLAIN && o->gram != GSVD_GRAM_SPLIT)
+        return -argpos;
+    if (o->eig != GSVD_EIG_AUTO && o->eig != GSVD_EIG_JACOBI2 && o->eig != GSVD_EIG_CHOL_JACOBI1)
+        return -argpos;
+    if (o->max_sweeps < 0 || o->jacobi_tol < 0.0 || o->n_slices < 0) return -argpos;
+    return 0;
+}
+
+int check_supported(const gsvd_opts *o) {
+    if (o->gram == GSVD_GRAM_SPLIT) return GSVD_ERR_UNSUPPORTED;
+    if (o->eig == GSVD_EIG_JACOBI2) return GSVD_ERR_UNSUPPORTED;
+    return 0;
+}
+
+int check_eig_supported(const gsvd_opts *o, int64_t n) {
+    if (int e = check_supported(o)) return e;
+    if (o->working == GSVD_F64 && n > GSVD_MAX_N_EIG_F64) return GSVD_ERR_UNSUPPORTED;
+    return 0;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+size_t wsize(int working) { return working == GSVD_F64 ? 8 : 4; }
+
+struct ThinLayout {
+    size_t mhi, mlo, w, part, total;
+};
+
+ThinLayout thin_layout(int64_t m, int64_t n, const gsvd_opts *o) {
+    ThinLayout L{};
+    const size_t nn = (size_t)n * (size_t)n;
+    gsvd::GramPlan p = gsvd::gram_plan(m, n);
+    size_t off = 0;
+    L.mhi = off;
+    off = align_up(off + nn * sizeof(double));
+    L.mlo = off;
+    off = align_up(off + nn * sizeof(double));
+    L.w = off;
+    off = align_up(off + nn * wsize(o->working));
+    L.part = off;
+    off = align_up(off + p.part_bytes);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gsvd_opts_default(gsvd_opts *o, int working) {
+    if (o == nullptr) return;
+    memset(o, 0, sizeof(*o));
+    o->working = working;
+    o->gram = GSVD_GRAM_AUTO;
+    o->eig = GSVD_EIG_AUTO;
+    o->n_slices = 0;
+    o->jacobi_tol = 0.0;
+    o->max_sweeps = 0;
+    o->flags = GSVD_WANT_U;
+}
+
+const char *gsvd_status_string(int code) {
+    switch (code) {
+        case GSVD_OK: return "success";
+        case GSVD_INFO_NOT_SPD: return "info 1: Gram matrix not positive definite (A not of full column rank at the Gram precision)";
+        case GSVD_INFO_NO_CONVERGE: return "info 2: Jacobi iteration did not converge within max_sweeps";
+        case GSVD_INFO_NONFINITE: return "info 3: input holds NaN or Inf";
+        case GSVD_ERR_HIP: return "HIP launch or runtime error";
+        case GSVD_ERR_UNSUPPORTED: return "option combination not implemented";
+        default: break;
+    }
+    if (code < 0 && code > -100) return "invalid argument (the value is minus its 1-based position)";
+    return "unknown status";
+}
+
+size_t gsvd_gram_workspace_size(int64_t m, int64_t n, const gsvd_opts *o) {
+    (void)o;
+    if (m < 1 || n < 1) return 0;
+    return align_up(gsvd::gram_plan(m, n).part_bytes);
+}
+
+int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda, double *dMhi, double *dMlo,
+              int64_t ldm, void *work, size_t work_bytes, const gsvd_opts *o, void *stream) {
+    if (m < 1) return -1;
+    if (n < 1 || n > GSVD_MAX_N || n > m) return -2;
+    if (dA == nullptr) return -3;
+    if (lda < m) return -4;
+    if (dMhi == nullptr) return -5;
+    if (int e = check_opts(o, 10)) return e;
+    if (o->working == GSVD_F64 && dMlo == nullptr) return -6;
+    if (ldm < n) return -7;
+    const size_t need = gsvd_gram_workspace_size(m, n, o);
+    if (work == nullptr || !aligned(work, kAlign)) return -8;
+    if (work_bytes < need) return -9;
+    if (int e = check_supported(o)) return e;
+    gsvd::GramPlan p = gsvd::gram_plan(m, n);
+    hipError_t err = gsvd::gram_launch(o->working, m, n, dA, lda, dMhi, dMlo, ldm, work, p,
+                                       (hipStream_t)stream);
+    return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
+}
+
+size_t gsvd_eig_workspace_size(int64_t n, const gsvd_opts *o) {
+    (void)n;
+    (void)o;
+    return 0;
+}
+
+int gsvd_eig(int64_t n, const double *dMhi, const double *dMlo, int64_t ldm, void *dS, void *dV,
+             int64_t ldv, void *dW, int64_t ldw, int *dInfo, void *work, size_t work_bytes,
+             const gsvd_opts *o, void *stream) {
+    (void)work;
+    (void)work_bytes;
+    if (n < 1 || n > GSVD_MAX_N) return -1;
+    if (dMhi == nullptr) return -2;
+    if (int e = check_opts(o, 13)) return e;
+    if (o->working == GSVD_F64 && dMlo == nullptr) return -3;
+    if (ldm < n) return -4;
+    if (dS == nullptr) return -5;
+    if (dV == nullptr) return -6;
+    if (ldv < n) return -7;
+    if (dW == nullptr) return -8;
+    if (ldw < n) return -9;
+    if (dInfo == nullptr) return -10;
+    if (int e = check_eig_supported(o, n)) return e;
+    const double tol = o->jacobi_tol > 0 ? o->jacobi_tol
+                                         : __builtin_sqrt((double)n) * unit_roundoff(o->working);
+    const int sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    hipError_t err = gsvd::eig_launch(o->working, n, dMhi, dMlo, ldm, dS, dV, ldv, dW, ldw, dInfo,
+                                      tol, sweeps, (hipStream_t)stream);
+    return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
+}
+
+int gsvd_u_recover(int64_t m, int64_t n, const void *dA, int64_t lda, const void *dW, int64_t ldw,
+                   void *dU, int64_t ldu, const gsvd_opts *o, void *stream) {
+    if (m < 1) return -1;
+    if (n < 1 || n > GSVD_MAX_N) return -2;
+    if (dA == nullptr) return -3;
+    if (lda < m) return -4;
+    if (dW == nullptr) return -5;
+    if (ldw < n) return -6;
+    if (dU == nullptr) return -7;
+    if (ldu < m) return -8;
+    if (int e = check_opts(o, 9)) return e;
+    hipError_t err = gsvd::urecover_launch(o->working, m, n, dA, lda, dW, ldw, dU, ldu,
+                                           (hipStream_t)stream);
+    return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
+}
+
+size_t gsvd_thin_workspace_size(int64_t m, int64_t n, const gsvd_opts *o) {
+    if (m < 1 || n < 1 || o == nullptr) return 0;
+    return thin_layout(m, n, o).total;
+}
+
+int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void *dV, int64_t ldv,
+              void *dU, int64_t ldu, void *work, size_t work_bytes, int *dInfo,
+              const gsvd_opts *o, void *stream) {
+    if (m < 1) return -1;
+    if (n < 1 || n > GSVD_MAX_N || n > m) return -2;
+    if (dA == nullptr) return -3;
+    if (lda < m) return -4;
+    if (dS == nullptr) return -5;
+    if (dV == nullptr) return -6;
+    if (ldv < n) return -7;
+    if (int e = check_opts(o, 13)) return e;
+    const bool want_u = (o->flags & GSVD_WANT_U) != 0;
+    if (want_u && dU == nullptr) return -8;
+    if (want_u && ldu < m) return -9;
+    if (work == nullptr || !aligned(work, kAlign)) return -10;
+    ThinLayout L = thin_layout(m, n, o);
+    if (work_bytes < L.total) return -11;
+    if (dInfo == nullptr) return -12;
+    if (int e = check_eig_supported(o, n)) return e;
+
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)work;
+    double *Mhi = (double *)(base + L.mhi);
+    double *Mlo = (double *)(base + L.mlo);
+    void *W = base + L.w;
+    gsvd::GramPlan p = gsvd::gram_plan(m, n);
+    hipError_t err = gsvd::gram_launch(o->working, m, n, dA, lda, Mhi, Mlo, n, base + L.part, p, st);
+    if (err != hipSuccess) return GSVD_ERR_HIP;
+    const double tol = o->jacobi_tol > 0 ? o->jacobi_tol
+                                         : __builtin_sqrt((double)n) * unit_roundoff(o->working);
+    const int sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    err = gsvd::eig_launch(o->working, n, Mhi, Mlo, n, dS, dV, ldv, W, n, dInfo, tol, sweeps, st);
+    if (err != hipSuccess) return GSVD_ERR_HIP;
+    if (want_u) {
+        err = gsvd::urecover_launch(o->working, m, n, dA, lda, W, n, dU, ldu, st);
+        if (err != hipSuccess) return GSVD_ERR_HIP;
+    }
+    return GSVD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,43 @@
+// Internal launch interfaces shared by the host entry points (gsvd_api.hip)
+// and the kernel files.  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gsvd {
+
+constexpr int GSVD_KMAX_N = 128;      // largest n the kernels are sized for
+constexpr int GSVD_KMAX_N_F64 = 96;   // FP64 working: R and V (FP64) must share LDS
+
+// Launch geometry of the split-m Gram (gram.hip).
+struct GramPlan {
+    int nbh;                 // ceil(n / 2): 2x2 blocks per side
+    int nblk;                // blocks in the upper triangle
+    int threads;             // lanes per workgroup
+    int grid_x;              // workgroups across the block list
+    int64_t rows_per_split;  // rows of A per slab
+    int64_t nsplit;          // slabs
+    size_t lds_bytes;        // dynamic LDS per workgroup
+    size_t part_bytes;       // workspace for the per-slab partial sums
+};
+
+GramPlan gram_plan(int64_t m, int64_t n);
+hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
+                       double *Mhi, double *Mlo, int64_t ldm, void *part, const GramPlan &p,
+                       hipStream_t st);
+
+// Eigensolver stage (eig.hip).
+size_t eig_lds_bytes(int working, int64_t n);
+int eig_max_n(int working);
+int eig_threads(int64_t n);
+hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *Mlo, int64_t ldm,
+                      void *S, void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
+                      int max_sweeps, hipStream_t st);
+
+// U = A W (urecover.hip).
+hipError_t urecover_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
+                           const void *W, int64_t ldw, void *U, int64_t ldu, hipStream_t st);
+
+}  // namespace gsvd

@@ -1,0 +1,126 @@
+"""The C-ABI library loads, exports every function include/gsvd.h declares, and
+rejects bad arguments synchronously (no kernel is launched, so no GPU is needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2603_11953_amd as gs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(gsvd_\w+)\s*\(", txt))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    decl = _declared()
+    assert {"gsvd_thin", "gsvd_gram", "gsvd_eig", "gsvd_u_recover"} <= decl
+    out = subprocess.run(["nm", "-D", "--defined-only", gs.lib_path], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (gsvd_\w+)", out))
+    assert decl <= exported, decl - exported
+    for name in decl:
+        assert hasattr(gs.lib, name)
+
+
+def test_opts_default_and_status():
+    o = gs.opts(gs.GSVD_F64)
+    assert o.working == gs.GSVD_F64 and o.flags == gs.GSVD_WANT_U and o.max_sweeps == 0
+    assert gs.gsvd_status_string(0) == "success"
+    assert "info 1" in gs.gsvd_status_string(1)
+    assert "invalid argument" in gs.gsvd_status_string(-4)
+
+
+def test_workspace_sizes_positive_and_aligned():
+    for w in (gs.GSVD_F32, gs.GSVD_F64):
+        o = gs.opts(w)
+        for m, n in ((1, 1), (2000, 20), (1_000_000, 64), (4_000_000, 128)):
+            t = gs.gsvd_thin_workspace_size(m, n, ctypes.byref(o))
+            g = gs.gsvd_gram_workspace_size(m, n, ctypes.byref(o))
+            assert t > 0 and t % 256 == 0 and g % 256 == 0 and t >= g + 2 * n * n * 8
+
+
+FAKE = 0x7F0000000000  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(m=0), -1),
+    (dict(n=0), -2),
+    (dict(m=10, n=20), -2),
+    (dict(n=gs.GSVD_MAX_N + 1, m=10_000), -2),
+    (dict(A=None), -3),
+    (dict(lda=99), -4),
+    (dict(S=None), -5),
+    (dict(V=None), -6),
+    (dict(ldv=3), -7),
+    (dict(U=None), -8),
+    (dict(ldu=50), -9),
+    (dict(work=FAKE + 8), -10),
+    (dict(work_bytes=16), -11),
+    (dict(info=None), -12),
+])
+def test_thin_rejects_bad_arguments(args, code):
+    o = gs.opts(gs.GSVD_F64)
+    a = dict(m=100, n=8, A=FAKE, lda=100, S=FAKE, V=FAKE, ldv=8, U=FAKE, ldu=100, work=FAKE,
+             work_bytes=1 << 40, info=FAKE)
+    a.update(args)
+    rc = gs.gsvd_thin(a["m"], a["n"], a["A"], a["lda"], a["S"], a["V"], a["ldv"], a["U"], a["ldu"],
+                      a["work"], a["work_bytes"], a["info"], ctypes.byref(o), None)
+    assert rc == code
+
+
+def test_bad_options_rejected():
+    o = gs.opts(gs.GSVD_F64)
+    o.working = 7
+    rc = gs.gsvd_thin(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 100, FAKE, 1 << 40, FAKE,
+                      ctypes.byref(o), None)
+    assert rc == -13
+    rc = gs.gsvd_thin(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 100, FAKE, 1 << 40, FAKE, None, None)
+    assert rc == -13
+
+
+def test_gram_eig_u_reject_bad_arguments():
+    o = gs.opts(gs.GSVD_F64)
+    assert gs.gsvd_gram(100, 8, FAKE, 100, FAKE, None, 8, FAKE, 1 << 40, ctypes.byref(o), None) == -6
+    assert gs.gsvd_gram(100, 8, FAKE, 100, FAKE, FAKE, 7, FAKE, 1 << 40, ctypes.byref(o), None) == -7
+    assert gs.gsvd_gram(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 0, ctypes.byref(o), None) == -9
+    assert gs.gsvd_eig(8, FAKE, None, 8, FAKE, FAKE, 8, FAKE, 8, FAKE, None, 0,
+                       ctypes.byref(o), None) == -3
+    assert gs.gsvd_eig(8, FAKE, FAKE, 8, FAKE, FAKE, 8, FAKE, 8, None, None, 0,
+                       ctypes.byref(o), None) == -10
+    assert gs.gsvd_u_recover(100, 8, FAKE, 100, FAKE, 8, FAKE, 99, ctypes.byref(o), None) == -8
+
+
+def test_unsupported_combinations_report_so():
+    o = gs.opts(gs.GSVD_F64, gs.GSVD_GRAM_SPLIT)
+    rc = gs.gsvd_thin(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 100, FAKE, 1 << 40, FAKE,
+                      ctypes.byref(o), None)
+    assert rc == -101
+
+
+def test_single_hip_runtime_in_process():
+    """torch and libgsvd.so must share one HIP runtime (stream handles and pointers pass between them)."""
+    import torch  # noqa: F401
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                paths.add(line.split()[-1])
+    assert len(paths) == 1, paths
+
+
+def test_fp64_eigensolver_limit():
+    o = gs.opts(gs.GSVD_F64)
+    rc = gs.gsvd_thin(1000, 97, FAKE, 1000, FAKE, FAKE, 97, FAKE, 1000, FAKE, 1 << 40, FAKE,
+                      ctypes.byref(o), None)
+    assert rc == -101
