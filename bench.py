@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""Benchmark: thin-SVD throughput of the Gram-based mixed precision method on one MI355X.
+
+One step = one call of gsvd_thin (Gram in the higher precision, Algorithm 2
+eigensolver, U = A V Sigma^-1) on an input already resident in HBM.
+
+Workload (default): FP64 A = B D, m = 1,000,000, n = 64, kappa(B) = 100
+(log-spaced singular values), D log-spaced over 1e10 with the columns
+shuffled; plain form (double-double Gram).  Prints one JSON line.
+
+    value        = thin-SVD GFLOP/s = (m n (n + 1) + 2 m n^2) / t_step
+    gram_hbm_gbps = (m n w + n^2 8) / t_gram (the metric's second figure)
+    roofline     = the dominant kernel (the dd Gram, FP64-VALU bound)
+    cpu_baseline = the CPU oracle (dd Gram + dd Jacobi + dd U) on a row sample
+
+Accuracy is checked against the oracle after the timed region; the result
+records whether the paper's tolerances were met.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "thin-SVD GFLOP/s & Gram HBM GB/s at σ rel-err tol; split/batched vs plain"
+FP64_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # FP64 lane-operations per second, 1 per FMA
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--m", type=int, default=1_000_000)
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle accuracy check")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--cpu-rows", type=int, default=1_000_000,
+                    help="rows of A the CPU oracle processes for the baseline")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_11953_amd", "csrc")
+    for f in ("gram.hip", "dd_device.hpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(m: int, n: int):
+    """HBM bytes per launch of the dd Gram kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source and this shape."""
+    path = os.path.join(ROOT, "profiles", "gram_dd_m1e6_n64_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("m") != m or t.get("n") != n:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: use --gpus 1 "
+                                   "(the row-split multi-GPU design is described, not built)"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2603_11953_amd as gs
+    from gen import matrices as g
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    spec = g.spec_tall_f64(m=args.m)
+    m, n = spec.m, spec.n
+    t0 = time.time()
+    A = g.make_a(spec)
+    log(f"generated A {m}x{n} fp64 in {time.time() - t0:.1f}s")
+    dA = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev).t()
+    lda = m
+
+    w = gs.GSVD_F64
+    o = gs.opts(w, gs.GSVD_GRAM_PLAIN, gs.GSVD_EIG_CHOL_JACOBI1)
+    import ctypes
+    ob = ctypes.byref(o)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    V = gs.colmajor_empty(n, n, torch.float64, dev)
+    U = gs.colmajor_empty(m, n, torch.float64, dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    work = gs.workspace(gs.gsvd_thin_workspace_size(m, n, ob), dev)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(int(stream.cuda_stream))
+
+    def step():
+        rc = gs.gsvd_thin(m, n, dA.data_ptr(), lda, S.data_ptr(), V.data_ptr(), n, U.data_ptr(), m,
+                          work.data_ptr(), work.numel(), info.data_ptr(), ob, sp)
+        if rc != 0:
+            raise RuntimeError(f"gsvd_thin: {rc} {gs.gsvd_status_string(rc)}")
+
+    # phase entry points: the same kernels with the same launch shapes as inside gsvd_thin
+    Mhi = gs.colmajor_empty(n, n, torch.float64, dev)
+    Mlo = gs.colmajor_empty(n, n, torch.float64, dev)
+    Wm = gs.colmajor_empty(n, n, torch.float64, dev)
+    gwork = gs.workspace(gs.gsvd_gram_workspace_size(m, n, ob), dev)
+    S2 = torch.empty_like(S)
+    V2 = torch.empty_like(V)
+    info2 = torch.zeros_like(info)
+    U2 = torch.empty_like(U)
+
+    def ph_gram():
+        rc = gs.gsvd_gram(m, n, dA.data_ptr(), lda, Mhi.data_ptr(), Mlo.data_ptr(), n,
+                          gwork.data_ptr(), gwork.numel(), ob, sp)
+        assert rc == 0, rc
+
+    def ph_eig():
+        rc = gs.gsvd_eig(n, Mhi.data_ptr(), Mlo.data_ptr(), n, S2.data_ptr(), V2.data_ptr(), n,
+                         Wm.data_ptr(), n, info2.data_ptr(), None, 0, ob, sp)
+        assert rc == 0, rc
+
+    def ph_u():
+        rc = gs.gsvd_u_recover(m, n, dA.data_ptr(), lda, Wm.data_ptr(), n, U2.data_ptr(), m, ob, sp)
+        assert rc == 0, rc
+
+    def timed(fn, k, w_):
+        for _ in range(w_):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k  # ms
+
+    log("warmup + timed steps")
+    ms_step = timed(step, args.steps, args.warmup)
+    log(f"step {ms_step:.4f} ms")
+    ms_gram = timed(ph_gram, args.steps, 2)
+    ms_eig = timed(ph_eig, args.steps, 2)
+    ms_u = timed(ph_u, args.steps, 2)
+    log(f"phases: gram {ms_gram:.4f} eig {ms_eig:.4f} u {ms_u:.4f} ms")
+
+    flops = m * n * (n + 1) + 2 * m * n * n
+    gflops = flops / (ms_step * 1e-3) / 1e9
+    gram_bytes = m * n * 8 + n * n * 8
+    gram_gbps = gram_bytes / (ms_gram * 1e-3) / 1e9
+    dd_macs = m * n * (n + 1) // 2
+    alu_ops = 10 * dd_macs  # FP64 VALU operations of the dd multiply-accumulates
+    achieved = alu_ops / (ms_gram * 1e-3) / 1e12
+
+    result = {
+        "metric": METRIC,
+        "value": round(gflops, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"FP64 A=BD m={m} n={n} kappa(B)=1e2 kappa(D)=1e10 (log-spaced, columns "
+                        "shuffled); plain double-double Gram, Algorithm 2 eigensolver, MFMA U",
+            "m": m, "n": n, "gram": "plain-dd", "eig": "alg2-chol-jacobi1",
+        },
+        "gram_hbm_gbps": round(gram_gbps, 2),
+        "phases_ms": {"gram": round(ms_gram, 5), "eig": round(ms_eig, 5), "u": round(ms_u, 5)},
+        "roofline": {
+            "kernel": "gram dd stage (gram_partial_kernel<double,true> + gram_reduce_kernel)",
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": round(FP64_VALU_PEAK_TOPS, 2),
+            "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_VALU_PEAK_TOPS, 4),
+            "traffic": measured_traffic(m, n),
+            "work_per_launch": f"{alu_ops} FP64 VALU ops = 10 per dd-MAC x m n (n+1)/2 dd-MACs",
+        },
+    }
+
+    if not args.no_check:
+        from oracle import ref
+        torch.cuda.synchronize()
+        inf = int(info.item())
+        Sn = S.cpu().numpy()
+        Vn = V.t().contiguous().cpu().numpy().T
+        Un = np.asfortranarray(U.t().contiguous().cpu().numpy().T)
+        t1 = time.time()
+        oracle = ref.svd(A)
+        err = float(ref.sigma_rel_err(Sn, oracle).max())
+        orth = ref.orth(Un)
+        rows = np.random.default_rng(0).integers(0, m, 20000)
+        res = ref.resid(A, Un, Sn, Vn, rows=rows)
+        u = 2.0 ** -53
+        kb = oracle.kappa_b
+        acc = {
+            "info": inf,
+            "sigma_max_rel_err": err,
+            "sigma_tol_50nu_kappaB": 50 * n * u * kb,
+            "u_orth": orth,
+            "orth_tol_50nu": 50 * n * u,
+            "resid_sampled": res,
+            "kappa_b_oracle": kb,
+        }
+        acc["meets_tol"] = bool(inf == 0 and err <= acc["sigma_tol_50nu_kappaB"]
+                                and orth <= acc["orth_tol_50nu"] and res <= 50 * n * u)
+        result["accuracy"] = acc
+        log(f"oracle check {time.time() - t1:.1f}s: {acc}")
+
+    if not args.no_cpu:
+        from oracle import ref
+        ms_rows = min(args.cpu_rows, m)
+        As = np.asfortranarray(A[:ms_rows])
+        t2 = time.perf_counter()
+        o2 = ref.svd(As, want_kappa=False)
+        ref.u_rows_dd(As, o2.V_hi, o2.V_lo, o2.sigma_hi, o2.sigma_lo)
+        tc = time.perf_counter() - t2
+        fl_s = ms_rows * n * (n + 1) + 2 * ms_rows * n * n
+        result["cpu_baseline"] = {
+            "value": round(fl_s / tc / 1e9, 4),
+            "unit": "GFLOP/s",
+            "cores": ref.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {ms_rows} of {m} rows: dd Gram + dd two-sided Jacobi + dd U, "
+                      f"{tc:.1f} s",
+        }
+        log(f"cpu baseline {result['cpu_baseline']}")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
