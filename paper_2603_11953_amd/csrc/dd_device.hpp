@@ -49,6 +49,15 @@ __device__ __forceinline__ dd_t dd_add(dd_t x, dd_t y) {
 }
 
 __device__ __forceinline__ dd_t dd_neg(dd_t x) { return dd_t{-x.hi, -x.lo}; }
+
+// x - y with the error bound relative to |x| + |y| (one TwoSum on the high
+// parts, low parts added in FP64): enough where the backward error model is
+// componentwise in the operands, as in a Cholesky update.
+__device__ __forceinline__ dd_t dd_sub_fast(dd_t x, dd_t y) {
+    dd_t s = two_sum(x.hi, -y.hi);
+    s.lo += x.lo - y.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
 __device__ __forceinline__ dd_t dd_sub(dd_t x, dd_t y) { return dd_add(x, dd_neg(y)); }
 
 __device__ __forceinline__ dd_t dd_mul(dd_t x, dd_t y) {

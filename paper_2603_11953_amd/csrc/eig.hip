@@ -4,8 +4,10 @@
 //      a power of two 2^e_j so that H = D~^-1 M_h D~^-1 is formed exactly.
 //   2. Cholesky H = R_H^T R_H at the Gram precision (double-double for FP64
 //      working, where M_h carries a low plane; FP64 otherwise), right-looking,
-//      on the packed upper triangle held in LDS.  (Alg. 2 step 1.)
+//      on the full square held in LDS.  (Alg. 2 step 1.)
 //   3. R = working(R_H) D~  (Alg. 2 step 2; the power-of-two scaling is exact).
+//      R is further scaled by one global power of two so its largest column
+//      norm is about 1 (no overflow in the squared norms below; undone at the end).
 //   4. One-sided Jacobi SVD of R (Alg. 2 step 3): plane rotations applied to
 //      the columns of R (Hestenes), accumulated in V = J_1 J_2 ..., until
 //      every pair of columns is numerically orthogonal,
@@ -13,8 +15,14 @@
 //      setting in which right-handed one-sided Jacobi keeps each column's
 //      rounding errors relative to that column's norm (Demmel-Veselic), and
 //      the same rotations applied to V keep A V Sigma^-1 orthonormal however
-//      graded the columns of A are.  Round-robin ordering: n/2 disjoint pairs
-//      per step, one 16-lane group per pair, all in LDS.
+//      graded the columns of A are.
+//      Parallel ordering: round robin, n/2 disjoint pairs per step, one group
+//      of 8 lanes (half a DPP row) per pair.  A lane keeps rows gl, gl + 8, ...
+//      of the pair's two columns of R in registers for the step; the three
+//      inner products are reduced across the group with DPP moves arranged so
+//      all 8 lanes obtain bitwise identical sums, and the rotation parameters
+//      come from the hardware reciprocal / reciprocal square root refined by
+//      Newton steps.
 //   5. sigma_p = ||r_p||; ordering sigma_1 >= ... >= sigma_n; each V column
 //      signed so its entry of largest magnitude is positive (lowest index on
 //      ties); Sigma and V cast to the working precision (Alg. 1 steps 4-5);
@@ -22,7 +30,7 @@
 //      Alg. 1 step 6).
 //   Storage of R and V during the Jacobi: FP64 for FP64 working (n <= 96 fits
 //   LDS), FP32 for FP32 working (the SVD of R "at precision u"; n <= 128),
-//   with the dot products and rotation parameters evaluated in FP64.
+//   with the inner products and rotation parameters evaluated in FP64.
 #include <hip/hip_runtime.h>
 
 #include "dd_device.hpp"
@@ -30,21 +38,70 @@
 
 namespace gsvd {
 
-constexpr int GRP = 16;  // lanes per Jacobi pair
-constexpr int EIG_MAXREG = 10;  // packed entries per lane while repacking R
+constexpr int GRP = 8;  // lanes per Jacobi pair: half a DPP row
+constexpr int MAXREG = 32;  // entries of R per lane while it moves into Y (see eig_launch)
+
+// Column stride of R and V in LDS during the Jacobi: n rounded up to a
+// multiple of 256 bytes.
+template <typename TS>
+__host__ __device__ __forceinline__ int jac_ld(int n) {
+    constexpr int q = 256 / (int)sizeof(TS);
+    return (n + q - 1) / q * q;
+}
 
 struct EigShared {
     int flag_rot;
     int flag_bad;  // GSVD info code, 0 = fine
+    int emax;
 };
 
-__device__ __forceinline__ int packed_idx(int i, int j) { return j * (j + 1) / 2 + i; }  // i <= j
+// ---- cross-lane helpers on doubles (DPP within a row of 16 lanes)
 
-template <typename TW, typename TS, bool DDGRAM>
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over aligned groups of 8 lanes (half a DPP row).  Steps: xor 1, xor 2
+// (quad permutes), then the half-row mirror (lane i <-> 7 - i).  Every step
+// adds the values of two lanes that hold the same partial sums in swapped
+// order, so all 8 lanes end with the same bits.
+__device__ __forceinline__ double group_sum(double x) {
+    x += dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_d<0x141>(x);  // row_half_mirror
+    return x;
+}
+
+// ---- reciprocal and reciprocal square root: hardware estimate + Newton
+
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double h = x * y;
+        const double e = __builtin_fma(-h, y, 1.0);  // 1 - x y^2
+        y = __builtin_fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+template <typename TW, typename TS, bool DDGRAM, int RPL>
 __global__ void __launch_bounds__(1024)
 eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__restrict__ Mlo,
                         int64_t ldm, TW *__restrict__ S, TW *__restrict__ V, int64_t ldv,
-                        TW *__restrict__ W, int64_t ldw, int *__restrict__ info, double tol,
+                        TW *__restrict__ W, int64_t ldw, int *__restrict__ info, double tol2,
                         int max_sweeps) {
     extern __shared__ double lds[];
     __shared__ EigShared sh;
@@ -52,30 +109,32 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
     __shared__ double ssig[GSVD_KMAX_N];
     __shared__ int srank[GSVD_KMAX_N];
     __shared__ double ssign[GSVD_KMAX_N];
+    __shared__ dd_t rowk[GSVD_KMAX_N];
 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    const int npk = n * (n + 1) / 2;
 
     if (tid == 0) {
         sh.flag_rot = 0;
         sh.flag_bad = 0;
+        sh.emax = -100000;
     }
     __syncthreads();
 
     // ---- 1. scaling exponents and input checks
     for (int j = tid; j < n; j += nthr) {
-        double mjj = Mhi[j + (int64_t)j * ldm];
+        const double mjj = Mhi[j + (int64_t)j * ldm];
         if (!(mjj > 0.0) || !__builtin_isfinite(mjj)) {
             atomicMax(&sh.flag_bad, __builtin_isfinite(mjj) ? 1 : 3);
             sexp[j] = 0;
         } else {
-            sexp[j] = ilogb(__builtin_sqrt(mjj));
+            const int e = ilogb(__builtin_sqrt(mjj));
+            sexp[j] = e;
+            atomicMax(&sh.emax, e);
         }
     }
     for (int q = tid; q < n * n; q += nthr) {
-        int i = q % n, j = q / n;
-        double v = Mhi[i + (int64_t)j * ldm];
+        const double v = Mhi[(q % n) + (int64_t)(q / n) * ldm];
         if (!__builtin_isfinite(v)) atomicMax(&sh.flag_bad, 3);
     }
     __syncthreads();
@@ -84,90 +143,102 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
         return;
     }
 
-    // ---- 2. H = D~^-1 M D~^-1 (exact), packed upper, dd in LDS; Cholesky
-    dd_t *H = reinterpret_cast<dd_t *>(lds);
-    for (int q = tid; q < npk; q += nthr) {
-        // decode packed q -> (i, j), i <= j
-        int j = (int)((__builtin_sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-        while (j * (j + 1) / 2 > q) --j;
-        while ((j + 1) * (j + 2) / 2 <= q) ++j;
-        int i = q - j * (j + 1) / 2;
-        int sc = -(sexp[i] + sexp[j]);
-        double hi = ldexp(Mhi[i + (int64_t)j * ldm], sc);
-        double lo = DDGRAM ? ldexp(Mlo[i + (int64_t)j * ldm], sc) : 0.0;
-        H[q] = dd_t{hi, lo};
+    // ---- 2. H = D~^-1 M D~^-1 (exact) as a full n x n square in LDS; Cholesky
+    //      (only the upper triangle is read and written)
+    dd_t *Hd = reinterpret_cast<dd_t *>(lds);  // DDGRAM
+    double *Hs = lds;                            // !DDGRAM
+    for (int q = tid; q < n * n; q += nthr) {
+        const int i = q % n, j = q / n;
+        if (i > j) continue;
+        const int sc = -(sexp[i] + sexp[j]);
+        const double hi = ldexp(Mhi[i + (int64_t)j * ldm], sc);
+        if (DDGRAM) {
+            Hd[q] = dd_t{hi, ldexp(Mlo[i + (int64_t)j * ldm], sc)};
+        } else {
+            Hs[q] = hi;
+        }
     }
     __syncthreads();
 
+    const int tx = tid & 31, ty = tid >> 5, nty = nthr >> 5;
     for (int k = 0; k < n; ++k) {
-        dd_t hkk = H[packed_idx(k, k)];
+        const dd_t hkk = DDGRAM ? Hd[k + k * n] : dd_t{Hs[k + k * n], 0.0};
         if (!(hkk.hi > 0.0)) {  // uniform across the workgroup
             if (tid == 0) *info = 1;
             return;
         }
-        dd_t rkk = DDGRAM ? dd_sqrt(hkk) : dd_t{__builtin_sqrt(hkk.hi), 0.0};
-        dd_t inv = DDGRAM ? dd_div(dd_t{1.0, 0.0}, rkk) : dd_t{1.0 / rkk.hi, 0.0};
-        __syncthreads();  // everyone has read H(k,k)
-        for (int j = k + 1 + tid; j < n; j += nthr) {
-            int q = packed_idx(k, j);
-            H[q] = DDGRAM ? dd_mul(H[q], inv) : dd_t{H[q].hi / rkk.hi, 0.0};
+        if (DDGRAM) {
+            // 1/sqrt(h) in dd: the FP64 estimate y refined once in dd,
+            // y + y (1 - h y^2) / 2; then sqrt(h) = h / sqrt(h)
+            const double y = rsq_nr(hkk.hi);
+            const dd_t hy2 = dd_mul_d(dd_mul_d(hkk, y), y);
+            const dd_t inv = dd_add(dd_t{y, 0.0}, dd_mul_d(dd_sub(dd_t{1.0, 0.0}, hy2), 0.5 * y));
+            const dd_t rkk = dd_mul(hkk, inv);
+            for (int j = k + 1 + tid; j < n; j += nthr) {
+                const dd_t v = dd_mul(Hd[k + j * n], inv);
+                Hd[k + j * n] = v;
+                rowk[j] = v;
+            }
+            if (tid == 0) Hd[k + k * n] = rkk;
+        } else {
+            const double rkk = __builtin_sqrt(hkk.hi);
+            for (int j = k + 1 + tid; j < n; j += nthr) {
+                const double v = Hs[k + j * n] / rkk;
+                Hs[k + j * n] = v;
+                rowk[j] = dd_t{v, 0.0};
+            }
+            if (tid == 0) Hs[k + k * n] = rkk;
         }
-        if (tid == 0) H[packed_idx(k, k)] = rkk;
         __syncthreads();
-        // trailing update of the (n-k-1) x (n-k-1) upper triangle
-        const int L = n - k - 1;
-        const int cnt = L * (L + 1) / 2;
-        for (int f = tid; f < cnt; f += nthr) {
-            int jj = (int)((__builtin_sqrt(8.0 * f + 1.0) - 1.0) * 0.5);
-            while (jj * (jj + 1) / 2 > f) --jj;
-            while ((jj + 1) * (jj + 2) / 2 <= f) ++jj;
-            int ii = f - jj * (jj + 1) / 2;
-            int i = k + 1 + ii, j = k + 1 + jj;
-            dd_t rki = H[packed_idx(k, i)], rkj = H[packed_idx(k, j)];
-            int q = packed_idx(i, j);
-            if (DDGRAM) {
-                H[q] = dd_sub(H[q], dd_mul(rki, rkj));
-            } else {
-                H[q].hi = __builtin_fma(-rki.hi, rkj.hi, H[q].hi);
+        // trailing update of the upper triangle: H(i, j) -= R(k, i) R(k, j), k < i <= j
+        for (int j = k + 1 + ty; j < n; j += nty) {
+            const dd_t rkj = rowk[j];
+            for (int i = k + 1 + tx; i <= j; i += 32) {
+                const dd_t rki = rowk[i];
+                if (DDGRAM) {
+                    Hd[i + j * n] = dd_sub_fast(Hd[i + j * n], dd_mul(rki, rkj));
+                } else {
+                    Hs[i + j * n] = __builtin_fma(-rki.hi, rkj.hi, Hs[i + j * n]);
+                }
             }
         }
         __syncthreads();
     }
 
-    // ---- 3. R = working(R_H) D~ as an n x n column-major TS matrix Y in LDS,
-    //      V = I next to it.  The packed dd triangle overlaps both, so every
+    // ---- 3. R = working(R_H) D~ 2^-emax as an n x n column-major TS matrix Y in
+    //      LDS, V = I next to it.  The Cholesky square overlaps both, so every
     //      lane first lifts its share of R into registers.
-    //      (eig_threads keeps ceil(npk / nthr) <= EIG_MAXREG for every n <= GSVD_KMAX_N)
-    double rv[EIG_MAXREG];
+    const int emax = sh.emax;
+    double rv[MAXREG];
 #pragma unroll
-    for (int c = 0; c < EIG_MAXREG; ++c) {
+    for (int c = 0; c < MAXREG; ++c) {
         const int q = tid + c * nthr;
         rv[c] = 0.0;
-        if (q < npk) {
-            int j = (int)((__builtin_sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-            while (j * (j + 1) / 2 > q) --j;
-            while ((j + 1) * (j + 2) / 2 <= q) ++j;
-            const double r = (double)(TW)H[q].hi;  // round to the working precision
-            rv[c] = ldexp(r, sexp[j]);
+        if (q < n * n) {
+            const int i = q % n, j = q / n;
+            if (i <= j) {
+                const double h = DDGRAM ? Hd[q].hi : Hs[q];
+                rv[c] = ldexp((double)(TW)h, sexp[j] - emax);  // round to working, rescale
+            }
         }
     }
     __syncthreads();
+    // column stride: a multiple of 256 bytes, so a column's bank offset depends
+    // only on the row (see the row-block rotation in the Jacobi loop)
+    const int ld = jac_ld<TS>(n);
     TS *Y = reinterpret_cast<TS *>(lds);
-    TS *Vs = Y + n * n;
-    for (int q = tid; q < n * n; q += nthr) {
-        Y[q] = (TS)0;
-        Vs[q] = (q % n == q / n) ? (TS)1 : (TS)0;
-    }
+    TS *Vs = Y + n * ld;
+    // zero everything first: rows n .. ld-1 are padding that the Jacobi loop
+    // reads and rotates without bounds checks (zeros stay zeros)
+    for (int q = tid; q < 2 * n * ld; q += nthr) Y[q] = (TS)0;
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < EIG_MAXREG; ++c) {
+    for (int c = 0; c < MAXREG; ++c) {
         const int q = tid + c * nthr;
-        if (q < npk) {
-            int j = (int)((__builtin_sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-            while (j * (j + 1) / 2 > q) --j;
-            while ((j + 1) * (j + 2) / 2 <= q) ++j;
-            const int i = q - j * (j + 1) / 2;
-            Y[i + j * n] = (TS)rv[c];  // R(i, j), exact in TS (already rounded to TW)
+        if (q < n * n) {
+            const int r = q % n, col = q / n;
+            Y[r + col * ld] = (TS)rv[c];
+            if (r == col) Vs[r + col * ld] = (TS)1;
         }
     }
     __syncthreads();
@@ -181,46 +252,75 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
     for (int sw = 0; sw < max_sweeps && !converged; ++sw) {
         for (int step = 0; step < N - 1; ++step) {
             for (int pr = grp; pr < npair; pr += ngrp) {
-                // round-robin: position 0 holds player 0, position t >= 1 holds
+                // round robin: position 0 holds player 0, position t >= 1 holds
                 // player 1 + (t - 1 + step) mod (N - 1); pair pr = positions pr, N-1-pr
-                int a = (pr == 0) ? 0 : 1 + (pr - 1 + step) % (N - 1);
-                int t2 = N - 1 - pr;
-                int b = 1 + (t2 - 1 + step) % (N - 1);
-                int p = a < b ? a : b, q = a < b ? b : a;
+                int a = 0;
+                if (pr != 0) {
+                    a = pr - 1 + step;
+                    if (a >= N - 1) a -= N - 1;
+                    a += 1;
+                }
+                int b = N - 2 - pr + step;
+                if (b >= N - 1) b -= N - 1;
+                b += 1;
+                const int p = a < b ? a : b, q = a < b ? b : a;
                 if (q >= n) continue;  // dummy player (uniform within the group)
-                TS *yp = Y + p * n, *yq = Y + q * n;
-                double al = 0, be = 0, ga = 0;
-                for (int r = gl; r < n; r += GRP) {
-                    double x = (double)yp[r], y = (double)yq[r];
-                    al = __builtin_fma(x, x, al);
-                    be = __builtin_fma(y, y, be);
-                    ga = __builtin_fma(x, y, ga);
-                }
+                TS *yp = Y + p * ld, *yq = Y + q * ld;
+                TS *vp = Vs + p * ld, *vq = Vs + q * ld;
+                // register i holds row block (i + rot) mod RPL: the four groups that
+                // share an LDS cycle read different 64-byte blocks, so different banks.
+                // Rows up to GRP * RPL <= ld exist (zero padding), so no bounds checks;
+                // all four columns are fetched before any use.
+                const int rot = grp & 3;
+                TS x0[RPL], x1[RPL], w0[RPL], w1[RPL];
 #pragma unroll
-                for (int off = GRP / 2; off >= 1; off >>= 1) {
-                    al += __shfl_xor(al, off, GRP);
-                    be += __shfl_xor(be, off, GRP);
-                    ga += __shfl_xor(ga, off, GRP);
+                for (int i = 0; i < RPL; ++i) {
+                    int blk = i + rot;
+                    if (blk >= RPL) blk -= RPL;
+                    if (blk >= RPL) blk -= RPL;
+                    if (blk >= RPL) blk -= RPL;
+                    const int r = gl + GRP * blk;
+                    x0[i] = yp[r];
+                    x1[i] = yq[r];
+                    w0[i] = vp[r];
+                    w1[i] = vq[r];
                 }
-                // the xor butterfly leaves bitwise identical sums in all 16 lanes
-                if (__builtin_fabs(ga) > tol * __builtin_sqrt(al) * __builtin_sqrt(be)) {
-                    double zeta = (be - al) / (2.0 * ga);
+                double al = 0, be = 0, ga = 0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const double a0 = (double)x0[i], a1 = (double)x1[i];
+                    al = __builtin_fma(a0, a0, al);
+                    be = __builtin_fma(a1, a1, be);
+                    ga = __builtin_fma(a0, a1, ga);
+                }
+                al = group_sum(al);
+                be = group_sum(be);
+                ga = group_sum(ga);
+                if (ga * ga > tol2 * (al * be)) {
+                    const double zeta = (be - al) * rcp_nr(2.0 * ga);
+                    const double az = __builtin_fabs(zeta);
                     double t;
-                    double az = __builtin_fabs(zeta);
                     if (az > 1e150) {
-                        t = 0.5 / zeta;
+                        t = 0.5 * rcp_nr(zeta);
                     } else {
-                        t = 1.0 / (az + __builtin_sqrt(1.0 + zeta * zeta));
+                        const double x = __builtin_fma(zeta, zeta, 1.0);
+                        const double root = x * rsq_nr(x);
+                        t = rcp_nr(az + root);
                         if (zeta < 0) t = -t;
                     }
-                    double c = 1.0 / __builtin_sqrt(1.0 + t * t);
-                    double s = c * t;
-                    TS *vp = Vs + p * n, *vq = Vs + q * n;
-                    for (int r = gl; r < n; r += GRP) {
-                        double x = (double)yp[r], y = (double)yq[r];
-                        yp[r] = (TS)(c * x - s * y);
-                        yq[r] = (TS)(s * x + c * y);
-                        double u = (double)vp[r], w = (double)vq[r];
+                    const double c = rsq_nr(__builtin_fma(t, t, 1.0));
+                    const double s = c * t;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) {
+                        int blk = i + rot;
+                        if (blk >= RPL) blk -= RPL;
+                        if (blk >= RPL) blk -= RPL;
+                        if (blk >= RPL) blk -= RPL;
+                        const int r = gl + GRP * blk;
+                        const double a0 = (double)x0[i], a1 = (double)x1[i];
+                        const double u = (double)w0[i], w = (double)w1[i];
+                        yp[r] = (TS)(c * a0 - s * a1);
+                        yq[r] = (TS)(s * a0 + c * a1);
                         vp[r] = (TS)(c * u - s * w);
                         vq[r] = (TS)(s * u + c * w);
                     }
@@ -240,37 +340,37 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
         return;
     }
 
-    // ---- 5. sigma_p = ||y_p||, ordering, sign of V columns, cast, W
+    // ---- 5. sigma_p = ||y_p|| 2^emax, ordering, sign of V columns, cast, W
     for (int p = grp; p < n; p += ngrp) {
-        const TS *yp = Y + p * n;
-        const TS *vp = Vs + p * n;
+        const TS *yp = Y + p * ld;
+        const TS *vp = Vs + p * ld;
         double ss = 0;
         double best = -1.0;
         int barg = 0;
         for (int r = gl; r < n; r += GRP) {
-            double x = (double)yp[r];
+            const double x = (double)yp[r];
             ss = __builtin_fma(x, x, ss);
-            double av = __builtin_fabs((double)vp[r]);
+            const double av = __builtin_fabs((double)vp[r]);
             if (av > best) { best = av; barg = r; }
         }
+        ss = group_sum(ss);
 #pragma unroll
         for (int off = GRP / 2; off >= 1; off >>= 1) {
-            ss += __shfl_xor(ss, off, GRP);
-            double ob = __shfl_xor(best, off, GRP);
-            int oa = __shfl_xor(barg, off, GRP);
+            const double ob = __shfl_xor(best, off, GRP);
+            const int oa = __shfl_xor(barg, off, GRP);
             if (ob > best || (ob == best && oa < barg)) { best = ob; barg = oa; }
         }
         if (gl == 0) {
-            ssig[p] = __builtin_sqrt(ss);
+            ssig[p] = ldexp(__builtin_sqrt(ss), emax);
             ssign[p] = vp[barg] < 0 ? -1.0 : 1.0;
         }
     }
     __syncthreads();
     for (int p = tid; p < n; p += nthr) {
-        double sp = ssig[p];
+        const double sp = ssig[p];
         int rk = 0;
         for (int q = 0; q < n; ++q) {
-            double sq = ssig[q];
+            const double sq = ssig[q];
             rk += (sq > sp) || (sq == sp && q < p);
         }
         srank[p] = rk;
@@ -282,10 +382,10 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
         return;
     }
     for (int q = tid; q < n * n; q += nthr) {
-        int r = q % n, p = q / n;
-        int pos = srank[p];
-        TW sw = (TW)ssig[p];
-        TW vw = (TW)(ssign[p] * (double)Vs[r + p * n]);
+        const int r = q % n, p = q / n;
+        const int pos = srank[p];
+        const TW sw = (TW)ssig[p];
+        const TW vw = (TW)(ssign[p] * (double)Vs[r + p * ld]);
         V[r + (int64_t)pos * ldv] = vw;
         W[r + (int64_t)pos * ldw] = vw / sw;
         if (r == 0) S[pos] = sw;
@@ -294,23 +394,66 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
 }
 
 size_t eig_lds_bytes(int working, int64_t n) {
-    size_t packed = (size_t)(n * (n + 1) / 2) * sizeof(dd_t);
-    size_t full = 2 * (size_t)(n * n) * (working == 1 ? sizeof(double) : sizeof(float));
-    return packed > full ? packed : full;
+    const size_t chol = (size_t)(n * n) * (working == 1 ? sizeof(dd_t) : sizeof(double));
+    const size_t jac = working == 1 ? 2 * (size_t)(n * jac_ld<double>((int)n)) * sizeof(double)
+                                    : 2 * (size_t)(n * jac_ld<float>((int)n)) * sizeof(float);
+    return chol > jac ? chol : jac;
 }
 
 int eig_max_n(int working) { return working == 1 ? GSVD_KMAX_N_F64 : GSVD_KMAX_N; }
 
 int eig_threads(int64_t n) {
-    int N = (int)(n + (n & 1));
+    // the Jacobi uses GRP (n+1)/2 lanes; the Cholesky and the repacking use all
+    // of them, so small problems get a small workgroup and larger ones 1024 lanes
+    const int N = (int)(n + (n & 1));
     int t = GRP * (N / 2);
+    if (n >= 32) t = 1024;
     if (t < 64) t = 64;
     if (t > 1024) t = 1024;
-    t = ((t + 63) / 64) * 64;
-    // every lane holds at most EIG_MAXREG packed entries while R is repacked
-    const int npk = (int)(n * (n + 1) / 2);
-    while ((npk + t - 1) / t > EIG_MAXREG && t < 1024) t += 64;
-    return t;
+    return ((t + 63) / 64) * 64;
+}
+
+template <typename TW, typename TS, bool DD, int RPL>
+static hipError_t launch_rpl(int64_t n, const double *Mhi, const double *Mlo, int64_t ldm, void *S,
+                             void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol2,
+                             int max_sweeps, size_t lds, int thr, hipStream_t st) {
+    auto k = eig_chol_jacobi1_kernel<TW, TS, DD, RPL>;
+    hipError_t err = hipFuncSetAttribute((const void *)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k, dim3(1), dim3(thr), lds, st, (int)n, Mhi, Mlo, ldm, (TW *)S, (TW *)V,
+                       ldv, (TW *)W, ldw, info, tol2, max_sweeps);
+    return hipGetLastError();
+}
+
+template <typename TW, typename TS, bool DD>
+static hipError_t launch_t(int64_t n, const double *Mhi, const double *Mlo, int64_t ldm, void *S,
+                           void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol2,
+                           int max_sweeps, size_t lds, int thr, hipStream_t st) {
+#define GSVD_EIG_CASE(R)                                                                       \
+    case R:                                                                                    \
+        return launch_rpl<TW, TS, DD, R>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2,     \
+                                         max_sweeps, lds, thr, st);
+    switch ((int)((n + GRP - 1) / GRP)) {
+        GSVD_EIG_CASE(1)
+        GSVD_EIG_CASE(2)
+        GSVD_EIG_CASE(3)
+        GSVD_EIG_CASE(4)
+        GSVD_EIG_CASE(5)
+        GSVD_EIG_CASE(6)
+        GSVD_EIG_CASE(7)
+        GSVD_EIG_CASE(8)
+        GSVD_EIG_CASE(9)
+        GSVD_EIG_CASE(10)
+        GSVD_EIG_CASE(11)
+        GSVD_EIG_CASE(12)
+        GSVD_EIG_CASE(13)
+        GSVD_EIG_CASE(14)
+        GSVD_EIG_CASE(15)
+        GSVD_EIG_CASE(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef GSVD_EIG_CASE
 }
 
 hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *Mlo, int64_t ldm,
@@ -318,26 +461,16 @@ hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *M
                       int max_sweeps, hipStream_t st) {
     const size_t lds = eig_lds_bytes(working, n);
     const int thr = eig_threads(n);
-    if (n < 1 || n > eig_max_n(working) || (n * (n + 1) / 2 + thr - 1) / thr > EIG_MAXREG)
-        return hipErrorInvalidValue;
-    hipError_t err;
+    if (n < 1 || n > eig_max_n(working)) return hipErrorInvalidValue;
+    if ((n * n + thr - 1) / thr > MAXREG) return hipErrorInvalidValue;
+    const double tol2 = tol * tol;
     if (working == 1) {
-        auto k = eig_chol_jacobi1_kernel<double, double, true>;
         if (Mlo == nullptr) return hipErrorInvalidValue;
-        err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-        if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k, dim3(1), dim3(thr), lds, st, (int)n, Mhi, Mlo, ldm, (double *)S,
-                           (double *)V, ldv, (double *)W, ldw, info, tol, max_sweeps);
-    } else {
-        auto k = eig_chol_jacobi1_kernel<float, float, false>;
-        err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-        if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k, dim3(1), dim3(thr), lds, st, (int)n, Mhi, Mlo, ldm, (float *)S,
-                           (float *)V, ldv, (float *)W, ldw, info, tol, max_sweeps);
+        return launch_t<double, double, true>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2,
+                                              max_sweeps, lds, thr, st);
     }
-    return hipGetLastError();
+    return launch_t<float, float, false>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2,
+                                         max_sweeps, lds, thr, st);
 }
 
 }  // namespace gsvd

@@ -1,21 +1,25 @@
 // Higher-precision Gram M_h = A^T A (Alg. 1 steps 1-2, eq. (ATA)).
 //
-// Split-m tiled SYRK.  The upper triangle of M is covered by 2x2 register
-// blocks (bi, bj), bi <= bj, enumerated row by row; every lane of a workgroup
-// owns one block.  blockIdx.y selects a slab of rows ("split"); the slab is
-// streamed through LDS in chunks of KC rows, each chunk staged as a row-major
-// KC x NC tile so a lane reads its two A(k, i) values and its two A(k, j)
-// values with one 16-byte LDS read each.  Global loads walk down the columns
-// (A is column-major), so they are coalesced.  The chunk after the current one
-// is fetched into registers while the current one is consumed.
+// Split-m tiled SYRK.  The upper triangle of M is covered by 4x4 register
+// blocks (bi, bj), bi <= bj, enumerated row by row.  A workgroup holds
+// nblk x ks lanes: lane t owns block t % nblk for the k-group t / nblk, and
+// the ks k-groups take interleaved rows of each LDS chunk, so every lane keeps
+// 16 independent accumulators (enough independent work to hide FP64 latency)
+// and a 64-column problem fills 680 of 704 lanes.  blockIdx.y selects a slab
+// of rows ("split").  The slab is streamed through LDS in chunks of kc rows
+// staged row-major (a lane reads its four A(k, i) and four A(k, j) with four
+// 16-byte LDS reads per 16 multiply-adds); global loads walk down the columns
+// of the column-major A, so they are coalesced, and the next chunk is fetched
+// into registers while the current one is consumed.
 //
 // FP64 A: every product is formed exactly (TwoProduct) and summed in
 // double-double (TwoSum), i.e. the Gram is carried at u_h ~ 2^-104.
 // FP32 A: the FP64 product of two FP32 numbers is exact; the sums are FP64.
 //
-// Each (split, block) writes its four dd partial sums to its own slot of the
-// workspace; gram_reduce_kernel then adds the splits with a fixed-shape tree,
-// so the result does not depend on scheduling.
+// At the end of the slab the k-groups are added into k-group 0 in a fixed
+// order through LDS, and each (split, block) writes its 16 dd partial sums to
+// its own slot of the workspace; gram_reduce_kernel then adds the splits with
+// a fixed-shape tree.  The result does not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include "dd_device.hpp"
@@ -23,73 +27,74 @@
 
 namespace gsvd {
 
-constexpr int KC = 32;  // rows per LDS chunk
+constexpr int BS = 4;       // register block edge
+constexpr int MAXPER = 4;   // staged chunk elements per lane
 
-__device__ __forceinline__ void decode_block(int b, int nbh, int &bi, int &bj) {
+__device__ __forceinline__ void decode_block(int b, int nb, int &bi, int &bj) {
     int i = 0, rem = b;
-    while (rem >= nbh - i) {
-        rem -= nbh - i;
+    while (rem >= nb - i) {
+        rem -= nb - i;
         ++i;
     }
     bi = i;
     bj = i + rem;
 }
 
+constexpr int GRAM_MAX_THREADS = 768;  // three waves per SIMD: up to 168 VGPRs per lane
+
 template <typename T, bool DD>
-__global__ void __launch_bounds__(1024)
-gram_partial_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int nbh, int nblk,
-                    int64_t rows_per_split, double *__restrict__ part) {
+__global__ void __launch_bounds__(GRAM_MAX_THREADS)
+gram_partial_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int nb, int nblk,
+                    int ks, int kc, int64_t rows_per_split, double *__restrict__ part) {
     extern __shared__ double lds[];
-    const int NC = 2 * nbh;       // staged columns (n rounded up to even)
-    const int LDL = NC + 2;       // row stride in LDS (keeps 16-byte alignment)
+    const int NC = BS * nb;     // staged columns (n rounded up to a multiple of 4)
+    const int LDL = NC + 2;     // row stride in LDS (16-byte aligned rows)
     double *buf0 = lds;
-    double *buf1 = lds + KC * LDL;
+    double *buf1 = lds + kc * LDL;
 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    const int b = blockIdx.x * nthr + tid;
-    const bool active = b < nblk;
+    const int g = tid / nblk;          // k-group
+    const int b = tid - g * nblk;      // block
+    const bool active = g < ks;
     int bi = 0, bj = 0;
-    if (active) decode_block(b, nbh, bi, bj);
+    if (active) decode_block(b, nb, bi, bj);
 
     const int64_t split = blockIdx.y;
     const int64_t r0 = split * rows_per_split;
     const int64_t r1 = (r0 + rows_per_split < m) ? r0 + rows_per_split : m;
-    const int nchunk = (int)((r1 - r0 + KC - 1) / KC);
+    const int nchunk = (int)((r1 - r0 + kc - 1) / kc);
 
-    // staging: element e of a chunk is (k = e % KC, c = e / KC)
-    const int nelem = KC * NC;
-    constexpr int MAXPER = 8;  // KC * 128 / 576 rounded up; checked on the host
-    const int per = (nelem + nthr - 1) / nthr;
-
+    // staging: element e of a chunk is (k = e % kc, c = e / kc)
+    const int nelem = kc * NC;
     double stage[MAXPER];
     auto fetch = [&](int chunk) {
-        const int64_t base = r0 + (int64_t)chunk * KC;
+        const int64_t base = r0 + (int64_t)chunk * kc;
 #pragma unroll
         for (int q = 0; q < MAXPER; ++q) {
             stage[q] = 0.0;
-            if (q < per) {
-                int e = tid + q * nthr;
-                if (e < nelem) {
-                    int k = e % KC, c = e / KC;
-                    int64_t r = base + k;
-                    if (r < r1 && c < n) stage[q] = (double)A[r + (int64_t)c * lda];
-                }
+            const int e = tid + q * nthr;
+            if (e < nelem) {
+                const int k = e % kc, c = e / kc;
+                const int64_t r = base + k;
+                if (r < r1 && c < n) stage[q] = (double)A[r + (int64_t)c * lda];
             }
         }
     };
     auto commit = [&](double *dst) {
 #pragma unroll
         for (int q = 0; q < MAXPER; ++q) {
-            if (q < per) {
-                int e = tid + q * nthr;
-                if (e < nelem) dst[(e % KC) * LDL + e / KC] = stage[q];
-            }
+            const int e = tid + q * nthr;
+            if (e < nelem) dst[(e % kc) * LDL + e / kc] = stage[q];
         }
     };
 
-    double h00 = 0, h01 = 0, h10 = 0, h11 = 0;
-    double l00 = 0, l01 = 0, l10 = 0, l11 = 0;
+    double hi[BS * BS], lo[BS * BS];
+#pragma unroll
+    for (int q = 0; q < BS * BS; ++q) {
+        hi[q] = 0.0;
+        lo[q] = 0.0;
+    }
 
     if (nchunk > 0) {
         fetch(0);
@@ -102,54 +107,97 @@ gram_partial_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int 
         const bool more = ch + 1 < nchunk;
         if (more) fetch(ch + 1);
         if (active) {
-            const double *pi = cur + 2 * bi;
-            const double *pj = cur + 2 * bj;
-#pragma unroll 8
-            for (int k = 0; k < KC; ++k) {
-                const double2 ai = *reinterpret_cast<const double2 *>(pi + k * LDL);
-                const double2 aj = *reinterpret_cast<const double2 *>(pj + k * LDL);
+            const double *pi = cur + BS * bi;
+            const double *pj = cur + BS * bj;
+            for (int k = g; k < kc; k += ks) {
+                const double2 a01 = *reinterpret_cast<const double2 *>(pi + k * LDL);
+                const double2 a23 = *reinterpret_cast<const double2 *>(pi + k * LDL + 2);
+                const double2 b01 = *reinterpret_cast<const double2 *>(pj + k * LDL);
+                const double2 b23 = *reinterpret_cast<const double2 *>(pj + k * LDL + 2);
+                const double av[BS] = {a01.x, a01.y, a23.x, a23.y};
+                const double bv[BS] = {b01.x, b01.y, b23.x, b23.y};
                 if (DD) {
-                    dd_mac(h00, l00, ai.x, aj.x);
-                    dd_mac(h01, l01, ai.x, aj.y);
-                    dd_mac(h10, l10, ai.y, aj.x);
-                    dd_mac(h11, l11, ai.y, aj.y);
+                    // four rows of four independent dd multiply-adds, each row written
+                    // stage by stage so the dependent operations are four apart
+#pragma unroll
+                    for (int r = 0; r < BS; ++r) {
+                        double p[BS], e[BS], s[BS], v[BS];
+#pragma unroll
+                        for (int c = 0; c < BS; ++c) p[c] = av[r] * bv[c];
+#pragma unroll
+                        for (int c = 0; c < BS; ++c) e[c] = __builtin_fma(av[r], bv[c], -p[c]);
+#pragma unroll
+                        for (int c = 0; c < BS; ++c) s[c] = hi[BS * r + c] + p[c];
+#pragma unroll
+                        for (int c = 0; c < BS; ++c) v[c] = s[c] - hi[BS * r + c];
+#pragma unroll
+                        for (int c = 0; c < BS; ++c) {
+                            const int q = BS * r + c;
+                            const double err = (hi[q] - (s[c] - v[c])) + (p[c] - v[c]);
+                            hi[q] = s[c];
+                            lo[q] += e[c] + err;
+                        }
+                    }
                 } else {
-                    h00 = __builtin_fma(ai.x, aj.x, h00);
-                    h01 = __builtin_fma(ai.x, aj.y, h01);
-                    h10 = __builtin_fma(ai.y, aj.x, h10);
-                    h11 = __builtin_fma(ai.y, aj.y, h11);
+#pragma unroll
+                    for (int q = 0; q < BS * BS; ++q)
+                        hi[q] = __builtin_fma(av[q / BS], bv[q % BS], hi[q]);
                 }
             }
         }
         if (more) commit(nxt);
         __syncthreads();
     }
-    if (active) {
-        if (DD) {
-            dd_t s;
-            s = quick_two_sum(h00, l00); h00 = s.hi; l00 = s.lo;
-            s = quick_two_sum(h01, l01); h01 = s.hi; l01 = s.lo;
-            s = quick_two_sum(h10, l10); h10 = s.hi; l10 = s.lo;
-            s = quick_two_sum(h11, l11); h11 = s.hi; l11 = s.lo;
+
+    // add the k-groups into k-group 0, one group at a time (fixed order)
+    double *red = lds;  // nblk x 16 dd, reuses the chunk buffers
+    for (int r = 1; r < ks; ++r) {
+        if (active && g == r) {
+            double4 *dst = reinterpret_cast<double4 *>(red + (size_t)b * 32);
+#pragma unroll
+            for (int q = 0; q < BS * BS; q += 2) dst[q / 2] = make_double4(hi[q], lo[q], hi[q + 1], lo[q + 1]);
         }
-        double4 *dst = reinterpret_cast<double4 *>(part + ((size_t)split * nblk + b) * 8);
-        dst[0] = make_double4(h00, l00, h01, l01);
-        dst[1] = make_double4(h10, l10, h11, l11);
+        __syncthreads();
+        if (active && g == 0) {
+            const double4 *src = reinterpret_cast<const double4 *>(red + (size_t)b * 32);
+#pragma unroll
+            for (int q = 0; q < BS * BS; q += 2) {
+                const double4 o = src[q / 2];
+                if (DD) {
+                    dd_t x = dd_add(dd_t{hi[q], lo[q]}, dd_t{o.x, o.y});
+                    dd_t y = dd_add(dd_t{hi[q + 1], lo[q + 1]}, dd_t{o.z, o.w});
+                    hi[q] = x.hi; lo[q] = x.lo; hi[q + 1] = y.hi; lo[q + 1] = y.lo;
+                } else {
+                    hi[q] += o.x;
+                    hi[q + 1] += o.z;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (active && g == 0) {
+        double4 *dst = reinterpret_cast<double4 *>(part + ((size_t)split * nblk + b) * 32);
+#pragma unroll
+        for (int q = 0; q < BS * BS; q += 2) {
+            dd_t x = quick_two_sum(hi[q], lo[q]);
+            dd_t y = quick_two_sum(hi[q + 1], lo[q + 1]);
+            dst[q / 2] = make_double4(x.hi, x.lo, y.hi, y.lo);
+        }
     }
 }
 
 // One wavefront per M entry: lane l adds splits l, l + 64, ... in order, then a
 // fixed xor-butterfly over the 64 lanes; lane 0 writes M(i, j) and M(j, i).
 __global__ void __launch_bounds__(256)
-gram_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nbh, int nblk, int n,
+gram_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nb, int nblk, int n,
                    double *__restrict__ Mhi, double *__restrict__ Mlo, int64_t ldm) {
     const int lane = threadIdx.x & 63;
     const int64_t entry = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (entry >= (int64_t)nblk * 4) return;
-    const int b = (int)(entry >> 2), e = (int)(entry & 3);
+    if (entry >= (int64_t)nblk * BS * BS) return;
+    const int b = (int)(entry / (BS * BS)), e = (int)(entry % (BS * BS));
     dd_t acc{0.0, 0.0};
     for (int64_t s = lane; s < nsplit; s += 64) {
-        const double *p = part + ((size_t)s * nblk + b) * 8 + 2 * e;
+        const double *p = part + ((size_t)s * nblk + b) * 32 + 2 * e;
         acc = dd_add(acc, dd_t{p[0], p[1]});
     }
 #pragma unroll
@@ -159,8 +207,8 @@ gram_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nbh, int
     }
     if (lane == 0) {
         int bi, bj;
-        decode_block(b, nbh, bi, bj);
-        const int i = 2 * bi + (e >> 1), j = 2 * bj + (e & 1);
+        decode_block(b, nb, bi, bj);
+        const int i = BS * bi + e / BS, j = BS * bj + e % BS;
         if (i < n && j < n && i <= j) {
             Mhi[i + (int64_t)j * ldm] = acc.hi;
             Mhi[j + (int64_t)i * ldm] = acc.hi;
@@ -174,36 +222,48 @@ gram_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nbh, int
 
 GramPlan gram_plan(int64_t m, int64_t n) {
     GramPlan p{};
-    p.nbh = (int)((n + 1) / 2);
-    p.nblk = p.nbh * (p.nbh + 1) / 2;
-    const int wgs_x = (p.nblk + 1023) / 1024;
-    const int per_wg = (p.nblk + wgs_x - 1) / wgs_x;
-    // enough lanes for the blocks, and for staging a chunk with <= 8 values per lane
-    int need = per_wg;
-    const int stage_need = (KC * 2 * p.nbh + 7) / 8;
-    if (stage_need > need) need = stage_need;
-    p.threads = ((need + 63) / 64) * 64;
-    p.grid_x = wgs_x;
-    // about 2048 workgroups in flight, every slab a multiple of KC rows
-    int64_t target = 2048 / wgs_x;
-    if (target < 1) target = 1;
+    p.nb = (int)((n + BS - 1) / BS);
+    p.nblk = p.nb * (p.nb + 1) / 2;
+    // k-groups: the count whose lanes fill whole wavefronts best, at most 16
+    int best_ks = 1;
+    double best_fill = 0.0;
+    for (int ks = 1; ks <= 16 && ks * p.nblk <= GRAM_MAX_THREADS; ++ks) {
+        const int lanes = ks * p.nblk;
+        const double fill = (double)lanes / (double)(((lanes + 63) / 64) * 64);
+        if (fill >= best_fill - 1e-9) {
+            best_fill = fill;
+            best_ks = ks;
+        }
+    }
+    p.ks = best_ks;
+    p.threads = ((p.ks * p.nblk + 63) / 64) * 64;
+    // rows per k-group per chunk: up to 8, as many as the lanes can stage with
+    // <= MAXPER values each (kk = 1 always fits: 4 nb <= MAXPER nb (nb + 1) / 2)
+    int kk = 8;
+    while (kk > 1 && p.ks * kk * BS * p.nb > MAXPER * p.threads) --kk;
+    p.kc = p.ks * kk;
+    // slabs: about two workgroups per compute unit, every slab a multiple of kc rows
+    int64_t target = 512;
     int64_t rps = (m + target - 1) / target;
-    rps = ((rps + KC - 1) / KC) * KC;
-    if (rps < KC) rps = KC;
+    rps = ((rps + p.kc - 1) / p.kc) * p.kc;
+    if (rps < p.kc) rps = p.kc;
     p.rows_per_split = rps;
     p.nsplit = (m + rps - 1) / rps;
     if (p.nsplit < 1) p.nsplit = 1;
-    p.lds_bytes = (size_t)2 * KC * (2 * p.nbh + 2) * sizeof(double);
-    p.part_bytes = (size_t)p.nsplit * p.nblk * 8 * sizeof(double);
+    const size_t chunk = (size_t)2 * p.kc * (BS * p.nb + 2) * sizeof(double);
+    const size_t red = (size_t)p.nblk * 32 * sizeof(double);
+    p.lds_bytes = chunk > red ? chunk : red;
+    p.part_bytes = (size_t)p.nsplit * p.nblk * 32 * sizeof(double);
     return p;
 }
 
 hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                        double *Mhi, double *Mlo, int64_t ldm, void *part, const GramPlan &p,
                        hipStream_t st) {
-    // every chunk element must fit the per-thread staging array
-    if ((KC * 2 * p.nbh + p.threads - 1) / p.threads > 8) return hipErrorInvalidValue;
-    dim3 grid(p.grid_x, (unsigned)p.nsplit);
+    if (p.threads > GRAM_MAX_THREADS || (p.kc * BS * p.nb + p.threads - 1) / p.threads > MAXPER ||
+        p.ks * p.nblk > p.threads || p.lds_bytes > 160 * 1024)
+        return hipErrorInvalidValue;
+    dim3 grid(1, (unsigned)p.nsplit);
     hipError_t err;
     if (working == 1) {
         auto k = gram_partial_kernel<double, true>;
@@ -211,21 +271,21 @@ hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t
                                   (int)p.lds_bytes);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(k, grid, dim3(p.threads), p.lds_bytes, st, (const double *)A, lda, m,
-                           (int)n, p.nbh, p.nblk, p.rows_per_split, (double *)part);
+                           (int)n, p.nb, p.nblk, p.ks, p.kc, p.rows_per_split, (double *)part);
     } else {
         auto k = gram_partial_kernel<float, false>;
         err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)p.lds_bytes);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(k, grid, dim3(p.threads), p.lds_bytes, st, (const float *)A, lda, m,
-                           (int)n, p.nbh, p.nblk, p.rows_per_split, (double *)part);
+                           (int)n, p.nb, p.nblk, p.ks, p.kc, p.rows_per_split, (double *)part);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    const int64_t entries = (int64_t)p.nblk * 4;
+    const int64_t entries = (int64_t)p.nblk * BS * BS;
     const unsigned rgrid = (unsigned)((entries + 3) / 4);
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(rgrid), dim3(256), 0, st, (const double *)part,
-                       p.nsplit, p.nbh, p.nblk, (int)n, Mhi, Mlo, ldm);
+                       p.nsplit, p.nb, p.nblk, (int)n, Mhi, Mlo, ldm);
     return hipGetLastError();
 }
 

@@ -13,10 +13,11 @@ constexpr int GSVD_KMAX_N_F64 = 96;   // FP64 working: R and V (FP64) must share
 
 // Launch geometry of the split-m Gram (gram.hip).
 struct GramPlan {
-    int nbh;                 // ceil(n / 2): 2x2 blocks per side
+    int nb;                  // ceil(n / 4): 4x4 blocks per side
     int nblk;                // blocks in the upper triangle
+    int ks;                  // k-groups per workgroup
+    int kc;                  // rows per LDS chunk (a multiple of ks)
     int threads;             // lanes per workgroup
-    int grid_x;              // workgroups across the block list
     int64_t rows_per_split;  // rows of A per slab
     int64_t nsplit;          // slabs
     size_t lds_bytes;        // dynamic LDS per workgroup
