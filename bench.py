@@ -96,48 +96,10 @@ def main():
     log(f"generated A {m}x{n} fp64 in {time.time() - t0:.1f}s")
     dA = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev).t()
     lda = m
-
-    w = gs.GSVD_F64
-    o = gs.opts(w, gs.GSVD_GRAM_PLAIN, gs.GSVD_EIG_CHOL_JACOBI1)
     import ctypes
-    ob = ctypes.byref(o)
-    S = torch.empty(n, dtype=torch.float64, device=dev)
-    V = gs.colmajor_empty(n, n, torch.float64, dev)
-    U = gs.colmajor_empty(m, n, torch.float64, dev)
-    info = torch.zeros(1, dtype=torch.int32, device=dev)
-    work = gs.workspace(gs.gsvd_thin_workspace_size(m, n, ob), dev)
+
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(int(stream.cuda_stream))
-
-    def step():
-        rc = gs.gsvd_thin(m, n, dA.data_ptr(), lda, S.data_ptr(), V.data_ptr(), n, U.data_ptr(), m,
-                          work.data_ptr(), work.numel(), info.data_ptr(), ob, sp)
-        if rc != 0:
-            raise RuntimeError(f"gsvd_thin: {rc} {gs.gsvd_status_string(rc)}")
-
-    # phase entry points: the same kernels with the same launch shapes as inside gsvd_thin
-    Mhi = gs.colmajor_empty(n, n, torch.float64, dev)
-    Mlo = gs.colmajor_empty(n, n, torch.float64, dev)
-    Wm = gs.colmajor_empty(n, n, torch.float64, dev)
-    gwork = gs.workspace(gs.gsvd_gram_workspace_size(m, n, ob), dev)
-    S2 = torch.empty_like(S)
-    V2 = torch.empty_like(V)
-    info2 = torch.zeros_like(info)
-    U2 = torch.empty_like(U)
-
-    def ph_gram():
-        rc = gs.gsvd_gram(m, n, dA.data_ptr(), lda, Mhi.data_ptr(), Mlo.data_ptr(), n,
-                          gwork.data_ptr(), gwork.numel(), ob, sp)
-        assert rc == 0, rc
-
-    def ph_eig():
-        rc = gs.gsvd_eig(n, Mhi.data_ptr(), Mlo.data_ptr(), n, S2.data_ptr(), V2.data_ptr(), n,
-                         Wm.data_ptr(), n, info2.data_ptr(), None, 0, ob, sp)
-        assert rc == 0, rc
-
-    def ph_u():
-        rc = gs.gsvd_u_recover(m, n, dA.data_ptr(), lda, Wm.data_ptr(), n, U2.data_ptr(), m, ob, sp)
-        assert rc == 0, rc
 
     def timed(fn, k, w_):
         for _ in range(w_):
@@ -152,21 +114,85 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k  # ms
 
-    log("warmup + timed steps")
-    ms_step = timed(step, args.steps, args.warmup)
-    log(f"step {ms_step:.4f} ms")
-    ms_gram = timed(ph_gram, args.steps, 2)
-    ms_eig = timed(ph_eig, args.steps, 2)
-    ms_u = timed(ph_u, args.steps, 2)
-    log(f"phases: gram {ms_gram:.4f} eig {ms_eig:.4f} u {ms_u:.4f} ms")
+    def measure(gram_mode):
+        """Time gsvd_thin and its three phases (same kernels, same launch shapes)."""
+        o = gs.opts(gs.GSVD_F64, gram_mode, gs.GSVD_EIG_CHOL_JACOBI1)
+        ob = ctypes.byref(o)
+        S = torch.empty(n, dtype=torch.float64, device=dev)
+        V = gs.colmajor_empty(n, n, torch.float64, dev)
+        U = gs.colmajor_empty(m, n, torch.float64, dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        work = gs.workspace(gs.gsvd_thin_workspace_size(m, n, ob), dev)
+
+        def step():
+            rc = gs.gsvd_thin(m, n, dA.data_ptr(), lda, S.data_ptr(), V.data_ptr(), n,
+                              U.data_ptr(), m, work.data_ptr(), work.numel(), info.data_ptr(),
+                              ob, sp)
+            if rc != 0:
+                raise RuntimeError(f"gsvd_thin: {rc} {gs.gsvd_status_string(rc)}")
+
+        Mhi = gs.colmajor_empty(n, n, torch.float64, dev)
+        Mlo = gs.colmajor_empty(n, n, torch.float64, dev)
+        Wm = gs.colmajor_empty(n, n, torch.float64, dev)
+        gwork = gs.workspace(gs.gsvd_gram_workspace_size(m, n, ob), dev)
+        S2, V2, info2, U2 = torch.empty_like(S), torch.empty_like(V), torch.zeros_like(info), \
+            torch.empty_like(U)
+
+        def ph_gram():
+            assert gs.gsvd_gram(m, n, dA.data_ptr(), lda, Mhi.data_ptr(), Mlo.data_ptr(), n,
+                                gwork.data_ptr(), gwork.numel(), ob, sp) == 0
+
+        def ph_eig():
+            assert gs.gsvd_eig(n, Mhi.data_ptr(), Mlo.data_ptr(), n, S2.data_ptr(), V2.data_ptr(),
+                               n, Wm.data_ptr(), n, info2.data_ptr(), None, 0, ob, sp) == 0
+
+        def ph_u():
+            assert gs.gsvd_u_recover(m, n, dA.data_ptr(), lda, Wm.data_ptr(), n, U2.data_ptr(), m,
+                                     ob, sp) == 0
+
+        ms_step = timed(step, args.steps, args.warmup)
+        ms_gram = timed(ph_gram, args.steps, 2)
+        ms_eig = timed(ph_eig, args.steps, 2)
+        ms_u = timed(ph_u, args.steps, 2)
+        log(f"{'split' if gram_mode == gs.GSVD_GRAM_SPLIT else 'plain'}: step {ms_step:.4f} ms, "
+            f"gram {ms_gram:.4f} eig {ms_eig:.4f} u {ms_u:.4f}")
+        return dict(ms_step=ms_step, ms_gram=ms_gram, ms_eig=ms_eig, ms_u=ms_u, S=S, V=V, U=U,
+                    info=info)
+
+    def check(r, oracle):
+        from oracle import ref
+        torch.cuda.synchronize()
+        Sn = r["S"].cpu().numpy()
+        Vn = r["V"].t().contiguous().cpu().numpy().T
+        Un = np.asfortranarray(r["U"].t().contiguous().cpu().numpy().T)
+        err = float(ref.sigma_rel_err(Sn, oracle).max())
+        orth = ref.orth(Un)
+        rows = np.random.default_rng(0).integers(0, m, 20000)
+        res = ref.resid(A, Un, Sn, Vn, rows=rows)
+        u = 2.0 ** -53
+        kb = oracle.kappa_b
+        acc = {"info": int(r["info"].item()), "sigma_max_rel_err": err,
+               "sigma_tol_50nu_kappaB": 50 * n * u * kb, "u_orth": orth,
+               "orth_tol_50nu": 50 * n * u, "resid_sampled": res, "kappa_b_oracle": kb}
+        acc["meets_tol"] = bool(acc["info"] == 0 and err <= acc["sigma_tol_50nu_kappaB"]
+                                and orth <= acc["orth_tol_50nu"] and res <= 50 * n * u)
+        return acc
+
+    log("plain form")
+    plain = measure(gs.GSVD_GRAM_PLAIN)
+    log("split form")
+    split = measure(gs.GSVD_GRAM_SPLIT)
 
     flops = m * n * (n + 1) + 2 * m * n * n
-    gflops = flops / (ms_step * 1e-3) / 1e9
+    gflops = flops / (plain["ms_step"] * 1e-3) / 1e9
     gram_bytes = m * n * 8 + n * n * 8
-    gram_gbps = gram_bytes / (ms_gram * 1e-3) / 1e9
     dd_macs = m * n * (n + 1) // 2
     alu_ops = 10 * dd_macs  # FP64 VALU operations of the dd multiply-accumulates
-    achieved = alu_ops / (ms_gram * 1e-3) / 1e12
+    achieved = alu_ops / (plain["ms_gram"] * 1e-3) / 1e12
+
+    def phases(r):
+        return {"gram": round(r["ms_gram"], 5), "eig": round(r["ms_eig"], 5),
+                "u": round(r["ms_u"], 5)}
 
     result = {
         "metric": METRIC,
@@ -175,7 +201,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": round(plain["ms_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -186,8 +212,17 @@ def main():
                         "shuffled); plain double-double Gram, Algorithm 2 eigensolver, MFMA U",
             "m": m, "n": n, "gram": "plain-dd", "eig": "alg2-chol-jacobi1",
         },
-        "gram_hbm_gbps": round(gram_gbps, 2),
-        "phases_ms": {"gram": round(ms_gram, 5), "eig": round(ms_eig, 5), "u": round(ms_u, 5)},
+        "gram_hbm_gbps": round(gram_bytes / (plain["ms_gram"] * 1e-3) / 1e9, 2),
+        "phases_ms": phases(plain),
+        "split": {
+            "gram": "int8-slices-10 (operand split on the int8 matrix cores, dd sums)",
+            "ms_per_step": round(split["ms_step"], 5),
+            "value": round(flops / (split["ms_step"] * 1e-3) / 1e9, 3),
+            "gram_hbm_gbps": round(gram_bytes / (split["ms_gram"] * 1e-3) / 1e9, 2),
+            "phases_ms": phases(split),
+            "speedup_vs_plain": round(plain["ms_step"] / split["ms_step"], 3),
+            "gram_speedup_vs_plain": round(plain["ms_gram"] / split["ms_gram"], 3),
+        },
         "roofline": {
             "kernel": "gram dd stage (gram_partial_kernel<double,true> + gram_reduce_kernel)",
             "bound": "alu",
@@ -202,32 +237,12 @@ def main():
 
     if not args.no_check:
         from oracle import ref
-        torch.cuda.synchronize()
-        inf = int(info.item())
-        Sn = S.cpu().numpy()
-        Vn = V.t().contiguous().cpu().numpy().T
-        Un = np.asfortranarray(U.t().contiguous().cpu().numpy().T)
         t1 = time.time()
         oracle = ref.svd(A)
-        err = float(ref.sigma_rel_err(Sn, oracle).max())
-        orth = ref.orth(Un)
-        rows = np.random.default_rng(0).integers(0, m, 20000)
-        res = ref.resid(A, Un, Sn, Vn, rows=rows)
-        u = 2.0 ** -53
-        kb = oracle.kappa_b
-        acc = {
-            "info": inf,
-            "sigma_max_rel_err": err,
-            "sigma_tol_50nu_kappaB": 50 * n * u * kb,
-            "u_orth": orth,
-            "orth_tol_50nu": 50 * n * u,
-            "resid_sampled": res,
-            "kappa_b_oracle": kb,
-        }
-        acc["meets_tol"] = bool(inf == 0 and err <= acc["sigma_tol_50nu_kappaB"]
-                                and orth <= acc["orth_tol_50nu"] and res <= 50 * n * u)
-        result["accuracy"] = acc
-        log(f"oracle check {time.time() - t1:.1f}s: {acc}")
+        result["accuracy"] = check(plain, oracle)
+        result["split"]["accuracy"] = check(split, oracle)
+        log(f"oracle check {time.time() - t1:.1f}s: plain {result['accuracy']}")
+        log(f"split {result['split']['accuracy']}")
 
     if not args.no_cpu:
         from oracle import ref

@@ -160,14 +160,16 @@ def workspace(nbytes: int, device):
 
 
 def thin(A, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, want_u: bool = True,
-         jacobi_tol: float = 0.0, max_sweeps: int = 0, work=None, stream=None):
+         jacobi_tol: float = 0.0, max_sweeps: int = 0, n_slices: int = 0, work=None,
+         stream=None):
     """Thin SVD of a column-major CUDA tensor A (m x n).  Returns (S, V, U, info) tensors;
     info is a one-element int32 device tensor (check it after synchronising)."""
     torch = _torch()
     w = _working_of(A)
     m, n = int(A.shape[0]), int(A.shape[1])
     lda = _ld(A)
-    o = opts(w, gram, eig, want_u=want_u, jacobi_tol=jacobi_tol, max_sweeps=max_sweeps)
+    o = opts(w, gram, eig, want_u=want_u, jacobi_tol=jacobi_tol, max_sweeps=max_sweeps,
+             n_slices=n_slices)
     S = torch.empty(n, dtype=A.dtype, device=A.device)
     V = colmajor_empty(n, n, A.dtype, A.device)
     U = colmajor_empty(m, n, A.dtype, A.device) if want_u else None

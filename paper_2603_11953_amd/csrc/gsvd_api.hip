@@ -32,9 +32,32 @@ int check_opts(const gsvd_opts *o, int argpos) {
 }
 
 int check_supported(const gsvd_opts *o) {
-    if (o->gram == GSVD_GRAM_SPLIT) return GSVD_ERR_UNSUPPORTED;
+    if (o->gram == GSVD_GRAM_SPLIT && o->n_slices > GSVD_MAX_SLICES) return GSVD_ERR_UNSUPPORTED;
     if (o->eig == GSVD_EIG_JACOBI2) return GSVD_ERR_UNSUPPORTED;
     return 0;
+}
+
+bool use_split(const gsvd_opts *o) { return o->gram == GSVD_GRAM_SPLIT; }
+
+int slices_of(const gsvd_opts *o) {
+    if (o->n_slices > 0) return o->n_slices;
+    return o->working == GSVD_F64 ? 10 : 6;
+}
+
+// workspace bytes for the partial sums of whichever Gram form o selects
+size_t gram_part_bytes(int64_t m, int64_t n, const gsvd_opts *o) {
+    if (use_split(o)) return gsvd::split_plan(m, n, slices_of(o)).part_bytes;
+    return gsvd::gram_plan(m, n).part_bytes;
+}
+
+hipError_t gram_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A, int64_t lda,
+                    double *Mhi, double *Mlo, int64_t ldm, void *part, hipStream_t st) {
+    if (use_split(o)) {
+        gsvd::SplitPlan p = gsvd::split_plan(m, n, slices_of(o));
+        return gsvd::split_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
+    }
+    gsvd::GramPlan p = gsvd::gram_plan(m, n);
+    return gsvd::gram_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
 }
 
 int check_eig_supported(const gsvd_opts *o, int64_t n) {
@@ -54,7 +77,6 @@ struct ThinLayout {
 ThinLayout thin_layout(int64_t m, int64_t n, const gsvd_opts *o) {
     ThinLayout L{};
     const size_t nn = (size_t)n * (size_t)n;
-    gsvd::GramPlan p = gsvd::gram_plan(m, n);
     size_t off = 0;
     L.mhi = off;
     off = align_up(off + nn * sizeof(double));
@@ -63,7 +85,7 @@ ThinLayout thin_layout(int64_t m, int64_t n, const gsvd_opts *o) {
     L.w = off;
     off = align_up(off + nn * wsize(o->working));
     L.part = off;
-    off = align_up(off + p.part_bytes);
+    off = align_up(off + gram_part_bytes(m, n, o));
     L.total = off;
     return L;
 }
@@ -99,9 +121,8 @@ const char *gsvd_status_string(int code) {
 }
 
 size_t gsvd_gram_workspace_size(int64_t m, int64_t n, const gsvd_opts *o) {
-    (void)o;
-    if (m < 1 || n < 1) return 0;
-    return align_up(gsvd::gram_plan(m, n).part_bytes);
+    if (m < 1 || n < 1 || o == nullptr) return 0;
+    return align_up(gram_part_bytes(m, n, o));
 }
 
 int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda, double *dMhi, double *dMlo,
@@ -118,9 +139,7 @@ int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda, double *dMhi, d
     if (work == nullptr || !aligned(work, kAlign)) return -8;
     if (work_bytes < need) return -9;
     if (int e = check_supported(o)) return e;
-    gsvd::GramPlan p = gsvd::gram_plan(m, n);
-    hipError_t err = gsvd::gram_launch(o->working, m, n, dA, lda, dMhi, dMlo, ldm, work, p,
-                                       (hipStream_t)stream);
+    hipError_t err = gram_any(o, m, n, dA, lda, dMhi, dMlo, ldm, work, (hipStream_t)stream);
     return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
 }
 
@@ -201,8 +220,7 @@ int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void 
     double *Mhi = (double *)(base + L.mhi);
     double *Mlo = (double *)(base + L.mlo);
     void *W = base + L.w;
-    gsvd::GramPlan p = gsvd::gram_plan(m, n);
-    hipError_t err = gsvd::gram_launch(o->working, m, n, dA, lda, Mhi, Mlo, n, base + L.part, p, st);
+    hipError_t err = gram_any(o, m, n, dA, lda, Mhi, Mlo, n, base + L.part, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     const double tol = o->jacobi_tol > 0 ? o->jacobi_tol
                                          : __builtin_sqrt((double)n) * unit_roundoff(o->working);

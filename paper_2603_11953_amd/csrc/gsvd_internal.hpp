@@ -29,6 +29,22 @@ hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t
                        double *Mhi, double *Mlo, int64_t ldm, void *part, const GramPlan &p,
                        hipStream_t st);
 
+// Launch geometry of the operand-split Gram (gram_split.hip).
+struct SplitPlan {
+    int S;                   // slices per entry
+    int nb;                  // ceil(n / 16): 16-column blocks
+    int npair;               // tiles in the upper triangle
+    int64_t rows_per_split;  // rows of A per slab
+    int64_t nsplit;          // slabs
+    size_t lds_bytes;
+    size_t part_bytes;
+};
+
+SplitPlan split_plan(int64_t m, int64_t n, int S);
+hipError_t split_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
+                        double *Mhi, double *Mlo, int64_t ldm, void *part, const SplitPlan &p,
+                        hipStream_t st);
+
 // Eigensolver stage (eig.hip).
 size_t eig_lds_bytes(int working, int64_t n);
 int eig_max_n(int working);

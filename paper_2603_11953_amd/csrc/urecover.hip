@@ -100,6 +100,108 @@ urecover_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__ W, i
     }
 }
 
+// Tiled variant: a workgroup (4 wavefronts) walks over 64-row tiles of A.  The
+// tile is staged in LDS (column-major, padded) by coalesced loads, the next
+// tile is fetched into registers while the current one is multiplied, and W
+// sits in LDS for the workgroup's lifetime.  The 4 x NT result tiles (16 x 16)
+// of a row tile are dealt round-robin to the wavefronts; each MFMA takes its
+// A and B operands from LDS.
+constexpr int UT_BM = 64;       // rows per tile
+constexpr int UT_THREADS = 256;
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(UT_THREADS)
+urecover_tile_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__ W, int64_t ldw,
+                     T *__restrict__ U, int64_t ldu, int64_t m, int n, int64_t ntiles) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    constexpr int NTC = NT * 16;
+    constexpr int LDA_S = UT_BM + 2;          // padded column stride of the A tile
+    constexpr int LDW_S = NTC + 2;            // padded row stride of W
+    constexpr int PER = UT_BM * NTC / UT_THREADS;  // staged tile values per lane
+    extern __shared__ unsigned char smem_raw[];
+    T *Ws = reinterpret_cast<T *>(smem_raw);  // [NTC rows k][LDW_S], row-major
+    T *As = Ws + NTC * LDW_S;                 // [NTC cols][LDA_S], column-major
+
+    for (int q = threadIdx.x; q < NTC * NTC; q += UT_THREADS) {
+        const int k = q / NTC, j = q % NTC;
+        Ws[k * LDW_S + j] = (k < n && j < n) ? W[k + (int64_t)j * ldw] : (T)0;
+    }
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ksteps = (n + 3) / 4;
+
+    T stage[PER];
+    auto fetch = [&](int64_t tile) {
+        const int64_t r0 = tile * UT_BM;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * UT_THREADS;
+            const int row = e % UT_BM, col = e / UT_BM;
+            const int64_t r = r0 + row;
+            stage[q] = (r < m && col < n) ? A[r + (int64_t)col * lda] : (T)0;
+        }
+    };
+
+    int64_t tile = blockIdx.x;
+    if (tile < ntiles) fetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        __syncthreads();  // previous tile fully consumed (and W staged, first time)
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * UT_THREADS;
+            As[(e / UT_BM) * LDA_S + (e % UT_BM)] = stage[q];
+        }
+        __syncthreads();
+        const int64_t next = tile + gridDim.x;
+        if (next < ntiles) fetch(next);
+        const int64_t r0 = tile * UT_BM;
+        for (int item = wave; item < 4 * NT; item += 4) {
+            const int rb = item / NT, ct = item % NT;
+            acc_t acc = acc_t{0, 0, 0, 0};
+            const T *ap = As + rb * 16 + li;
+            const T *bp = Ws + ct * 16 + li;
+            for (int s = 0; s < ksteps; ++s) {
+                const int k = 4 * s + lk;
+                acc = Mfma<T>::step(ap[k * LDA_S], bp[k * LDW_S], acc);
+            }
+            const int col = ct * 16 + li;
+            if (col < n) {
+                T *dst = U + r0 + rb * 16 + (int64_t)col * ldu;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = Mfma<T>::row(lk, r);
+                    if (r0 + rb * 16 + rr < m) dst[rr] = acc[r];
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int NT>
+static size_t tile_lds(void) {
+    return (size_t)(NT * 16) * (NT * 16 + 2) * sizeof(T) + (size_t)(NT * 16) * (UT_BM + 2) * sizeof(T);
+}
+
+template <typename T, int NT>
+static hipError_t launch_tile(int64_t m, int64_t n, const T *A, int64_t lda, const T *W,
+                              int64_t ldw, T *U, int64_t ldu, hipStream_t st) {
+    const int64_t ntiles = (m + UT_BM - 1) / UT_BM;
+    const size_t lds = tile_lds<T, NT>();
+    const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+    int64_t grid = 256 * per_cu;
+    if (grid > ntiles) grid = ntiles;
+    if (grid < 1) grid = 1;
+    auto k = urecover_tile_kernel<T, NT>;
+    hipError_t err = hipFuncSetAttribute((const void *)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(UT_THREADS), lds, st, A, lda, W, ldw, U, ldu,
+                       m, (int)n, ntiles);
+    return hipGetLastError();
+}
+
 template <typename T, int NT>
 static hipError_t launch_nt(int64_t m, int64_t n, const T *A, int64_t lda, const T *W, int64_t ldw,
                             T *U, int64_t ldu, hipStream_t st) {
@@ -119,6 +221,20 @@ static hipError_t launch_nt(int64_t m, int64_t n, const T *A, int64_t lda, const
 template <typename T>
 static hipError_t launch_t(int64_t m, int64_t n, const T *A, int64_t lda, const T *W, int64_t ldw,
                            T *U, int64_t ldu, hipStream_t st) {
+    // tiled kernel while W and one A tile fit LDS comfortably; strip kernel otherwise
+    switch ((n + 15) / 16) {
+        case 1: return launch_tile<T, 1>(m, n, A, lda, W, ldw, U, ldu, st);
+        case 2: return launch_tile<T, 2>(m, n, A, lda, W, ldw, U, ldu, st);
+        case 3: return launch_tile<T, 3>(m, n, A, lda, W, ldw, U, ldu, st);
+        case 4: return launch_tile<T, 4>(m, n, A, lda, W, ldw, U, ldu, st);
+        case 5: return launch_tile<T, 5>(m, n, A, lda, W, ldw, U, ldu, st);
+        case 6: return launch_tile<T, 6>(m, n, A, lda, W, ldw, U, ldu, st);
+        default: break;
+    }
+    if (sizeof(T) == 4 && n <= 128) {
+        if (n <= 112) return launch_tile<T, 7>(m, n, A, lda, W, ldw, U, ldu, st);
+        return launch_tile<T, 8>(m, n, A, lda, W, ldw, U, ldu, st);
+    }
     switch ((n + 15) / 16) {
         case 1: return launch_nt<T, 1>(m, n, A, lda, W, ldw, U, ldu, st);
         case 2: return launch_nt<T, 2>(m, n, A, lda, W, ldw, U, ldu, st);

@@ -102,7 +102,7 @@ def test_gram_eig_u_reject_bad_arguments():
 
 
 def test_unsupported_combinations_report_so():
-    o = gs.opts(gs.GSVD_F64, gs.GSVD_GRAM_SPLIT)
+    o = gs.opts(gs.GSVD_F64, gs.GSVD_GRAM_SPLIT, n_slices=13)
     rc = gs.gsvd_thin(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 100, FAKE, 1 << 40, FAKE,
                       ctypes.byref(o), None)
     assert rc == -101
