@@ -43,11 +43,15 @@ enum { GSVD_F32 = 0, GSVD_F64 = 1 };
 enum {
     GSVD_GRAM_AUTO = 0,   /* library choice (currently PLAIN) */
     GSVD_GRAM_PLAIN = 1,  /* FP32 A: exact FP64 products, FP64 sums; FP64 A: double-double */
-    GSVD_GRAM_SPLIT = 2   /* operand splitting: per 64-row chunk and column, a power-of-two
-                             exponent and n_slices signed 7-bit integer slices; slice pairs
-                             r + t <= n_slices + 1 multiplied exactly on the int8 matrix cores;
-                             sums in double-double (FP64 A) or FP64 (FP32 A).  Relative
-                             resolution about 2^(-7 n_slices) of each chunk's column maximum */
+    GSVD_GRAM_SPLIT = 2   /* operand splitting: per slab of rows and column, a power-of-two
+                             exponent above the column's largest entry (raised, with two
+                             bits of headroom, when a larger entry arrives); each entry cut
+                             into n_slices base-128 digits of its two's-complement fixed-point
+                             form; digit pairs r + t <= n_slices + 1 multiplied exactly on the
+                             int8 matrix cores, sums in double-double (FP64 A) or FP64 (FP32
+                             A).  Each entry is represented to within 2^(-7 n_slices) of its
+                             column exponent, i.e. at most 2^(4 - 7 n_slices) of the slab's
+                             column maximum */
 };
 
 /* eigensolver of Alg. 1 step 3 */
@@ -73,7 +77,8 @@ enum {
 #define GSVD_INFO_NONFINITE 3     /* A (hence M_h) holds a NaN or Inf */
 
 #define GSVD_MAX_N 128            /* largest n the current kernels accept */
-#define GSVD_MAX_SLICES 12        /* largest n_slices of the split Gram */
+#define GSVD_MAX_SLICES 12        /* largest n_slices of the split Gram, FP64 A */
+#define GSVD_MAX_SLICES_F32 8     /* largest n_slices of the split Gram, FP32 A */
 #define GSVD_MAX_N_EIG_F64 96     /* FP64 working: largest n of the eigensolver stage
                                      (larger n returns GSVD_ERR_UNSUPPORTED) */
 
@@ -81,7 +86,8 @@ typedef struct {
     int working;        /* GSVD_F32 or GSVD_F64 */
     int gram;           /* GSVD_GRAM_* */
     int eig;            /* GSVD_EIG_* */
-    int n_slices;       /* split Gram only: 1..GSVD_MAX_SLICES; 0 = 10 (FP64 A), 6 (FP32 A) */
+    int n_slices;       /* split Gram only: 1..GSVD_MAX_SLICES (FP64 A) or
+                           1..GSVD_MAX_SLICES_F32 (FP32 A); 0 = 10 (FP64), 6 (FP32) */
     double jacobi_tol;  /* rotation threshold: a pair p, q is rotated when
                            |g_pq| > tol * sqrt(g_pp g_qq); 0 = sqrt(n) * u */
     int max_sweeps;     /* 0 = 30 */

@@ -32,7 +32,9 @@ int check_opts(const gsvd_opts *o, int argpos) {
 }
 
 int check_supported(const gsvd_opts *o) {
-    if (o->gram == GSVD_GRAM_SPLIT && o->n_slices > GSVD_MAX_SLICES) return GSVD_ERR_UNSUPPORTED;
+    if (o->gram == GSVD_GRAM_SPLIT &&
+        o->n_slices > (o->working == GSVD_F64 ? GSVD_MAX_SLICES : GSVD_MAX_SLICES_F32))
+        return GSVD_ERR_UNSUPPORTED;
     if (o->eig == GSVD_EIG_JACOBI2) return GSVD_ERR_UNSUPPORTED;
     return 0;
 }

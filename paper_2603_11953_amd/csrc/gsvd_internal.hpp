@@ -41,6 +41,7 @@ struct SplitPlan {
 };
 
 SplitPlan split_plan(int64_t m, int64_t n, int S);
+int split_max_slices(int working);
 hipError_t split_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                         double *Mhi, double *Mlo, int64_t ldm, void *part, const SplitPlan &p,
                         hipStream_t st);

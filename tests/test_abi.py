@@ -102,10 +102,11 @@ def test_gram_eig_u_reject_bad_arguments():
 
 
 def test_unsupported_combinations_report_so():
-    o = gs.opts(gs.GSVD_F64, gs.GSVD_GRAM_SPLIT, n_slices=13)
-    rc = gs.gsvd_thin(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 100, FAKE, 1 << 40, FAKE,
-                      ctypes.byref(o), None)
-    assert rc == -101
+    for w, s in ((gs.GSVD_F64, 13), (gs.GSVD_F32, 9)):
+        o = gs.opts(w, gs.GSVD_GRAM_SPLIT, n_slices=s)
+        rc = gs.gsvd_thin(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 100, FAKE, 1 << 40, FAKE,
+                          ctypes.byref(o), None)
+        assert rc == -101
 
 
 def test_single_hip_runtime_in_process():

@@ -1,10 +1,11 @@
 """Parity of the operand-split Gram (integer slices on the int8 matrix cores) with the oracle.
 
-Error model of the split form, per row k and entry (i, j) of a 64-row chunk
-with column exponents e (|a| < 2^e over the chunk): each entry is cut to S
-signed 7-bit digits (tail < 2^(e - 7S)) and slice pairs r + t > S + 1 are
-dropped (sum < (S + 1) 2^(e_i + e_j - 7S)), so the chunk's error is at most
-(S + 3) 2^(-7S) sum_k 2^(e_i + e_j), plus double-double rounding.
+Error model of the split form.  Rows are processed in slabs (the same slab
+plan as the library: about m / 1024 rows, rounded up to 64); within a slab the
+exponent E_j of column j never exceeds ilogb(slab max of column j) + 4.  Each
+entry is cut to S base-128 digits with a tail below 2^(E - 7 S), and digit pairs
+r + t > S + 1 are dropped (sum below (S + 1) 2^(E_i + E_j - 7 S)), so a row adds
+an error of at most (S + 3) 2^(E_i + E_j - 7 S), plus double-double rounding.
 """
 import numpy as np
 import pytest
@@ -16,16 +17,22 @@ from tests.helpers import U_DD, check_thin, say, sigma_tol, to_dev, to_np, u_of
 pytestmark = pytest.mark.gpu
 
 
+def _slab_rows(m):
+    rps = -(-m // 1024)
+    return max(64, -(-rps // 64) * 64)
+
+
 def _split_bound(A, S):
     A = np.abs(A.astype(np.float64))
     m, n = A.shape
-    pad = (-m) % 64
+    rps = _slab_rows(m)
+    pad = (-m) % rps
     Ap = np.vstack([A, np.zeros((pad, n))])
-    cmax = Ap.reshape(-1, 64, n).max(axis=1)  # chunk column maxima
+    smax = Ap.reshape(-1, rps, n).max(axis=1)  # slab column maxima
     with np.errstate(divide="ignore"):
-        e = np.where(cmax > 0, np.floor(np.log2(np.where(cmax > 0, cmax, 1.0))) + 1, -np.inf)
-    p2 = np.where(np.isfinite(e), 2.0 ** e, 0.0)  # 2^e per chunk and column
-    return (S + 3) * 2.0 ** (-7 * S) * 64 * (p2.T @ p2)
+        e = np.where(smax > 0, np.floor(np.log2(np.where(smax > 0, smax, 1.0))) + 4, -np.inf)
+    p2 = np.where(np.isfinite(e), 2.0 ** e, 0.0)  # 2^E per slab and column
+    return (S + 3) * 2.0 ** (-7 * S) * rps * (p2.T @ p2)
 
 
 def _gram_split(A, S):
@@ -69,16 +76,17 @@ def test_split_gram_parity(m, n, dt, S):
 
 
 def test_split_gram_exact_on_short_integer_entries():
-    """Entries with <= 7 S significant bits below their chunk maximum are cut without a tail,
-    and with n_slices = S every kept pair is exact: the Gram of such a matrix must be exact."""
+    """Entries that fit in the first few digits are cut without a tail, and when every pair of
+    non-zero digits is kept the Gram of such a matrix must be exact."""
     rng = np.random.default_rng(5)
-    # 20-bit integers times a per-column power of two: 3 slices hold them exactly;
-    # S = 6 keeps every pair r + t <= 7, i.e. all 9 pairs of 3 x 3 slices
+    # 20-bit integers times 2^c: a column's exponent is at most c + 24, so its entries
+    # sit in digits 1..4 (bits above E - 28 <= c - 4, two's complement included);
+    # S = 7 keeps every pair r + t <= 8, i.e. all 16 pairs of those digits
     A = rng.integers(-(2 ** 20), 2 ** 20, size=(3000, 24)).astype(np.float64)
     A *= 2.0 ** rng.integers(-30, 30, size=24)[None, :]
     A = np.asfortranarray(A)
     say("split gram exact")
-    Mh, Ml = _gram_split(A, 6)
+    Mh, Ml = _gram_split(A, 7)
     oh, ol = ref.gram_dd(A)
     assert np.array_equal(Mh, oh) and np.array_equal(Ml, ol)
 
