@@ -45,7 +45,22 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-rows", type=int, default=1_000_000,
                     help="rows of A the CPU oracle processes for the baseline")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB buffer 3 times (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib: int) -> None:
+    """Plain device-to-device copies of a known size: under rocprofv3 --pmc the FETCH_SIZE and
+    WRITE_SIZE of these dispatches give the factor that turns the counters into bytes."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 copies of {mib} MiB")
 
 
 def log(*a):
@@ -81,6 +96,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU: use --gpus 1 "
                                    "(the row-split multi-GPU design is described, not built)"}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
 
