@@ -92,6 +92,9 @@ typedef struct {
                            |g_pq| > tol * sqrt(g_pp g_qq); 0 = sqrt(n) * u */
     int max_sweeps;     /* 0 = 30 */
     unsigned flags;     /* GSVD_WANT_U ... */
+    int64_t slab_rows;  /* rows of A per Gram workgroup ("slab"); 0 = the library's tuning
+                           table (written by paper_2603_11953_amd/autotune.py), falling
+                           back to about 512 (plain) / 1024 (split) slabs per matrix */
 } gsvd_opts;
 
 /* Fill *o with the defaults for the given working precision (WANT_U set). */
@@ -156,6 +159,39 @@ int gsvd_eig(int64_t n, const double *dMhi, const double *dMlo, int64_t ldm,
 int gsvd_u_recover(int64_t m, int64_t n, const void *dA, int64_t lda,
                    const void *dW, int64_t ldw, void *dU, int64_t ldu,
                    const gsvd_opts *o, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent problems of uneven shape in one call
+ * (the method of Alg. 1 applied to each; nothing couples the problems).
+ *
+ * gsvd_thin_batched: for b = 0 .. batch-1, the thin SVD of the hM[b] x hN[b]
+ * matrix at dA[b] (leading dimension hLda[b]), written to dS[b] (hN[b]),
+ * dV[b] (ldv hLdv[b]), dU[b] (ldu hLdu[b], only with GSVD_WANT_U) and
+ * dInfo[b], exactly as gsvd_thin would with the same options (the tuning table
+ * may pick a different slab height, so the Gram's rounding may differ).
+ *  - dA, dS, dV, dU: DEVICE arrays of `batch` device pointers (dU may be NULL
+ *    without GSVD_WANT_U).  hM, hN, hLda, hLdv, hLdu: HOST arrays of `batch`
+ *    entries (hLdu may be NULL without GSVD_WANT_U).  dInfo: device int[batch].
+ *  - Every problem: m >= n >= 1, n <= GSVD_MAX_N_EIG_F64 (FP64 working) or
+ *    GSVD_MAX_N (FP32 working); 1 <= batch <= 65535.  One set of options for
+ *    all; the per-problem default Jacobi threshold is sqrt(n) u.
+ *  - The whole plan travels in kernel arguments: the call performs no
+ *    host-to-device copy, allocation or synchronisation, so it can be
+ *    captured in a HIP graph; a replay is valid while the shapes, the pointer
+ *    arrays' contents and the workspace stay as they were at capture.
+ * Workspace: gsvd_thin_batched_workspace_size(batch, hM, hN, o) bytes (0 when
+ * a shape is invalid).
+ * Arguments: 1 batch, 2 hM, 3 hN, 4 dA, 5 hLda, 6 dS, 7 dV, 8 hLdv, 9 dU,
+ * 10 hLdu, 11 work, 12 work_bytes, 13 dInfo, 14 o, 15 stream.
+ * ------------------------------------------------------------------------- */
+size_t gsvd_thin_batched_workspace_size(int batch, const int64_t *hM, const int64_t *hN,
+                                        const gsvd_opts *o);
+int gsvd_thin_batched(int batch, const int64_t *hM, const int64_t *hN,
+                      const void *const *dA, const int64_t *hLda,
+                      void *const *dS, void *const *dV, const int64_t *hLdv,
+                      void *const *dU, const int64_t *hLdu,
+                      void *work, size_t work_bytes, int *dInfo,
+                      const gsvd_opts *o, void *stream);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,8 @@ __all__ = [
     "GsvdOpts", "GsvdError", "lib", "lib_path", "opts", "thin", "gram", "eig", "u_recover",
     "gsvd_opts_default", "gsvd_status_string", "gsvd_thin", "gsvd_thin_workspace_size",
     "gsvd_gram", "gsvd_gram_workspace_size", "gsvd_eig", "gsvd_eig_workspace_size",
-    "gsvd_u_recover",
+    "gsvd_u_recover", "gsvd_thin_batched", "gsvd_thin_batched_workspace_size", "thin_batched",
+    "Batch",
 ]
 
 GSVD_F32, GSVD_F64 = 0, 1
@@ -43,6 +44,7 @@ class GsvdOpts(ctypes.Structure):
         ("jacobi_tol", ctypes.c_double),
         ("max_sweeps", ctypes.c_int),
         ("flags", ctypes.c_uint),
+        ("slab_rows", ctypes.c_int64),
     ]
 
 
@@ -84,6 +86,10 @@ def _load() -> ctypes.CDLL:
     L.gsvd_eig.restype = ci
     L.gsvd_u_recover.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, op, vp]
     L.gsvd_u_recover.restype = ci
+    L.gsvd_thin_batched_workspace_size.argtypes = [ci, vp, vp, op]
+    L.gsvd_thin_batched_workspace_size.restype = sz
+    L.gsvd_thin_batched.argtypes = [ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, op, vp]
+    L.gsvd_thin_batched.restype = ci
     return L
 
 
@@ -98,6 +104,8 @@ gsvd_gram_workspace_size = lib.gsvd_gram_workspace_size
 gsvd_eig = lib.gsvd_eig
 gsvd_eig_workspace_size = lib.gsvd_eig_workspace_size
 gsvd_u_recover = lib.gsvd_u_recover
+gsvd_thin_batched = lib.gsvd_thin_batched
+gsvd_thin_batched_workspace_size = lib.gsvd_thin_batched_workspace_size
 
 
 def gsvd_status_string(code: int) -> str:
@@ -106,12 +114,13 @@ def gsvd_status_string(code: int) -> str:
 
 def opts(working: int, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, *,
          want_u: bool = True, jacobi_tol: float = 0.0, max_sweeps: int = 0,
-         n_slices: int = 0) -> GsvdOpts:
+         n_slices: int = 0, slab_rows: int = 0) -> GsvdOpts:
     o = GsvdOpts()
     lib.gsvd_opts_default(ctypes.byref(o), int(working))
     o.gram, o.eig, o.n_slices = int(gram), int(eig), int(n_slices)
     o.jacobi_tol, o.max_sweeps = float(jacobi_tol), int(max_sweeps)
     o.flags = GSVD_WANT_U if want_u else 0
+    o.slab_rows = int(slab_rows)
     return o
 
 
@@ -160,8 +169,8 @@ def workspace(nbytes: int, device):
 
 
 def thin(A, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, want_u: bool = True,
-         jacobi_tol: float = 0.0, max_sweeps: int = 0, n_slices: int = 0, work=None,
-         stream=None):
+         jacobi_tol: float = 0.0, max_sweeps: int = 0, n_slices: int = 0, slab_rows: int = 0,
+         work=None, stream=None):
     """Thin SVD of a column-major CUDA tensor A (m x n).  Returns (S, V, U, info) tensors;
     info is a one-element int32 device tensor (check it after synchronising)."""
     torch = _torch()
@@ -169,7 +178,7 @@ def thin(A, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, want_u: boo
     m, n = int(A.shape[0]), int(A.shape[1])
     lda = _ld(A)
     o = opts(w, gram, eig, want_u=want_u, jacobi_tol=jacobi_tol, max_sweeps=max_sweeps,
-             n_slices=n_slices)
+             n_slices=n_slices, slab_rows=slab_rows)
     S = torch.empty(n, dtype=A.dtype, device=A.device)
     V = colmajor_empty(n, n, A.dtype, A.device)
     U = colmajor_empty(m, n, A.dtype, A.device) if want_u else None
@@ -229,3 +238,62 @@ def u_recover(A, W, *, stream=None):
                             ctypes.byref(o), _stream(stream))
     _check(rc, "gsvd_u_recover")
     return U
+
+
+class Batch:
+    """Everything one gsvd_thin_batched call needs, prepared once: outputs, the device
+    pointer arrays, the host shape arrays and the workspace.  ``run()`` enqueues the
+    call (capturable in a graph: it only launches kernels)."""
+
+    def __init__(self, As, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO,
+                 want_u: bool = True, jacobi_tol: float = 0.0, max_sweeps: int = 0,
+                 n_slices: int = 0, slab_rows: int = 0):
+        torch = _torch()
+        if len(As) < 1:
+            raise ValueError("empty batch")
+        dev = As[0].device
+        w = _working_of(As[0])
+        if any(_working_of(a) != w for a in As):
+            raise TypeError("all matrices of a batch share one dtype")
+        self.count = len(As)
+        self.As = list(As)
+        self.o = opts(w, gram, eig, want_u=want_u, jacobi_tol=jacobi_tol,
+                      max_sweeps=max_sweeps, n_slices=n_slices, slab_rows=slab_rows)
+        i64 = ctypes.c_int64 * self.count
+        self.hM = i64(*[int(a.shape[0]) for a in As])
+        self.hN = i64(*[int(a.shape[1]) for a in As])
+        self.hLda = i64(*[_ld(a) for a in As])
+        self.S = [torch.empty(int(a.shape[1]), dtype=a.dtype, device=dev) for a in As]
+        self.V = [colmajor_empty(int(a.shape[1]), int(a.shape[1]), a.dtype, dev) for a in As]
+        self.U = ([colmajor_empty(int(a.shape[0]), int(a.shape[1]), a.dtype, dev) for a in As]
+                  if want_u else None)
+        self.hLdv = i64(*[int(a.shape[1]) for a in As])
+        self.hLdu = i64(*[int(a.shape[0]) for a in As])
+        self.info = torch.full((self.count,), -1, dtype=torch.int32, device=dev)
+
+        def ptrs(ts):
+            return torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=dev)
+
+        self.dA, self.dS, self.dV = ptrs(self.As), ptrs(self.S), ptrs(self.V)
+        self.dU = ptrs(self.U) if want_u else None
+        need = lib.gsvd_thin_batched_workspace_size(self.count, self.hM, self.hN,
+                                                     ctypes.byref(self.o))
+        if need == 0:
+            raise GsvdError("gsvd_thin_batched_workspace_size: invalid shapes or options")
+        self.work = workspace(need, dev)
+
+    def run(self, stream=None) -> None:
+        rc = lib.gsvd_thin_batched(
+            self.count, self.hM, self.hN, self.dA.data_ptr(), self.hLda, self.dS.data_ptr(),
+            self.dV.data_ptr(), self.hLdv, self.dU.data_ptr() if self.dU is not None else None,
+            self.hLdu, self.work.data_ptr(), self.work.numel(), self.info.data_ptr(),
+            ctypes.byref(self.o), _stream(stream))
+        _check(rc, "gsvd_thin_batched")
+
+
+def thin_batched(As, *, stream=None, **kw):
+    """Thin SVDs of a list of column-major CUDA tensors in one batched call.
+    Returns (S list, V list, U list or None, info tensor)."""
+    b = Batch(As, **kw)
+    b.run(stream)
+    return b.S, b.V, b.U, b.info

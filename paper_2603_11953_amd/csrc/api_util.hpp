@@ -1,0 +1,91 @@
+// Host-side helpers shared by the single-problem and batched entry points:
+// option checks, the slice count and slab height in force, workspace alignment.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "gsvd.h"
+#include "gsvd_internal.hpp"
+#include "tune.hpp"
+
+namespace gsvd {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+inline bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+inline double unit_roundoff(int working) { return working == GSVD_F64 ? 0x1p-53 : 0x1p-24; }
+
+inline size_t wsize(int working) { return working == GSVD_F64 ? 8 : 4; }
+
+// Checks shared by every entry point that takes options.
+inline int check_opts(const gsvd_opts *o, int argpos) {
+    if (o == nullptr) return -argpos;
+    if (o->working != GSVD_F32 && o->working != GSVD_F64) return -argpos;
+    if (o->gram != GSVD_GRAM_AUTO && o->gram != GSVD_GRAM_PLAIN && o->gram != GSVD_GRAM_SPLIT)
+        return -argpos;
+    if (o->eig != GSVD_EIG_AUTO && o->eig != GSVD_EIG_JACOBI2 && o->eig != GSVD_EIG_CHOL_JACOBI1)
+        return -argpos;
+    if (o->max_sweeps < 0 || o->jacobi_tol < 0.0 || o->n_slices < 0 || o->slab_rows < 0)
+        return -argpos;
+    return 0;
+}
+
+inline int max_slices(int working) {
+    return working == GSVD_F64 ? GSVD_MAX_SLICES : GSVD_MAX_SLICES_F32;
+}
+
+inline int check_supported(const gsvd_opts *o) {
+    if (o->gram == GSVD_GRAM_SPLIT && o->n_slices > max_slices(o->working))
+        return GSVD_ERR_UNSUPPORTED;
+    if (o->eig == GSVD_EIG_JACOBI2) return GSVD_ERR_UNSUPPORTED;
+    return 0;
+}
+
+inline int check_eig_supported(const gsvd_opts *o, int64_t n) {
+    if (int e = check_supported(o)) return e;
+    if (o->working == GSVD_F64 && n > GSVD_MAX_N_EIG_F64) return GSVD_ERR_UNSUPPORTED;
+    return 0;
+}
+
+inline bool use_split(const gsvd_opts *o) { return o->gram == GSVD_GRAM_SPLIT; }
+
+// slice count of the split Gram: the caller's, else the tuning table's
+inline int slices_of(const gsvd_opts *o, int64_t n) {
+    if (o->n_slices > 0) return o->n_slices;
+    return tune_slices(o->working, n);
+}
+
+// slab height of the Gram: the caller's, else the tuning table's (0 = the
+// kernel's own default slab count)
+inline int64_t slab_rows_of(const gsvd_opts *o, int64_t m, int64_t n, bool batched) {
+    if (o->slab_rows > 0) return o->slab_rows;
+    return tune_slab_rows(o->working, use_split(o) ? GSVD_GRAM_SPLIT : GSVD_GRAM_PLAIN, n, m,
+                          batched);
+}
+
+inline GramPlan gram_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool batched) {
+    return gram_plan(m, n, slab_rows_of(o, m, n, batched));
+}
+
+inline SplitPlan split_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool batched) {
+    return split_plan(m, n, slices_of(o, n), slab_rows_of(o, m, n, batched));
+}
+
+// workspace bytes for the partial sums of whichever Gram form o selects
+inline size_t gram_part_bytes(int64_t m, int64_t n, const gsvd_opts *o, bool batched) {
+    if (use_split(o)) return split_plan_of(o, m, n, batched).part_bytes;
+    return gram_plan_of(o, m, n, batched).part_bytes;
+}
+
+inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
+    return o->jacobi_tol > 0 ? o->jacobi_tol : __builtin_sqrt((double)n) * unit_roundoff(o->working);
+}
+
+inline int sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 30; }
+
+}  // namespace gsvd

@@ -39,7 +39,8 @@
 namespace gsvd {
 
 constexpr int GRP = 8;  // lanes per Jacobi pair: half a DPP row
-constexpr int MAXREG = 32;  // entries of R per lane while it moves into Y (see eig_launch)
+constexpr int MAXREG = 16;  // entries of R per lane while it moves into Y: n^2 / lanes <= 16
+                            // for n <= 128 with 1024 lanes and for n < 32 with 8 (n+1)/2
 
 // Column stride of R and V in LDS during the Jacobi: n rounded up to a
 // multiple of 256 bytes.
@@ -97,19 +98,29 @@ __device__ __forceinline__ double rsq_nr(double x) {
     return y;
 }
 
+// Workgroup-shared state of the eigensolver besides the dynamic LDS square.
+struct EigSmem {
+    EigShared sh;
+    int sexp[GSVD_KMAX_N];
+    double ssig[GSVD_KMAX_N];
+    int srank[GSVD_KMAX_N];
+    double ssign[GSVD_KMAX_N];
+    dd_t rowk[GSVD_KMAX_N];
+};
+
+// Algorithm 2 for one n x n Gram (one workgroup; n <= GRP * RPL).
 template <typename TW, typename TS, bool DDGRAM, int RPL>
-__global__ void __launch_bounds__(1024)
-eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__restrict__ Mlo,
-                        int64_t ldm, TW *__restrict__ S, TW *__restrict__ V, int64_t ldv,
-                        TW *__restrict__ W, int64_t ldw, int *__restrict__ info, double tol2,
-                        int max_sweeps) {
-    extern __shared__ double lds[];
-    __shared__ EigShared sh;
-    __shared__ int sexp[GSVD_KMAX_N];
-    __shared__ double ssig[GSVD_KMAX_N];
-    __shared__ int srank[GSVD_KMAX_N];
-    __shared__ double ssign[GSVD_KMAX_N];
-    __shared__ dd_t rowk[GSVD_KMAX_N];
+__device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
+                                         const double *__restrict__ Mlo, int64_t ldm,
+                                         TW *__restrict__ S, TW *__restrict__ V, int64_t ldv,
+                                         TW *__restrict__ W, int64_t ldw, int *__restrict__ info,
+                                         double tol2, int max_sweeps, EigSmem &sm, double *lds) {
+    EigShared &sh = sm.sh;
+    int *sexp = sm.sexp;
+    double *ssig = sm.ssig;
+    int *srank = sm.srank;
+    double *ssign = sm.ssign;
+    dd_t *rowk = sm.rowk;
 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
@@ -393,6 +404,49 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
     if (tid == 0) *info = 0;
 }
 
+template <typename TW, typename TS, bool DDGRAM, int RPL>
+__global__ void __launch_bounds__(1024)
+eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__restrict__ Mlo,
+                        int64_t ldm, TW *__restrict__ S, TW *__restrict__ V, int64_t ldv,
+                        TW *__restrict__ W, int64_t ldw, int *__restrict__ info, double tol2,
+                        int max_sweeps) {
+    extern __shared__ double lds[];
+    __shared__ EigSmem sm;
+    eig_body<TW, TS, DDGRAM, RPL>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2, max_sweeps, sm,
+                                  lds);
+}
+
+// Batched: one workgroup per problem, the largest first (order is ascending in
+// n); the register depth RPL = ceil(n / GRP) is chosen per problem.  tol <= 0
+// selects sqrt(n) u_w.
+template <typename TW, typename TS, bool DDGRAM, int MAXRPL>
+__global__ void __launch_bounds__(1024)
+eig_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order, int batch,
+                   double tol, int max_sweeps) {
+    extern __shared__ double lds[];
+    __shared__ EigSmem sm;
+    const BatchMat &d = tab[order[batch - 1 - (int)blockIdx.x]];
+    const int n = d.n;
+    const double u = sizeof(TW) == 8 ? 0x1p-53 : 0x1p-24;
+    const double tol2 = tol > 0.0 ? tol * tol : (double)n * u * u;
+    const double *Mlo = DDGRAM ? d.Mlo : nullptr;
+#define GSVD_EIG_BODY(R)                                                                        \
+    case R:                                                                                     \
+        if (R <= MAXRPL)                                                                        \
+            eig_body<TW, TS, DDGRAM, (R <= MAXRPL ? R : 1)>(                                    \
+                n, d.Mhi, Mlo, n, (TW *)d.S, (TW *)d.V, d.ldv, (TW *)d.W, n, d.info, tol2,      \
+                max_sweeps, sm, lds);                                                           \
+        break;
+    switch ((n + GRP - 1) / GRP) {
+        GSVD_EIG_BODY(1) GSVD_EIG_BODY(2) GSVD_EIG_BODY(3) GSVD_EIG_BODY(4)
+        GSVD_EIG_BODY(5) GSVD_EIG_BODY(6) GSVD_EIG_BODY(7) GSVD_EIG_BODY(8)
+        GSVD_EIG_BODY(9) GSVD_EIG_BODY(10) GSVD_EIG_BODY(11) GSVD_EIG_BODY(12)
+        GSVD_EIG_BODY(13) GSVD_EIG_BODY(14) GSVD_EIG_BODY(15) GSVD_EIG_BODY(16)
+        default: break;
+    }
+#undef GSVD_EIG_BODY
+}
+
 size_t eig_lds_bytes(int working, int64_t n) {
     const size_t chol = (size_t)(n * n) * (working == 1 ? sizeof(dd_t) : sizeof(double));
     const size_t jac = working == 1 ? 2 * (size_t)(n * jac_ld<double>((int)n)) * sizeof(double)
@@ -471,6 +525,31 @@ hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *M
     }
     return launch_t<float, float, false>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2,
                                          max_sweeps, lds, thr, st);
+}
+
+hipError_t eig_batched_launch(int working, const BatchMat *tab, const int *order, int batch,
+                              int max_n, double tol, int max_sweeps, hipStream_t st) {
+    if (batch < 1 || max_n < 1 || max_n > eig_max_n(working)) return hipErrorInvalidValue;
+    const size_t lds = eig_lds_bytes(working, max_n);
+    const int thr = eig_threads(max_n);
+    if ((max_n * max_n + thr - 1) / thr > MAXREG) return hipErrorInvalidValue;
+    hipError_t err;
+    if (working == 1) {
+        auto k = eig_batched_kernel<double, double, true, GSVD_KMAX_N_F64 / GRP>;
+        err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k, dim3((unsigned)batch), dim3(thr), lds, st, tab, order, batch, tol,
+                           max_sweeps);
+    } else {
+        auto k = eig_batched_kernel<float, float, false, GSVD_KMAX_N / GRP>;
+        err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k, dim3((unsigned)batch), dim3(thr), lds, st, tab, order, batch, tol,
+                           max_sweeps);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace gsvd

@@ -42,11 +42,12 @@ __device__ __forceinline__ void decode_block(int b, int nb, int &bi, int &bj) {
 
 constexpr int GRAM_MAX_THREADS = 768;  // three waves per SIMD: up to 168 VGPRs per lane
 
+// The partial Gram of slab `split` of one matrix (one workgroup).
 template <typename T, bool DD>
-__global__ void __launch_bounds__(GRAM_MAX_THREADS)
-gram_partial_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int nb, int nblk,
-                    int ks, int kc, int64_t rows_per_split, double *__restrict__ part) {
-    extern __shared__ double lds[];
+__device__ __forceinline__ void gram_partial_body(const T *__restrict__ A, int64_t lda, int64_t m,
+                                                  int n, int nb, int nblk, int ks, int kc,
+                                                  int64_t rows_per_split, int64_t split,
+                                                  double *__restrict__ part, double *lds) {
     const int NC = BS * nb;     // staged columns (n rounded up to a multiple of 4)
     const int LDL = NC + 2;     // row stride in LDS (16-byte aligned rows)
     double *buf0 = lds;
@@ -60,7 +61,6 @@ gram_partial_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int 
     int bi = 0, bj = 0;
     if (active) decode_block(b, nb, bi, bj);
 
-    const int64_t split = blockIdx.y;
     const int64_t r0 = split * rows_per_split;
     const int64_t r1 = (r0 + rows_per_split < m) ? r0 + rows_per_split : m;
     const int nchunk = (int)((r1 - r0 + kc - 1) / kc);
@@ -186,11 +186,31 @@ gram_partial_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int 
     }
 }
 
+template <typename T, bool DD>
+__global__ void __launch_bounds__(GRAM_MAX_THREADS)
+gram_partial_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int nb, int nblk,
+                    int ks, int kc, int64_t rows_per_split, double *__restrict__ part) {
+    extern __shared__ double lds[];
+    gram_partial_body<T, DD>(A, lda, m, n, nb, nblk, ks, kc, rows_per_split, blockIdx.y, part, lds);
+}
+
+// Batched: blockIdx.z picks the problem order[first + z], blockIdx.y its slab.
+template <typename T, bool DD>
+__global__ void __launch_bounds__(GRAM_MAX_THREADS)
+gram_partial_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order,
+                            int first, int nb, int nblk, int ks, int kc) {
+    extern __shared__ double lds[];
+    const BatchMat &d = tab[order[first + blockIdx.z]];
+    if ((int)blockIdx.y >= d.nsplit) return;
+    gram_partial_body<T, DD>(reinterpret_cast<const T *>(d.A), d.lda, d.m, d.n, nb, nblk, ks, kc,
+                             d.rows_per_split, blockIdx.y, d.part, lds);
+}
+
 // One wavefront per M entry: lane l adds splits l, l + 64, ... in order, then a
 // fixed xor-butterfly over the 64 lanes; lane 0 writes M(i, j) and M(j, i).
-__global__ void __launch_bounds__(256)
-gram_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nb, int nblk, int n,
-                   double *__restrict__ Mhi, double *__restrict__ Mlo, int64_t ldm) {
+__device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part, int64_t nsplit,
+                                                 int nb, int nblk, int n, double *__restrict__ Mhi,
+                                                 double *__restrict__ Mlo, int64_t ldm) {
     const int lane = threadIdx.x & 63;
     const int64_t entry = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (entry >= (int64_t)nblk * BS * BS) return;
@@ -220,7 +240,21 @@ gram_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nb, int 
     }
 }
 
-GramPlan gram_plan(int64_t m, int64_t n) {
+__global__ void __launch_bounds__(256)
+gram_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nb, int nblk, int n,
+                   double *__restrict__ Mhi, double *__restrict__ Mlo, int64_t ldm) {
+    gram_reduce_body(part, nsplit, nb, nblk, n, Mhi, Mlo, ldm);
+}
+
+// Batched: blockIdx.y is the problem; blocks past its entries return at once.
+__global__ void __launch_bounds__(256)
+gram_reduce_batched_kernel(const BatchMat *__restrict__ tab) {
+    const BatchMat &d = tab[blockIdx.y];
+    const int nb = (d.n + BS - 1) / BS;
+    gram_reduce_body(d.part, d.nsplit, nb, nb * (nb + 1) / 2, d.n, d.Mhi, d.Mlo, d.n);
+}
+
+GramPlan gram_plan(int64_t m, int64_t n, int64_t slab_rows) {
     GramPlan p{};
     p.nb = (int)((n + BS - 1) / BS);
     p.nblk = p.nb * (p.nb + 1) / 2;
@@ -244,7 +278,7 @@ GramPlan gram_plan(int64_t m, int64_t n) {
     p.kc = p.ks * kk;
     // slabs: about two workgroups per compute unit, every slab a multiple of kc rows
     int64_t target = 512;
-    int64_t rps = (m + target - 1) / target;
+    int64_t rps = slab_rows > 0 ? slab_rows : (m + target - 1) / target;
     rps = ((rps + p.kc - 1) / p.kc) * p.kc;
     if (rps < p.kc) rps = p.kc;
     p.rows_per_split = rps;
@@ -257,12 +291,15 @@ GramPlan gram_plan(int64_t m, int64_t n) {
     return p;
 }
 
+static bool plan_ok(const GramPlan &p) {
+    return !(p.threads > GRAM_MAX_THREADS || (p.kc * BS * p.nb + p.threads - 1) / p.threads > MAXPER ||
+             p.ks * p.nblk > p.threads || p.lds_bytes > 160 * 1024);
+}
+
 hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                        double *Mhi, double *Mlo, int64_t ldm, void *part, const GramPlan &p,
                        hipStream_t st) {
-    if (p.threads > GRAM_MAX_THREADS || (p.kc * BS * p.nb + p.threads - 1) / p.threads > MAXPER ||
-        p.ks * p.nblk > p.threads || p.lds_bytes > 160 * 1024)
-        return hipErrorInvalidValue;
+    if (!plan_ok(p)) return hipErrorInvalidValue;
     dim3 grid(1, (unsigned)p.nsplit);
     hipError_t err;
     if (working == 1) {
@@ -286,6 +323,39 @@ hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t
     const unsigned rgrid = (unsigned)((entries + 3) / 4);
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(rgrid), dim3(256), 0, st, (const double *)part,
                        p.nsplit, p.nb, p.nblk, (int)n, Mhi, Mlo, ldm);
+    return hipGetLastError();
+}
+
+hipError_t gram_batched_launch(int working, const BatchMat *tab, const int *order, int first,
+                               int count, int max_nsplit, const GramPlan &p, hipStream_t st) {
+    if (!plan_ok(p) || count < 1 || count > 65535 || max_nsplit < 1 || max_nsplit > 65535)
+        return hipErrorInvalidValue;
+    const dim3 grid(1, (unsigned)max_nsplit, (unsigned)count);
+    hipError_t err;
+    if (working == 1) {
+        auto k = gram_partial_batched_kernel<double, true>;
+        err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)p.lds_bytes);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k, grid, dim3(p.threads), p.lds_bytes, st, tab, order, first, p.nb,
+                           p.nblk, p.ks, p.kc);
+    } else {
+        auto k = gram_partial_batched_kernel<float, false>;
+        err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)p.lds_bytes);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k, grid, dim3(p.threads), p.lds_bytes, st, tab, order, first, p.nb,
+                           p.nblk, p.ks, p.kc);
+    }
+    return hipGetLastError();
+}
+
+hipError_t gram_reduce_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st) {
+    if (batch < 1 || batch > 65535 || max_n < 1) return hipErrorInvalidValue;
+    const int nb = (max_n + BS - 1) / BS;
+    const int64_t entries = (int64_t)(nb * (nb + 1) / 2) * BS * BS;
+    hipLaunchKernelGGL(gram_reduce_batched_kernel, dim3((unsigned)((entries + 3) / 4), (unsigned)batch),
+                       dim3(256), 0, st, tab);
     return hipGetLastError();
 }
 

@@ -130,10 +130,12 @@ __host__ __device__ constexpr int sp_waves(int nb) {
     return (nb * (nb + 1) / 2 + sp_groups(nb) - 1) / sp_groups(nb);
 }
 
+// The partial Gram of slab `split` of one matrix, tiles of workgroup `grp`.
 template <typename T, int NB>
-__global__ void __launch_bounds__(64 * sp_waves(NB))
-gram_split_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int S,
-                  int64_t rows_per_split, double *__restrict__ part) {
+__device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t lda, int64_t m,
+                                                int n, int S, int64_t rows_per_split,
+                                                int64_t split, int grp,
+                                                double *__restrict__ part) {
     constexpr bool DD = sizeof(T) == 8;
     constexpr int SMAX = SplitMax<T>::S;
     constexpr int NW = sp_waves(NB);
@@ -150,13 +152,12 @@ gram_split_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int S,
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int64_t split = blockIdx.y;
     const int64_t r0 = split * rows_per_split;
     const int64_t r1 = (r0 + rows_per_split < m) ? r0 + rows_per_split : m;
     const int nchunk = (int)((r1 - r0 + SP_KT - 1) / SP_KT);
 
     // this wavefront's tile (I, J), I <= J
-    const int pidx = blockIdx.x * NW + wave;
+    const int pidx = grp * NW + wave;
     const bool has_tile = pidx < NPAIR;
     int bi = 0, bj = 0;
     if (has_tile) sp_decode_pair(pidx, NB, bi, bj);
@@ -304,10 +305,29 @@ gram_split_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int S,
     flush(first_flush);
 }
 
+template <typename T, int NB>
+__global__ void __launch_bounds__(64 * sp_waves(NB))
+gram_split_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int S,
+                  int64_t rows_per_split, double *__restrict__ part) {
+    gram_split_body<T, NB>(A, lda, m, n, S, rows_per_split, blockIdx.y, blockIdx.x, part);
+}
+
+// Batched: blockIdx.z picks the problem order[first + z], blockIdx.y its slab.
+template <typename T, int NB>
+__global__ void __launch_bounds__(64 * sp_waves(NB))
+gram_split_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order,
+                          int first, int S) {
+    const BatchMat &d = tab[order[first + blockIdx.z]];
+    if ((int)blockIdx.y >= d.nsplit) return;
+    gram_split_body<T, NB>(reinterpret_cast<const T *>(d.A), d.lda, d.m, d.n, S,
+                           d.rows_per_split, blockIdx.y, blockIdx.x, d.part);
+}
+
 // One wavefront per M entry of the tile layout; splits added as in the plain form.
-__global__ void __launch_bounds__(256)
-gram_split_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nb, int npair, int n,
-                         double *__restrict__ Mhi, double *__restrict__ Mlo, int64_t ldm) {
+__device__ __forceinline__ void gram_split_reduce_body(const double *__restrict__ part,
+                                                       int64_t nsplit, int nb, int npair, int n,
+                                                       double *__restrict__ Mhi,
+                                                       double *__restrict__ Mlo, int64_t ldm) {
     const int lanew = threadIdx.x & 63;
     const int64_t entry = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (entry >= (int64_t)npair * 256) return;
@@ -339,13 +359,27 @@ gram_split_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nb
 }
 
 
-SplitPlan split_plan(int64_t m, int64_t n, int S) {
+__global__ void __launch_bounds__(256)
+gram_split_reduce_kernel(const double *__restrict__ part, int64_t nsplit, int nb, int npair, int n,
+                         double *__restrict__ Mhi, double *__restrict__ Mlo, int64_t ldm) {
+    gram_split_reduce_body(part, nsplit, nb, npair, n, Mhi, Mlo, ldm);
+}
+
+// Batched: blockIdx.y is the problem; blocks past its entries return at once.
+__global__ void __launch_bounds__(256)
+gram_split_reduce_batched_kernel(const BatchMat *__restrict__ tab) {
+    const BatchMat &d = tab[blockIdx.y];
+    const int nb = (d.n + 15) / 16;
+    gram_split_reduce_body(d.part, d.nsplit, nb, nb * (nb + 1) / 2, d.n, d.Mhi, d.Mlo, d.n);
+}
+
+SplitPlan split_plan(int64_t m, int64_t n, int S, int64_t slab_rows) {
     SplitPlan p{};
     p.S = S;
     p.nb = (int)((n + 15) / 16);
     p.npair = p.nb * (p.nb + 1) / 2;
     int64_t target = 1024;  // slabs: four workgroups per compute unit
-    int64_t rps = (m + target - 1) / target;
+    int64_t rps = slab_rows > 0 ? slab_rows : (m + target - 1) / target;
     rps = ((rps + SP_KT - 1) / SP_KT) * SP_KT;
     if (rps < SP_KT) rps = SP_KT;
     p.rows_per_split = rps;
@@ -401,6 +435,53 @@ hipError_t split_launch(int working, int64_t m, int64_t n, const void *A, int64_
     if (working == 1)
         return split_launch_t<double>(m, n, (const double *)A, lda, Mhi, Mlo, ldm, part, p, st);
     return split_launch_t<float>(m, n, (const float *)A, lda, Mhi, Mlo, ldm, part, p, st);
+}
+
+template <typename T, int NB>
+static hipError_t split_batched_nb(const BatchMat *tab, const int *order, int first, int count,
+                                   int max_nsplit, const SplitPlan &p, hipStream_t st) {
+    auto k = gram_split_batched_kernel<T, NB>;
+    hipError_t err = hipFuncSetAttribute((const void *)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)p.lds_bytes);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k, dim3(sp_groups(NB), (unsigned)max_nsplit, (unsigned)count),
+                       dim3(64 * sp_waves(NB)), p.lds_bytes, st, tab, order, first, p.S);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t split_batched_t(const BatchMat *tab, const int *order, int first, int count,
+                                  int max_nsplit, const SplitPlan &p, hipStream_t st) {
+    switch (p.nb) {
+        case 1: return split_batched_nb<T, 1>(tab, order, first, count, max_nsplit, p, st);
+        case 2: return split_batched_nb<T, 2>(tab, order, first, count, max_nsplit, p, st);
+        case 3: return split_batched_nb<T, 3>(tab, order, first, count, max_nsplit, p, st);
+        case 4: return split_batched_nb<T, 4>(tab, order, first, count, max_nsplit, p, st);
+        case 5: return split_batched_nb<T, 5>(tab, order, first, count, max_nsplit, p, st);
+        case 6: return split_batched_nb<T, 6>(tab, order, first, count, max_nsplit, p, st);
+        case 7: return split_batched_nb<T, 7>(tab, order, first, count, max_nsplit, p, st);
+        case 8: return split_batched_nb<T, 8>(tab, order, first, count, max_nsplit, p, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t split_batched_launch(int working, const BatchMat *tab, const int *order, int first,
+                                int count, int max_nsplit, const SplitPlan &p, hipStream_t st) {
+    if (p.S < 1 || p.S > split_max_slices(working) || p.nb < 1 || p.nb > 8 || count < 1 ||
+        count > 65535 || max_nsplit < 1 || max_nsplit > 65535)
+        return hipErrorInvalidValue;
+    if (working == 1) return split_batched_t<double>(tab, order, first, count, max_nsplit, p, st);
+    return split_batched_t<float>(tab, order, first, count, max_nsplit, p, st);
+}
+
+hipError_t split_reduce_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st) {
+    if (batch < 1 || batch > 65535 || max_n < 1) return hipErrorInvalidValue;
+    const int nb = (max_n + 15) / 16;
+    const int64_t entries = (int64_t)(nb * (nb + 1) / 2) * 256;
+    hipLaunchKernelGGL(gram_split_reduce_batched_kernel,
+                       dim3((unsigned)((entries + 3) / 4), (unsigned)batch), dim3(256), 0, st, tab);
+    return hipGetLastError();
 }
 
 }  // namespace gsvd

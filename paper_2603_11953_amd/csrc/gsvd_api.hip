@@ -9,68 +9,22 @@
 #include <string.h>
 
 #include "gsvd.h"
+#include "api_util.hpp"
 #include "gsvd_internal.hpp"
 
+using namespace gsvd;
+
 namespace {
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-double unit_roundoff(int working) { return working == GSVD_F64 ? 0x1p-53 : 0x1p-24; }
-
-// Checks shared by every entry point that takes options.
-int check_opts(const gsvd_opts *o, int argpos) {
-    if (o == nullptr) return -argpos;
-    if (o->working != GSVD_F32 && o->working != GSVD_F64) return -argpos;
-    if (o->gram != GSVD_GRAM_AUTO && o->gram != GSVD_GRAM_PLAIN && o->gram != GSVD_GRAM_SPLIT)
-        return -argpos;
-    if (o->eig != GSVD_EIG_AUTO && o->eig != GSVD_EIG_JACOBI2 && o->eig != GSVD_EIG_CHOL_JACOBI1)
-        return -argpos;
-    if (o->max_sweeps < 0 || o->jacobi_tol < 0.0 || o->n_slices < 0) return -argpos;
-    return 0;
-}
-
-int check_supported(const gsvd_opts *o) {
-    if (o->gram == GSVD_GRAM_SPLIT &&
-        o->n_slices > (o->working == GSVD_F64 ? GSVD_MAX_SLICES : GSVD_MAX_SLICES_F32))
-        return GSVD_ERR_UNSUPPORTED;
-    if (o->eig == GSVD_EIG_JACOBI2) return GSVD_ERR_UNSUPPORTED;
-    return 0;
-}
-
-bool use_split(const gsvd_opts *o) { return o->gram == GSVD_GRAM_SPLIT; }
-
-int slices_of(const gsvd_opts *o) {
-    if (o->n_slices > 0) return o->n_slices;
-    return o->working == GSVD_F64 ? 10 : 6;
-}
-
-// workspace bytes for the partial sums of whichever Gram form o selects
-size_t gram_part_bytes(int64_t m, int64_t n, const gsvd_opts *o) {
-    if (use_split(o)) return gsvd::split_plan(m, n, slices_of(o)).part_bytes;
-    return gsvd::gram_plan(m, n).part_bytes;
-}
 
 hipError_t gram_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A, int64_t lda,
                     double *Mhi, double *Mlo, int64_t ldm, void *part, hipStream_t st) {
     if (use_split(o)) {
-        gsvd::SplitPlan p = gsvd::split_plan(m, n, slices_of(o));
-        return gsvd::split_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
+        SplitPlan p = split_plan_of(o, m, n, false);
+        return split_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
     }
-    gsvd::GramPlan p = gsvd::gram_plan(m, n);
-    return gsvd::gram_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
+    GramPlan p = gram_plan_of(o, m, n, false);
+    return gram_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
 }
-
-int check_eig_supported(const gsvd_opts *o, int64_t n) {
-    if (int e = check_supported(o)) return e;
-    if (o->working == GSVD_F64 && n > GSVD_MAX_N_EIG_F64) return GSVD_ERR_UNSUPPORTED;
-    return 0;
-}
-
-bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
-
-size_t wsize(int working) { return working == GSVD_F64 ? 8 : 4; }
 
 struct ThinLayout {
     size_t mhi, mlo, w, part, total;
@@ -87,7 +41,7 @@ ThinLayout thin_layout(int64_t m, int64_t n, const gsvd_opts *o) {
     L.w = off;
     off = align_up(off + nn * wsize(o->working));
     L.part = off;
-    off = align_up(off + gram_part_bytes(m, n, o));
+    off = align_up(off + gram_part_bytes(m, n, o, false));
     L.total = off;
     return L;
 }
@@ -106,6 +60,7 @@ void gsvd_opts_default(gsvd_opts *o, int working) {
     o->jacobi_tol = 0.0;
     o->max_sweeps = 0;
     o->flags = GSVD_WANT_U;
+    o->slab_rows = 0;
 }
 
 const char *gsvd_status_string(int code) {
@@ -124,7 +79,7 @@ const char *gsvd_status_string(int code) {
 
 size_t gsvd_gram_workspace_size(int64_t m, int64_t n, const gsvd_opts *o) {
     if (m < 1 || n < 1 || o == nullptr) return 0;
-    return align_up(gram_part_bytes(m, n, o));
+    return align_up(gram_part_bytes(m, n, o, false));
 }
 
 int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda, double *dMhi, double *dMlo,
@@ -168,9 +123,8 @@ int gsvd_eig(int64_t n, const double *dMhi, const double *dMlo, int64_t ldm, voi
     if (ldw < n) return -9;
     if (dInfo == nullptr) return -10;
     if (int e = check_eig_supported(o, n)) return e;
-    const double tol = o->jacobi_tol > 0 ? o->jacobi_tol
-                                         : __builtin_sqrt((double)n) * unit_roundoff(o->working);
-    const int sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    const double tol = jacobi_tol_of(o, n);
+    const int sweeps = sweeps_of(o);
     hipError_t err = gsvd::eig_launch(o->working, n, dMhi, dMlo, ldm, dS, dV, ldv, dW, ldw, dInfo,
                                       tol, sweeps, (hipStream_t)stream);
     return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
@@ -224,9 +178,8 @@ int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void 
     void *W = base + L.w;
     hipError_t err = gram_any(o, m, n, dA, lda, Mhi, Mlo, n, base + L.part, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
-    const double tol = o->jacobi_tol > 0 ? o->jacobi_tol
-                                         : __builtin_sqrt((double)n) * unit_roundoff(o->working);
-    const int sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    const double tol = jacobi_tol_of(o, n);
+    const int sweeps = sweeps_of(o);
     err = gsvd::eig_launch(o->working, n, Mhi, Mlo, n, dS, dV, ldv, W, n, dInfo, tol, sweeps, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (want_u) {

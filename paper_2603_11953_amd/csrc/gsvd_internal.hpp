@@ -11,6 +11,19 @@ namespace gsvd {
 constexpr int GSVD_KMAX_N = 128;      // largest n the kernels are sized for
 constexpr int GSVD_KMAX_N_F64 = 96;   // FP64 working: R and V (FP64) must share LDS
 
+// One problem of a batch as the batched kernels see it (device memory, written
+// by the batch set-up kernel).  Every pointer is a device address.
+struct BatchMat {
+    const void *A;
+    void *S, *V, *U;
+    void *W;                 // fl(V Sigma^-1), n x n, ld = n, working precision
+    double *Mhi, *Mlo;       // Gram planes, n x n, ld = n
+    double *part;            // Gram partial sums of the slabs
+    int *info;
+    int64_t m, lda, ldu, rows_per_split;
+    int n, ldv, nsplit, pad;
+};
+
 // Launch geometry of the split-m Gram (gram.hip).
 struct GramPlan {
     int nb;                  // ceil(n / 4): 4x4 blocks per side
@@ -24,10 +37,18 @@ struct GramPlan {
     size_t part_bytes;       // workspace for the per-slab partial sums
 };
 
-GramPlan gram_plan(int64_t m, int64_t n);
+// slab_rows > 0 fixes the slab height (rounded up to a whole number of chunks);
+// 0 picks about 512 slabs.
+GramPlan gram_plan(int64_t m, int64_t n, int64_t slab_rows = 0);
 hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                        double *Mhi, double *Mlo, int64_t ldm, void *part, const GramPlan &p,
                        hipStream_t st);
+// Batched: the problems order[first .. first + count) share n (hence the plan's
+// nb, nblk, ks, kc, threads); grid.y covers max_nsplit slabs.  The reduction
+// launch covers every problem of the batch (up to max_n).
+hipError_t gram_batched_launch(int working, const BatchMat *tab, const int *order, int first,
+                               int count, int max_nsplit, const GramPlan &p, hipStream_t st);
+hipError_t gram_reduce_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st);
 
 // Launch geometry of the operand-split Gram (gram_split.hip).
 struct SplitPlan {
@@ -40,11 +61,18 @@ struct SplitPlan {
     size_t part_bytes;
 };
 
-SplitPlan split_plan(int64_t m, int64_t n, int S);
+// slab_rows > 0 fixes the slab height (rounded up to a multiple of 64); 0 picks
+// about 1024 slabs.
+SplitPlan split_plan(int64_t m, int64_t n, int S, int64_t slab_rows = 0);
 int split_max_slices(int working);
 hipError_t split_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                         double *Mhi, double *Mlo, int64_t ldm, void *part, const SplitPlan &p,
                         hipStream_t st);
+// Batched: the problems order[first .. first + count) share ceil(n / 16) = p.nb
+// and the slice count p.S.
+hipError_t split_batched_launch(int working, const BatchMat *tab, const int *order, int first,
+                                int count, int max_nsplit, const SplitPlan &p, hipStream_t st);
+hipError_t split_reduce_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st);
 
 // Eigensolver stage (eig.hip).
 size_t eig_lds_bytes(int working, int64_t n);
@@ -53,9 +81,17 @@ int eig_threads(int64_t n);
 hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *Mlo, int64_t ldm,
                       void *S, void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
                       int max_sweeps, hipStream_t st);
+// Batched: one workgroup per problem, problems taken in the order given
+// (order[batch - 1 - block]); tol = 0 means sqrt(n) u per problem.
+hipError_t eig_batched_launch(int working, const BatchMat *tab, const int *order, int batch,
+                              int max_n, double tol, int max_sweeps, hipStream_t st);
 
 // U = A W (urecover.hip).
 hipError_t urecover_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                            const void *W, int64_t ldw, void *U, int64_t ldu, hipStream_t st);
+// Batched: the problems order[first .. first + count) share nt = ceil(n / 16).
+hipError_t urecover_batched_launch(int working, const BatchMat *tab, const int *order, int first,
+                                   int count, int nt, int64_t max_m, hipStream_t st);
+int urecover_batched_max_nt(int working);
 
 }  // namespace gsvd

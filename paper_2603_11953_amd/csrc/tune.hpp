@@ -1,0 +1,28 @@
+// Launch-shape and slice-count tuning table: lookups (tune.hip) over the rows
+// that paper_2603_11953_amd/autotune.py measured and wrote to tune_table.inc.
+#pragma once
+
+#include <stdint.h>
+
+namespace gsvd {
+
+struct TuneSlab {
+    int working;       // GSVD_F32 / GSVD_F64
+    int gram;          // GSVD_GRAM_PLAIN / GSVD_GRAM_SPLIT
+    int batched;       // 0: one problem per call, 1: the batched entry point
+    int n_max;         // row applies to n <= n_max ...
+    int64_t m_max;     // ... and m <= m_max (first matching row wins)
+    int64_t slab_rows; // rows of A per Gram workgroup
+};
+
+struct TuneSlices {
+    int working;
+    int n_max;
+    int slices;        // split Gram slice count
+};
+
+// 0 when no row matches: the plan then uses its own default slab count
+int64_t tune_slab_rows(int working, int gram, int64_t n, int64_t m, bool batched);
+int tune_slices(int working, int64_t n);
+
+}  // namespace gsvd

@@ -109,10 +109,13 @@ urecover_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__ W, i
 constexpr int UT_BM = 64;       // rows per tile
 constexpr int UT_THREADS = 256;
 
+// Row tiles tile0, tile0 + stride, ... of one product U = A W.
 template <typename T, int NT>
-__global__ void __launch_bounds__(UT_THREADS)
-urecover_tile_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__ W, int64_t ldw,
-                     T *__restrict__ U, int64_t ldu, int64_t m, int n, int64_t ntiles) {
+__device__ __forceinline__ void urecover_tile_body(const T *__restrict__ A, int64_t lda,
+                                                   const T *__restrict__ W, int64_t ldw,
+                                                   T *__restrict__ U, int64_t ldu, int64_t m,
+                                                   int n, int64_t ntiles, int64_t tile0,
+                                                   int64_t stride) {
     typedef typename Mfma<T>::acc_t acc_t;
     constexpr int NTC = NT * 16;
     constexpr int LDA_S = UT_BM + 2;          // padded column stride of the A tile
@@ -144,9 +147,9 @@ urecover_tile_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__
         }
     };
 
-    int64_t tile = blockIdx.x;
+    int64_t tile = tile0;
     if (tile < ntiles) fetch(tile);
-    for (; tile < ntiles; tile += gridDim.x) {
+    for (; tile < ntiles; tile += stride) {
         __syncthreads();  // previous tile fully consumed (and W staged, first time)
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -154,7 +157,7 @@ urecover_tile_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__
             As[(e / UT_BM) * LDA_S + (e % UT_BM)] = stage[q];
         }
         __syncthreads();
-        const int64_t next = tile + gridDim.x;
+        const int64_t next = tile + stride;
         if (next < ntiles) fetch(next);
         const int64_t r0 = tile * UT_BM;
         for (int item = wave; item < 4 * NT; item += 4) {
@@ -177,6 +180,27 @@ urecover_tile_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__
             }
         }
     }
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(UT_THREADS)
+urecover_tile_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__ W, int64_t ldw,
+                     T *__restrict__ U, int64_t ldu, int64_t m, int n, int64_t ntiles) {
+    urecover_tile_body<T, NT>(A, lda, W, ldw, U, ldu, m, n, ntiles, blockIdx.x, gridDim.x);
+}
+
+// Batched: blockIdx.z picks the problem order[first + z]; its row tiles are
+// dealt to the gridDim.x workgroups of that problem.
+template <typename T, int NT>
+__global__ void __launch_bounds__(UT_THREADS)
+urecover_tile_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order,
+                             int first) {
+    const BatchMat &d = tab[order[first + blockIdx.z]];
+    const int64_t ntiles = (d.m + UT_BM - 1) / UT_BM;
+    if ((int64_t)blockIdx.x >= ntiles) return;
+    urecover_tile_body<T, NT>(reinterpret_cast<const T *>(d.A), d.lda,
+                              reinterpret_cast<const T *>(d.W), d.n, reinterpret_cast<T *>(d.U),
+                              d.ldu, d.m, d.n, ntiles, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int NT>
@@ -254,6 +278,51 @@ hipError_t urecover_launch(int working, int64_t m, int64_t n, const void *A, int
         return launch_t<double>(m, n, (const double *)A, lda, (const double *)W, ldw, (double *)U,
                                 ldu, st);
     return launch_t<float>(m, n, (const float *)A, lda, (const float *)W, ldw, (float *)U, ldu, st);
+}
+
+int urecover_batched_max_nt(int working) { return working == 1 ? 6 : 8; }
+
+template <typename T, int NT>
+static hipError_t batched_tile(const BatchMat *tab, const int *order, int first, int count,
+                               int64_t max_m, hipStream_t st) {
+    const size_t lds = tile_lds<T, NT>();
+    // about eight row tiles per workgroup for the tallest problem of the group
+    int64_t gx = ((max_m + UT_BM - 1) / UT_BM + 7) / 8;
+    if (gx < 1) gx = 1;
+    if (gx > 65535) gx = 65535;
+    auto k = urecover_tile_batched_kernel<T, NT>;
+    hipError_t err = hipFuncSetAttribute((const void *)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k, dim3((unsigned)gx, 1, (unsigned)count), dim3(UT_THREADS), lds, st, tab,
+                       order, first);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t batched_t(const BatchMat *tab, const int *order, int first, int count, int nt,
+                            int64_t max_m, hipStream_t st) {
+    switch (nt) {
+        case 1: return batched_tile<T, 1>(tab, order, first, count, max_m, st);
+        case 2: return batched_tile<T, 2>(tab, order, first, count, max_m, st);
+        case 3: return batched_tile<T, 3>(tab, order, first, count, max_m, st);
+        case 4: return batched_tile<T, 4>(tab, order, first, count, max_m, st);
+        case 5: return batched_tile<T, 5>(tab, order, first, count, max_m, st);
+        case 6: return batched_tile<T, 6>(tab, order, first, count, max_m, st);
+        case 7: if (sizeof(T) == 4) return batched_tile<T, 7>(tab, order, first, count, max_m, st);
+                return hipErrorInvalidValue;
+        case 8: if (sizeof(T) == 4) return batched_tile<T, 8>(tab, order, first, count, max_m, st);
+                return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t urecover_batched_launch(int working, const BatchMat *tab, const int *order, int first,
+                                   int count, int nt, int64_t max_m, hipStream_t st) {
+    if (count < 1 || count > 65535 || nt < 1 || nt > urecover_batched_max_nt(working))
+        return hipErrorInvalidValue;
+    if (working == 1) return batched_t<double>(tab, order, first, count, nt, max_m, st);
+    return batched_t<float>(tab, order, first, count, nt, max_m, st);
 }
 
 }  // namespace gsvd

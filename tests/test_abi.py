@@ -125,3 +125,64 @@ def test_fp64_eigensolver_limit():
     rc = gs.gsvd_thin(1000, 97, FAKE, 1000, FAKE, FAKE, 97, FAKE, 1000, FAKE, 1 << 40, FAKE,
                       ctypes.byref(o), None)
     assert rc == -101
+
+
+def _batch_call(batch=3, M=(1000, 2000, 500), N=(16, 64, 8), lda=None, ldv=None, ldu=None,
+                work_bytes=1 << 40, null=(), o=None, working=gs.GSVD_F64):
+    i64 = ctypes.c_int64 * max(len(M), 1)
+    hM, hN = i64(*M), i64(*N)
+    hLda = i64(*(lda or M))
+    hLdv = i64(*(ldv or N))
+    hLdu = i64(*(ldu or M))
+    o = o or gs.opts(working)
+    args = dict(dA=FAKE, dS=FAKE, dV=FAKE, dU=FAKE, work=FAKE, dInfo=FAKE, hM=hM, hN=hN,
+                hLda=hLda, hLdv=hLdv, hLdu=hLdu)
+    for k in null:
+        args[k] = None
+    return gs.gsvd_thin_batched(batch, args["hM"], args["hN"], args["dA"], args["hLda"],
+                                args["dS"], args["dV"], args["hLdv"], args["dU"], args["hLdu"],
+                                args["work"], work_bytes, args["dInfo"], ctypes.byref(o), None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(batch=0), -1),
+    (dict(null=("hM",)), -2),
+    (dict(null=("hN",)), -3),
+    (dict(null=("dA",)), -4),
+    (dict(null=("hLda",)), -5),
+    (dict(null=("dS",)), -6),
+    (dict(null=("dV",)), -7),
+    (dict(null=("hLdv",)), -8),
+    (dict(null=("dU",)), -9),
+    (dict(null=("hLdu",)), -10),
+    (dict(null=("work",)), -11),
+    (dict(work_bytes=0), -12),
+    (dict(null=("dInfo",)), -13),
+    (dict(M=(1000, 10, 500)), -2),          # m < n
+    (dict(N=(16, 0, 8)), -3),
+    (dict(N=(16, 97, 8)), -3),              # FP64 eigensolver limit
+    (dict(lda=(1000, 1999, 500)), -5),
+    (dict(ldv=(16, 63, 8)), -8),
+    (dict(ldu=(999, 2000, 500)), -10),
+])
+def test_batched_argument_errors(kw, code):
+    assert _batch_call(**kw) == code
+
+
+def test_batched_workspace_and_unsupported():
+    i64 = ctypes.c_int64 * 3
+    hM, hN = i64(1000, 2000, 500), i64(16, 64, 8)
+    for w in (gs.GSVD_F32, gs.GSVD_F64):
+        for g in (gs.GSVD_GRAM_PLAIN, gs.GSVD_GRAM_SPLIT):
+            o = gs.opts(w, g)
+            t = gs.gsvd_thin_batched_workspace_size(3, hM, hN, ctypes.byref(o))
+            assert t > 0 and t % 256 == 0
+    o = gs.opts(gs.GSVD_F64)
+    assert gs.gsvd_thin_batched_workspace_size(3, hM, i64(16, 97, 8), ctypes.byref(o)) == 0
+    assert gs.gsvd_thin_batched_workspace_size(0, hM, hN, ctypes.byref(o)) == 0
+    # FP32 working allows n up to 128 in a batch
+    o32 = gs.opts(gs.GSVD_F32)
+    assert gs.gsvd_thin_batched_workspace_size(3, i64(1000, 2000, 500), i64(16, 128, 8),
+                                               ctypes.byref(o32)) > 0
+    assert _batch_call(o=gs.opts(gs.GSVD_F64, gs.GSVD_GRAM_SPLIT, n_slices=13)) == -101
+    assert _batch_call(o=gs.opts(gs.GSVD_F64, eig=gs.GSVD_EIG_JACOBI2)) == -101
