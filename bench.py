@@ -15,6 +15,9 @@ shuffled; plain form (double-double Gram).  Prints one JSON line.
 
 Accuracy is checked against the oracle after the timed region; the result
 records whether the paper's tolerances were met.
+
+    batched      = 512 FP64 problems of uneven shape through gsvd_thin_batched
+                   (eager and graph-replayed) vs 512 gsvd_thin calls
 """
 from __future__ import annotations
 
@@ -45,6 +48,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-rows", type=int, default=1_000_000,
                     help="rows of A the CPU oracle processes for the baseline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched leg (512 FP64 problems of uneven shape)")
+    ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB buffer 3 times (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -88,6 +94,104 @@ def measured_traffic(m: int, n: int):
     if t.get("kernel_source_hash") != kernel_source_hash() or t.get("m") != m or t.get("n") != n:
         return None
     return t.get("bytes_per_launch")
+
+
+def batched_leg(args, torch, gs, g, log_fn):
+    """The batched workload: 512 FP64 problems A = B D, m ~ U[1e4, 2e5], n from
+    {16, 32, 48, 64, 96}, kappa(B) log-U[10, 1e3], kappa(D) log-U[1e4, 1e12].  One
+    gsvd_thin_batched call (eager and replayed from a captured HIP graph) against the
+    same 512 problems through 512 gsvd_thin calls on the same stream."""
+    import ctypes
+    from concurrent.futures import ThreadPoolExecutor
+
+    specs = g.batch_specs()
+    t0 = time.time()
+    with ThreadPoolExecutor(16) as ex:
+        As = list(ex.map(g.make_a, specs))
+    log_fn(f"batched: generated {len(As)} problems ({sum(A.nbytes for A in As) / 1e9:.1f} GB) "
+           f"in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    dAs = [torch.from_numpy(np.ascontiguousarray(A.T)).to(dev).t() for A in As]
+    flops = sum(A.shape[0] * A.shape[1] * (A.shape[1] + 1) + 2 * A.shape[0] * A.shape[1] ** 2
+                for A in As)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(int(stream.cuda_stream))
+
+    def timed(fn, k, w_):
+        for _ in range(w_):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    out = {"problems": len(As), "flop": flops}
+    sample = sorted(set([0, 1, 2] + [int(np.argmax([A.shape[1] * 1e7 + A.shape[0] for A in As]))]))
+    from oracle import ref
+    for form, gram in (("plain", gs.GSVD_GRAM_PLAIN), ("split", gs.GSVD_GRAM_SPLIT)):
+        b = gs.Batch(dAs, gram=gram)
+        ms_b = timed(lambda: b.run(stream), args.batched_steps, 1)
+        graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(stream)
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(graph, stream=s):
+                b.run(s)
+        stream.wait_stream(s)
+        torch.cuda.synchronize()
+        ms_g = timed(graph.replay, args.batched_steps, 1)
+        o = gs.opts(gs.GSVD_F64, gram)
+        ob = ctypes.byref(o)
+        wsz = max(gs.gsvd_thin_workspace_size(A.shape[0], A.shape[1], ob) for A in As)
+        work = gs.workspace(wsz, dev)
+        info1 = torch.zeros(len(As), dtype=torch.int32, device=dev)
+
+        def seq():
+            for k, A in enumerate(dAs):
+                m, n = A.shape
+                rc = gs.gsvd_thin(m, n, A.data_ptr(), m, b.S[k].data_ptr(), b.V[k].data_ptr(), n,
+                                  b.U[k].data_ptr(), m, work.data_ptr(), work.numel(),
+                                  info1[k:].data_ptr(), ob, sp)
+                if rc != 0:
+                    raise RuntimeError(f"gsvd_thin {rc}")
+
+        ms_s = timed(seq, max(1, args.batched_steps // 2), 1)
+        # accuracy of the batched call on a sample of problems
+        b.run(stream)
+        torch.cuda.synchronize()
+        info = b.info.cpu().numpy()
+        errs, orths, tols = [], [], []
+        for k in sample:
+            A = As[k]
+            orc = ref.svd(A)
+            S = b.S[k].cpu().numpy()
+            U = np.asfortranarray(b.U[k].t().contiguous().cpu().numpy().T)
+            errs.append(float(ref.sigma_rel_err(S, orc).max()))
+            orths.append(ref.orth(U))
+            tols.append(50 * A.shape[1] * 2.0 ** -53 * orc.kappa_b)
+        ok = bool(np.all(info == 0) and all(e <= t for e, t in zip(errs, tols)))
+        out[form] = {
+            "ms_batched": round(ms_b, 4), "ms_graph_replay": round(ms_g, 4),
+            "ms_sequential_512_calls": round(ms_s, 4),
+            "value_batched_gflops": round(flops / (min(ms_b, ms_g) * 1e-3) / 1e9, 2),
+            "speedup_vs_sequential": round(ms_s / min(ms_b, ms_g), 3),
+            "info_all_zero": bool(np.all(info == 0)),
+            "sample": {"problems": sample, "sigma_max_rel_err": errs, "sigma_tol": tols,
+                       "u_orth": orths}, "meets_tol": ok,
+        }
+        log_fn(f"batched {form}: {ms_b:.3f} ms eager, {ms_g:.3f} ms graph, sequential {ms_s:.3f} "
+               f"ms; sample ok={ok}")
+        del b, graph, work
+        torch.cuda.synchronize()
+    out["split_speedup_vs_plain"] = round(
+        min(out["plain"]["ms_batched"], out["plain"]["ms_graph_replay"]) /
+        min(out["split"]["ms_batched"], out["split"]["ms_graph_replay"]), 3)
+    return out
 
 
 def main():
@@ -252,6 +356,9 @@ def main():
             "work_per_launch": f"{alu_ops} FP64 VALU ops = 10 per dd-MAC x m n (n+1)/2 dd-MACs",
         },
     }
+
+    if not args.no_batched:
+        result["batched"] = batched_leg(args, torch, gs, g, log)
 
     if not args.no_check:
         from oracle import ref
