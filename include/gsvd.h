@@ -56,10 +56,14 @@ enum {
 
 /* eigensolver of Alg. 1 step 3 */
 enum {
-    GSVD_EIG_AUTO = 0,       /* library choice (currently CHOL_JACOBI1) */
-    GSVD_EIG_JACOBI2 = 1,    /* two-sided Jacobi on M_h (Sec. 2.1, Remark 1); reserved */
+    GSVD_EIG_AUTO = 0,       /* JACOBI2 for FP32 working, CHOL_JACOBI1 for FP64 working */
+    GSVD_EIG_JACOBI2 = 1,    /* two-sided Jacobi on M_h at u_h (Sec. 2.1, Remark 1): FP32
+                                working only (M_h and the rotations in FP64); default
+                                threshold n * 2^-53; V needs gsvd_eig_workspace_size
+                                bytes of scratch when n > 96 */
     GSVD_EIG_CHOL_JACOBI1 = 2 /* Algorithm 2: Cholesky of M_h at u_h, R cast to u,
-                                 one-sided Jacobi SVD of R (Thm. 2, Lemma 1) */
+                                 one-sided Jacobi SVD of R (Thm. 2, Lemma 1); default
+                                 threshold sqrt(n) * u */
 };
 
 /* flags */
@@ -89,7 +93,7 @@ typedef struct {
     int n_slices;       /* split Gram only: 1..GSVD_MAX_SLICES (FP64 A) or
                            1..GSVD_MAX_SLICES_F32 (FP32 A); 0 = 10 (FP64), 6 (FP32) */
     double jacobi_tol;  /* rotation threshold: a pair p, q is rotated when
-                           |g_pq| > tol * sqrt(g_pp g_qq); 0 = sqrt(n) * u */
+                           |g_pq| > tol * sqrt(g_pp g_qq); 0 = the eigensolver's default */
     int max_sweeps;     /* 0 = 30 */
     unsigned flags;     /* GSVD_WANT_U ... */
     int64_t slab_rows;  /* rows of A per Gram workgroup ("slab"); 0 = the library's tuning
@@ -143,6 +147,8 @@ int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda,
  * for FP32 working) compute S (n, descending, working precision), V (n x n,
  * ldv >= n, working precision) and W = fl(V diag(S)^{-1}) (n x n, ldw >= n,
  * working precision, the matrix that Alg. 1 step 6 multiplies A by), and *dInfo.
+ * work: gsvd_eig_workspace_size(n, o) bytes (0 except for JACOBI2 with n > 96;
+ * may then be NULL).
  * Arguments: 1 n, 2 dMhi, 3 dMlo, 4 ldm, 5 dS, 6 dV, 7 ldv, 8 dW, 9 ldw,
  * 10 dInfo, 11 work, 12 work_bytes, 13 o, 14 stream.
  */

@@ -211,19 +211,23 @@ def gram(A, *, work=None, stream=None):
     return Mhi, Mlo
 
 
-def eig(Mhi, Mlo, working: int, *, jacobi_tol: float = 0.0, max_sweeps: int = 0, stream=None):
+def eig(Mhi, Mlo, working: int, *, eig: int = GSVD_EIG_AUTO, jacobi_tol: float = 0.0,
+        max_sweeps: int = 0, stream=None):
     """Eigensolver stage on a device Gram: returns (S, V, W, info) in the working precision."""
     torch = _torch()
     n = int(Mhi.shape[0])
     dt = torch.float64 if working == GSVD_F64 else torch.float32
-    o = opts(working, GSVD_GRAM_PLAIN, GSVD_EIG_AUTO, jacobi_tol=jacobi_tol, max_sweeps=max_sweeps)
+    o = opts(working, GSVD_GRAM_PLAIN, eig, jacobi_tol=jacobi_tol, max_sweeps=max_sweeps)
     S = torch.empty(n, dtype=dt, device=Mhi.device)
     V = colmajor_empty(n, n, dt, Mhi.device)
     W = colmajor_empty(n, n, dt, Mhi.device)
     info = torch.full((1,), -1, dtype=torch.int32, device=Mhi.device)
+    need = lib.gsvd_eig_workspace_size(n, ctypes.byref(o))
+    work = workspace(need, Mhi.device) if need > 0 else None
     rc = lib.gsvd_eig(n, Mhi.data_ptr(), Mlo.data_ptr() if Mlo is not None else None, _ld(Mhi),
-                      S.data_ptr(), V.data_ptr(), n, W.data_ptr(), n, info.data_ptr(), None, 0,
-                      ctypes.byref(o), _stream(stream))
+                      S.data_ptr(), V.data_ptr(), n, W.data_ptr(), n, info.data_ptr(),
+                      work.data_ptr() if work is not None else None,
+                      work.numel() if work is not None else 0, ctypes.byref(o), _stream(stream))
     _check(rc, "gsvd_eig")
     return S, V, W, info
 

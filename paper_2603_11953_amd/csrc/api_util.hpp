@@ -39,10 +39,18 @@ inline int max_slices(int working) {
     return working == GSVD_F64 ? GSVD_MAX_SLICES : GSVD_MAX_SLICES_F32;
 }
 
+// The eigensolver in force: AUTO is the two-sided Jacobi for FP32 working
+// (M_h in FP64) and Algorithm 2 for FP64 working (M_h in double-double).
+inline int eig_mode_of(const gsvd_opts *o) {
+    if (o->eig != GSVD_EIG_AUTO) return o->eig;
+    return o->working == GSVD_F32 ? GSVD_EIG_JACOBI2 : GSVD_EIG_CHOL_JACOBI1;
+}
+
 inline int check_supported(const gsvd_opts *o) {
     if (o->gram == GSVD_GRAM_SPLIT && o->n_slices > max_slices(o->working))
         return GSVD_ERR_UNSUPPORTED;
-    if (o->eig == GSVD_EIG_JACOBI2) return GSVD_ERR_UNSUPPORTED;
+    // the two-sided Jacobi runs in FP64: it is the u_h solver of FP32 working only
+    if (eig_mode_of(o) == GSVD_EIG_JACOBI2 && o->working != GSVD_F32) return GSVD_ERR_UNSUPPORTED;
     return 0;
 }
 
@@ -82,8 +90,27 @@ inline size_t gram_part_bytes(int64_t m, int64_t n, const gsvd_opts *o, bool bat
     return gram_plan_of(o, m, n, batched).part_bytes;
 }
 
+// default rotation threshold: n u_h for the two-sided Jacobi on M_h (FP64),
+// sqrt(n) u_w for the one-sided Jacobi on R in Algorithm 2
 inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
-    return o->jacobi_tol > 0 ? o->jacobi_tol : __builtin_sqrt((double)n) * unit_roundoff(o->working);
+    if (o->jacobi_tol > 0) return o->jacobi_tol;
+    if (eig_mode_of(o) == GSVD_EIG_JACOBI2) return (double)n * 0x1p-53;
+    return __builtin_sqrt((double)n) * unit_roundoff(o->working);
+}
+
+inline size_t eig_work_bytes(const gsvd_opts *o, int64_t n) {
+    return eig_mode_of(o) == GSVD_EIG_JACOBI2 ? j2_work_bytes(n) : 0;
+}
+
+inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, const double *Mlo,
+                          int64_t ldm, void *S, void *V, int64_t ldv, void *W, int64_t ldw,
+                          int *info, void *work, hipStream_t st) {
+    const double tol = jacobi_tol_of(o, n);
+    const int sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    if (eig_mode_of(o) == GSVD_EIG_JACOBI2)
+        return eig_jacobi2_launch(o->working, n, Mhi, ldm, S, V, ldv, W, ldw, info, tol, sweeps,
+                                  work, st);
+    return eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps, st);
 }
 
 inline int sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 30; }

@@ -239,8 +239,11 @@ int gsvd_thin_batched(int batch, const int64_t *hM, const int64_t *hN, const voi
     err = use_split(o) ? split_reduce_batched_launch(tab, batch, P.max_n, st)
                        : gram_reduce_batched_launch(tab, batch, P.max_n, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
-    err = eig_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol, sweeps_of(o),
-                             st);
+    err = eig_mode_of(o) == GSVD_EIG_JACOBI2
+              ? eig_jacobi2_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol,
+                                           sweeps_of(o), st)
+              : eig_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol,
+                                   sweeps_of(o), st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (want_u) {
         for (const UClass &c : P.u) {

@@ -27,7 +27,7 @@ hipError_t gram_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A, int
 }
 
 struct ThinLayout {
-    size_t mhi, mlo, w, part, total;
+    size_t mhi, mlo, w, eigw, part, total;
 };
 
 ThinLayout thin_layout(int64_t m, int64_t n, const gsvd_opts *o) {
@@ -40,6 +40,8 @@ ThinLayout thin_layout(int64_t m, int64_t n, const gsvd_opts *o) {
     off = align_up(off + nn * sizeof(double));
     L.w = off;
     off = align_up(off + nn * wsize(o->working));
+    L.eigw = off;
+    off = align_up(off + eig_work_bytes(o, n));
     L.part = off;
     off = align_up(off + gram_part_bytes(m, n, o, false));
     L.total = off;
@@ -101,16 +103,13 @@ int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda, double *dMhi, d
 }
 
 size_t gsvd_eig_workspace_size(int64_t n, const gsvd_opts *o) {
-    (void)n;
-    (void)o;
-    return 0;
+    if (n < 1 || o == nullptr) return 0;
+    return align_up(eig_work_bytes(o, n));
 }
 
 int gsvd_eig(int64_t n, const double *dMhi, const double *dMlo, int64_t ldm, void *dS, void *dV,
              int64_t ldv, void *dW, int64_t ldw, int *dInfo, void *work, size_t work_bytes,
              const gsvd_opts *o, void *stream) {
-    (void)work;
-    (void)work_bytes;
     if (n < 1 || n > GSVD_MAX_N) return -1;
     if (dMhi == nullptr) return -2;
     if (int e = check_opts(o, 13)) return e;
@@ -122,11 +121,12 @@ int gsvd_eig(int64_t n, const double *dMhi, const double *dMlo, int64_t ldm, voi
     if (dW == nullptr) return -8;
     if (ldw < n) return -9;
     if (dInfo == nullptr) return -10;
+    const size_t need = eig_work_bytes(o, n);
+    if (need > 0 && (work == nullptr || !aligned(work, kAlign))) return -11;
+    if (work_bytes < need) return -12;
     if (int e = check_eig_supported(o, n)) return e;
-    const double tol = jacobi_tol_of(o, n);
-    const int sweeps = sweeps_of(o);
-    hipError_t err = gsvd::eig_launch(o->working, n, dMhi, dMlo, ldm, dS, dV, ldv, dW, ldw, dInfo,
-                                      tol, sweeps, (hipStream_t)stream);
+    hipError_t err = eig_any(o, n, dMhi, dMlo, ldm, dS, dV, ldv, dW, ldw, dInfo, work,
+                             (hipStream_t)stream);
     return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
 }
 
@@ -178,9 +178,7 @@ int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void 
     void *W = base + L.w;
     hipError_t err = gram_any(o, m, n, dA, lda, Mhi, Mlo, n, base + L.part, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
-    const double tol = jacobi_tol_of(o, n);
-    const int sweeps = sweeps_of(o);
-    err = gsvd::eig_launch(o->working, n, Mhi, Mlo, n, dS, dV, ldv, W, n, dInfo, tol, sweeps, st);
+    err = eig_any(o, n, Mhi, Mlo, n, dS, dV, ldv, W, n, dInfo, base + L.eigw, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (want_u) {
         err = gsvd::urecover_launch(o->working, m, n, dA, lda, W, n, dU, ldu, st);

@@ -86,6 +86,17 @@ hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *M
 hipError_t eig_batched_launch(int working, const BatchMat *tab, const int *order, int batch,
                               int max_n, double tol, int max_sweeps, hipStream_t st);
 
+// Two-sided Jacobi eigensolver for FP32 working (eig_jacobi2.hip).  V needs
+// j2_work_bytes(n) of device scratch (0 while it fits LDS, n <= 96).
+size_t j2_work_bytes(int64_t n);
+hipError_t eig_jacobi2_launch(int working, int64_t n, const double *Mhi, int64_t ldm, void *S,
+                              void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
+                              int max_sweeps, void *work, hipStream_t st);
+// Batched: for max_n > 96 each problem's V scratch is its (then unused) Gram
+// partial-sum area, which always holds at least n^2 doubles.
+hipError_t eig_jacobi2_batched_launch(int working, const BatchMat *tab, const int *order, int batch,
+                                      int max_n, double tol, int max_sweeps, hipStream_t st);
+
 // U = A W (urecover.hip).
 hipError_t urecover_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                            const void *W, int64_t ldw, void *U, int64_t ldu, hipStream_t st);

@@ -73,24 +73,31 @@ def test_gram_deterministic_and_power_of_two_equivariant():
 
 # ------------------------------------------------------------------ eigensolver stage
 
-EIG_CASES = [(1, "f64"), (2, "f64"), (7, "f64"), (20, "f64"), (64, "f64"), (65, "f64"), (96, "f64"),
-             (1, "f32"), (20, "f32"), (64, "f32"), (97, "f32"), (128, "f32")]
+EIG_CASES = [(1, "f64", "alg2"), (2, "f64", "alg2"), (7, "f64", "alg2"), (20, "f64", "alg2"),
+             (64, "f64", "alg2"), (65, "f64", "alg2"), (96, "f64", "alg2"),
+             (1, "f32", "alg2"), (20, "f32", "alg2"), (64, "f32", "alg2"), (97, "f32", "alg2"),
+             (128, "f32", "alg2"),
+             (1, "f32", "jacobi2"), (2, "f32", "jacobi2"), (7, "f32", "jacobi2"),
+             (20, "f32", "jacobi2"), (64, "f32", "jacobi2"), (96, "f32", "jacobi2"),
+             (97, "f32", "jacobi2"), (128, "f32", "jacobi2")]
 
 
-@pytest.mark.parametrize("n,dt", EIG_CASES)
-def test_eig_parity(n, dt):
-    """Alg. 2 on the oracle's M_h: sigma within 50 n u kappa(B); V orthogonal and
-    matching the oracle's eigenvectors; W == fl(V / S) bitwise."""
+@pytest.mark.parametrize("n,dt,mode", EIG_CASES)
+def test_eig_parity(n, dt, mode):
+    """Eigensolver stage on the oracle's M_h (Alg. 2, or the two-sided Jacobi on M_h):
+    sigma within 50 n u kappa(B); V orthogonal and matching the oracle's eigenvectors;
+    W == fl(V / S) bitwise."""
     import paper_2603_11953_amd as gs
     torch = _torch()
     A = g.make_a(g.MatrixSpec(m=4 * n + 50, n=n, kappa_b=100, kappa_d=1e8, mode_b=3, mode_d=3,
                               seed=200 + n, dtype=dt, shuffle=True))
     o = ref.svd(A)
     w = gs.GSVD_F64 if dt == "f64" else gs.GSVD_F32
-    say("eig", n, dt)
+    say("eig", n, dt, mode)
     Mh = to_dev(o.M_hi)
     Ml = to_dev(o.M_lo) if dt == "f64" else None
-    S, V, W, info = gs.eig(Mh, Ml, w)
+    em = gs.GSVD_EIG_JACOBI2 if mode == "jacobi2" else gs.GSVD_EIG_CHOL_JACOBI1
+    S, V, W, info = gs.eig(Mh, Ml, w, eig=em)
     _sync()
     assert int(info.item()) == 0
     S, V, W = to_np(S), to_np(V), to_np(W)
@@ -244,3 +251,37 @@ def test_info_no_convergence():
     A = g.make_a(g.MatrixSpec(m=500, n=30, kappa_b=100, kappa_d=10, seed=9))
     say("info max_sweeps=1")
     assert _thin(A, max_sweeps=1)[3] == 2
+    A32 = g.make_a(g.MatrixSpec(m=500, n=30, kappa_b=100, kappa_d=10, seed=9, dtype="f32"))
+    assert _thin(A32, max_sweeps=1)[3] == 2  # the two-sided Jacobi (FP32 default)
+
+
+@pytest.mark.parametrize("bad", [np.nan, 0.0])
+def test_info_codes_two_sided_jacobi(bad):
+    A = g.make_a(g.MatrixSpec(m=500, n=10, kappa_b=10, kappa_d=10, seed=9, dtype="f32"))
+    if bad == 0.0:
+        A[:, 4] = 0.0
+    else:
+        A[123, 6] = bad
+    say("info jacobi2", bad)
+    assert _thin(np.asfortranarray(A))[3] == (1 if bad == 0.0 else 3)
+
+
+def test_two_sided_jacobi_is_O_u_while_alg2_tracks_kappa_b():
+    """Sec. 4.1.1 / Remark 1 vs Remark 2, FP32 working at kappa(B) = 1e4: the two-sided Jacobi
+    on M_h (u_h = 2^-53, u_h kappa(B)^2 << u) keeps sigma at O(u), while Algorithm 2 is only
+    bounded by O(u) kappa(B); each within its own bound, and the two-sided one more accurate."""
+    import paper_2603_11953_amd as gs
+    errs = {"jacobi2": [], "alg2": []}
+    for seed in range(4):
+        A = g.make_a(g.MatrixSpec(m=2048, n=64, kappa_b=1e4, kappa_d=1e6, mode_b=3, mode_d=5,
+                                  seed=900 + seed, dtype="f32", shuffle=True))
+        o = ref.svd(A)
+        for mode, em in (("jacobi2", gs.GSVD_EIG_JACOBI2), ("alg2", gs.GSVD_EIG_CHOL_JACOBI1)):
+            say("accuracy mode", mode, seed)
+            S, V, Uo, info = _thin(A, eig=em)
+            assert info == 0
+            errs[mode].append(float(ref.sigma_rel_err(S.astype(np.float64), o).max()))
+    u = 2.0 ** -24
+    assert max(errs["jacobi2"]) <= 8 * u, errs            # O(u): the cast of sigma dominates
+    assert max(errs["alg2"]) <= 50 * 64 * u * 1e4, errs   # O(u) kappa(B)
+    assert np.median(errs["jacobi2"]) < np.median(errs["alg2"]), errs
