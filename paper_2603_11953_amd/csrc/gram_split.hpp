@@ -1,0 +1,404 @@
+// Gram M_h = A^T A by exact operand splitting on the int8 matrix cores
+// (the "split" form of Alg. 1 steps 1-2).
+//
+// A workgroup owns a slab of rows and keeps, per column j, an exponent E_j
+// with |a_kj| < 2^(E_j - 1) for every row seen so far.  Each entry is written
+// as a signed 128-bit fixed-point number F = a 2^(128 - E_j) (|F| < 2^127) and
+// cut into base-128 digits of F's two's-complement form,
+//     a = 2^E_j sum_{r=1..S} d_r 2^(-7 r) + tail,  d_1 in [-64, 63], d_r in [0, 127] (r > 1),
+// 0 <= tail < 2^(E_j - 7 S).  Digit r sits at bits 128 - 7 r .. 134 - 7 r of F
+// whatever S is, so each digit is one bitfield extract.  The contribution of
+// the rows to M(i, j) is
+//     2^(E_i + E_j) sum_{s=2..S+1} 2^(-7 s) I_s,   I_s = sum_{r+t=s} sum_k d_r,ki d_t,kj,
+// keeping the slice pairs r + t <= S + 1 (the dropped pairs are below the last
+// kept digit).  The I_s are exact integers accumulated by
+// v_mfma_i32_16x16x64_i8 in int32 registers across chunks of 64 rows.
+//
+// The integer sums stay in registers until an exponent has to grow (a chunk
+// holds an entry >= 2^(E_j - 1)), until 128 chunks have been added (the int32
+// bound: 128 chunks x 64 rows x at most 16 pairs x 127^2 < 2^31), or until the
+// slab ends.  Then
+// they are "flushed": combined exactly (Horner over groups of four diagonals,
+// each group exact in FP64) into double-double (FP64 A) or FP64 (FP32 A), and
+// added to the workgroup's own slot of the partial-sum buffer.  A new exponent
+// is set two bits above what the chunk needs, so flushes are rare.
+//
+// Layout: the chunk's digits sit in LDS as int8 planes, column-major (the 64
+// rows of a column are 64 contiguous bytes).  A 16x16 tile (I, J) of M takes
+// its A operand from columns 16 I .. 16 I + 15 and its B operand from columns
+// 16 J .. 16 J + 15: lane l reads the 16 bytes of rows 16 (l / 16) .. + 15 of
+// column 16 I + l % 16 (resp. 16 J + l % 16); the integer result gives lane l,
+// register q the entry (4 (l / 16) + q, l % 16).  The tiles I <= J of the upper
+// triangle are dealt round-robin to the wavefronts of the workgroup.
+//
+// The slab / partial / fixed-order reduction structure is the one of the plain
+// form, so the result is reproducible bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dd_device.hpp"
+#include "gsvd_internal.hpp"
+
+namespace gsvd {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int SP_KT = 64;           // rows per chunk (one MFMA k-depth)
+constexpr int SP_FLUSH_EVERY = 128;  // chunks between forced flushes (int32 bound)
+constexpr int SP_HEAD = 2;          // extra exponent bits when an exponent is (re)set
+constexpr int SP_NOEXP = -100000;   // exponent of a column not seen non-zero yet
+
+template <typename T>
+struct SplitMax {
+    static constexpr int S = sizeof(T) == 8 ? 12 : 8;
+};
+
+__device__ __forceinline__ void sp_decode_pair(int p, int nb, int &bi, int &bj) {
+    int i = 0, rem = p;
+    while (rem >= nb - i) {
+        rem -= nb - i;
+        ++i;
+    }
+    bi = i;
+    bj = i + rem;
+}
+
+// max over the 16 lanes of a DPP row
+__device__ __forceinline__ int row_max_i(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false));
+    return x;
+}
+
+// exponent needed by a: the smallest e with |a| < 2^(e - 1); SP_NOEXP for a = 0
+__device__ __forceinline__ int need_exp(double a) { return a != 0.0 ? ilogb(a) + 2 : SP_NOEXP; }
+
+// F = a 2^(128 - E) truncated toward minus infinity, as two's complement (hi, lo)
+__device__ __forceinline__ void fixed128(double a, int E, unsigned long long &hi,
+                                         unsigned long long &lo) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(a);
+    const int ea = (int)((bits >> 52) & 0x7ff);
+    unsigned long long mant = bits & 0xfffffffffffffull;
+    if (ea != 0) mant |= 1ull << 52;
+    // |a| = mant 2^(max(ea, 1) - 1075); |F| = mant 2^sh
+    const int sh = (ea != 0 ? ea : 1) - 1075 + 128 - E;
+    unsigned long long h = 0, l = 0;
+    if (mant != 0 && sh > -53) {
+        if (sh >= 64) {
+            h = mant << (sh - 64);
+        } else if (sh > 0) {
+            l = mant << sh;
+            h = mant >> (64 - sh);
+        } else {
+            l = mant >> (-sh);
+        }
+    }
+    if (bits >> 63) {  // negate the 128-bit value
+        h = ~h;
+        l = ~l;
+        l += 1;
+        if (l == 0) h += 1;
+    }
+    hi = h;
+    lo = l;
+}
+
+// digit r (1-based) of F: bits 128 - 7 r .. 134 - 7 r, the first one signed
+template <int R>
+__device__ __forceinline__ int digit(unsigned long long hi, unsigned long long lo) {
+    constexpr int p = 128 - 7 * R;  // lowest bit of the digit
+    if (R == 1) return (int)((long long)hi >> 57);
+    if (p >= 64) return (int)((hi >> (p - 64)) & 127ull);
+    if (p + 7 <= 64) return (int)((lo >> p) & 127ull);
+    return (int)(((lo >> p) | (hi << (64 - p))) & 127ull);
+}
+
+template <int R>
+__device__ __forceinline__ unsigned pack4(const unsigned long long *hi, const unsigned long long *lo) {
+    unsigned w = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w |= ((unsigned)digit<R>(hi[q], lo[q]) & 0xffu) << (8 * q);
+    return w;
+}
+
+// Tiles of the upper triangle per workgroup: one per wavefront, at most 12
+// wavefronts (three per SIMD, 168 registers each).  Larger triangles are dealt
+// to several workgroups per slab, each slicing the whole chunk.
+__host__ __device__ constexpr int sp_groups(int nb) { return (nb * (nb + 1) / 2 + 11) / 12; }
+__host__ __device__ constexpr int sp_waves(int nb) {
+    return (nb * (nb + 1) / 2 + sp_groups(nb) - 1) / sp_groups(nb);
+}
+
+// The partial Gram of slab `split` of one matrix, tiles of workgroup `grp`.
+template <typename T, int NB, int SS>
+__device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t lda, int64_t m,
+                                                int n, int64_t rows_per_split, int64_t split,
+                                                int grp, double *__restrict__ part) {
+    constexpr bool DD = sizeof(T) == 8;
+    constexpr int SMAX = SS;  // slice count, fixed at compile time
+    constexpr int NW = sp_waves(NB);
+    constexpr int NT = 64 * NW;
+    constexpr int N16 = 16 * NB;
+    constexpr int NPAIR = NB * (NB + 1) / 2;
+    constexpr int SL = N16 * SP_KT;  // bytes per digit plane
+    constexpr int CPP = NT / 16;     // columns loaded per pass
+    constexpr int NPASS = (N16 + CPP - 1) / CPP;
+    extern __shared__ unsigned char smem[];
+    int *expo = reinterpret_cast<int *>(smem);  // [N16] current E_j
+    int *need = expo + N16;                     // [N16] this chunk's need
+    signed char *planes = reinterpret_cast<signed char *>(smem + 2 * N16 * sizeof(int));
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = split * rows_per_split;
+    const int64_t r1 = (r0 + rows_per_split < m) ? r0 + rows_per_split : m;
+    const int nchunk = (int)((r1 - r0 + SP_KT - 1) / SP_KT);
+
+    // this wavefront's tile (I, J), I <= J
+    const int pidx = grp * NW + wave;
+    const bool has_tile = pidx < NPAIR;
+    int bi = 0, bj = 0;
+    if (has_tile) sp_decode_pair(pidx, NB, bi, bj);
+    const int ca = 16 * bi + (lane & 15), cb = 16 * bj + (lane & 15);
+    const int koff = 16 * (lane >> 4);
+
+    // loading: pass p covers columns CPP p .. CPP p + CPP - 1; thread t takes
+    // column CPP p + t / 16 and rows 4 (t % 16) .. + 3 of the chunk
+    const int lc = tid >> 4, lr = 4 * (tid & 15);
+    T vals[NPASS][4];
+    auto fetch = [&](int chunk) {
+        const int64_t base = r0 + (int64_t)chunk * SP_KT + lr;
+#pragma unroll
+        for (int p = 0; p < NPASS; ++p) {
+            const int c = CPP * p + lc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = base + q;
+                vals[p][q] = (c < n && r < r1) ? A[r + (int64_t)c * lda] : (T)0;
+            }
+        }
+    };
+
+    v4i diag[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) diag[s] = v4i{0, 0, 0, 0};
+
+    // partial slot of this slab's tile: [split][tile][lane][q][hi, lo]
+    double *dst = part + (((size_t)split * NPAIR + (has_tile ? pidx : 0)) * 64 + lane) * 8;
+    // flush: add the integer sums (with the current exponents) to the slot
+    auto flush = [&](bool first) {
+        if (!has_tile) return;
+        const int ej = expo[cb];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ei = expo[16 * bi + 4 * (lane >> 4) + q];
+            dd_t tot{0.0, 0.0};
+            if (ei > SP_NOEXP && ej > SP_NOEXP) {
+                if (DD) {
+#pragma unroll
+                    for (int g0 = 0; g0 < SMAX; g0 += 4) {
+                        {
+                            // exact: |I_s| < 2^31, so the group sum is a
+                            // multiple of 2^-21 below 2^32 (53 bits)
+                            double v = 0.0;
+#pragma unroll
+                            for (int u = 3; u >= 0; --u)
+                                if (g0 + u < SMAX) v = v * 0x1p-7 + (double)diag[g0 + u][q];
+                            tot = dd_add(tot, dd_t{ldexp(v, -7 * (g0 + 2)), 0.0});
+                        }
+                    }
+                    tot.hi = ldexp(tot.hi, ei + ej);
+                    tot.lo = ldexp(tot.lo, ei + ej);
+                } else {
+                    double v = 0.0;
+#pragma unroll
+                    for (int s0 = SMAX - 1; s0 >= 0; --s0) v = v * 0x1p-7 + (double)diag[s0][q];
+                    tot.hi = ldexp(v, ei + ej - 14);
+                }
+            }
+            if (!first) tot = dd_add(tot, dd_t{dst[2 * q], dst[2 * q + 1]});
+            dst[2 * q] = tot.hi;
+            dst[2 * q + 1] = tot.lo;
+        }
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) diag[s] = v4i{0, 0, 0, 0};
+    };
+
+    for (int c = tid; c < N16; c += NT) expo[c] = SP_NOEXP;
+    bool first_flush = true;
+    int since_flush = 0;
+    if (nchunk > 0) fetch(0);
+    for (int ch = 0; ch < nchunk; ++ch) {
+        __syncthreads();  // the previous chunk's planes and needs are no longer read
+        // ---- exponents this chunk needs
+#pragma unroll
+        for (int p = 0; p < NPASS; ++p) {
+            const int c = CPP * p + lc;
+            int e = SP_NOEXP;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) e = max(e, need_exp((double)vals[p][q]));
+            e = row_max_i(e);  // the 16 lanes holding column c
+            if ((tid & 15) == 0 && c < N16) need[c] = e;
+        }
+        __syncthreads();
+        int grow = 0;
+        for (int c = tid; c < N16; c += NT) grow |= need[c] > expo[c];
+        grow = __syncthreads_or(grow);
+        if (grow || since_flush == SP_FLUSH_EVERY) {
+            if (since_flush > 0) {
+                flush(first_flush);
+                first_flush = false;
+            }
+            since_flush = 0;
+            __syncthreads();  // every wavefront has read the old exponents
+            for (int c = tid; c < N16; c += NT)
+                if (need[c] > expo[c]) expo[c] = need[c] + SP_HEAD;
+            __syncthreads();
+        }
+        // ---- digits of the chunk
+#pragma unroll
+        for (int p = 0; p < NPASS; ++p) {
+            const int c = CPP * p + lc;
+            if (c < N16) {
+                const int E = expo[c];
+                unsigned long long hi[4], lo[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fixed128((double)vals[p][q], E, hi[q], lo[q]);
+                signed char *pd = planes + c * SP_KT + lr;
+#define GSVD_SPLIT_PLANE(R)                                                                  \
+    if constexpr (R <= SS) *reinterpret_cast<unsigned *>(pd + (R - 1) * SL) = pack4<R>(hi, lo);
+                GSVD_SPLIT_PLANE(1) GSVD_SPLIT_PLANE(2) GSVD_SPLIT_PLANE(3) GSVD_SPLIT_PLANE(4)
+                GSVD_SPLIT_PLANE(5) GSVD_SPLIT_PLANE(6) GSVD_SPLIT_PLANE(7) GSVD_SPLIT_PLANE(8)
+                GSVD_SPLIT_PLANE(9) GSVD_SPLIT_PLANE(10) GSVD_SPLIT_PLANE(11)
+                GSVD_SPLIT_PLANE(12)
+#undef GSVD_SPLIT_PLANE
+            }
+        }
+        __syncthreads();
+        if (ch + 1 < nchunk) fetch(ch + 1);  // overlaps the MFMA phase
+
+        // ---- this wavefront's tile: the SS B-operand planes stay in registers,
+        //      each A-operand plane r meets the planes t <= SS - 1 - r
+        if (has_tile) {
+            v4i bop[SS];
+#pragma unroll
+            for (int t = 0; t < SS; ++t)
+                bop[t] = *reinterpret_cast<const v4i *>(planes + t * SL + cb * SP_KT + koff);
+#pragma unroll
+            for (int r = 0; r < SS; ++r) {
+                const v4i aop = *reinterpret_cast<const v4i *>(planes + r * SL + ca * SP_KT + koff);
+#pragma unroll
+                for (int t = 0; t < SS - r; ++t)
+                    diag[r + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, bop[t], diag[r + t], 0,
+                                                                       0, 0);
+            }
+        }
+        ++since_flush;
+    }
+    flush(first_flush);
+}
+
+template <typename T, int NB, int SS>
+__global__ void __launch_bounds__(64 * sp_waves(NB))
+gram_split_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int64_t rows_per_split,
+                  double *__restrict__ part) {
+    gram_split_body<T, NB, SS>(A, lda, m, n, rows_per_split, blockIdx.y, blockIdx.x, part);
+}
+
+// Batched: blockIdx.z picks the problem order[first + z], blockIdx.y its slab.
+template <typename T, int NB, int SS>
+__global__ void __launch_bounds__(64 * sp_waves(NB))
+gram_split_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order,
+                          int first) {
+    const BatchMat &d = tab[order[first + blockIdx.z]];
+    if ((int)blockIdx.y >= d.nsplit) return;
+    gram_split_body<T, NB, SS>(reinterpret_cast<const T *>(d.A), d.lda, d.m, d.n,
+                               d.rows_per_split, blockIdx.y, blockIdx.x, d.part);
+}
+
+// Launchers of the partial-sum kernels for one element type: the (NB, S)
+// instance is picked at run time from the plan.
+template <typename T, int NB, int SS>
+static hipError_t split_partial_inst(int64_t m, int64_t n, const T *A, int64_t lda, void *part,
+                                     const SplitPlan &p, hipStream_t st) {
+    auto k = gram_split_kernel<T, NB, SS>;
+    hipError_t err = hipFuncSetAttribute((const void *)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)p.lds_bytes);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k, dim3(sp_groups(NB), (unsigned)p.nsplit), dim3(64 * sp_waves(NB)),
+                       p.lds_bytes, st, A, lda, m, (int)n, p.rows_per_split, (double *)part);
+    return hipGetLastError();
+}
+
+template <typename T, int NB, int SS>
+static hipError_t split_batched_inst(const BatchMat *tab, const int *order, int first, int count,
+                                     int max_nsplit, const SplitPlan &p, hipStream_t st) {
+    auto k = gram_split_batched_kernel<T, NB, SS>;
+    hipError_t err = hipFuncSetAttribute((const void *)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)p.lds_bytes);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k, dim3(sp_groups(NB), (unsigned)max_nsplit, (unsigned)count),
+                       dim3(64 * sp_waves(NB)), p.lds_bytes, st, tab, order, first);
+    return hipGetLastError();
+}
+
+#define GSVD_SPLIT_S_CASES(CALL, NB)                                                         \
+    switch (p.S) {                                                                           \
+        case 1: return CALL(NB, 1);                                                          \
+        case 2: return CALL(NB, 2);                                                          \
+        case 3: return CALL(NB, 3);                                                          \
+        case 4: return CALL(NB, 4);                                                          \
+        case 5: return CALL(NB, 5);                                                          \
+        case 6: return CALL(NB, 6);                                                          \
+        case 7: return CALL(NB, 7);                                                          \
+        case 8: return CALL(NB, 8);                                                          \
+        case 9: if constexpr (SplitMax<T>::S >= 9) return CALL(NB, 9); else break;           \
+        case 10: if constexpr (SplitMax<T>::S >= 10) return CALL(NB, 10); else break;        \
+        case 11: if constexpr (SplitMax<T>::S >= 11) return CALL(NB, 11); else break;        \
+        case 12: if constexpr (SplitMax<T>::S >= 12) return CALL(NB, 12); else break;        \
+        default: break;                                                                      \
+    }                                                                                        \
+    return hipErrorInvalidValue;
+
+#define GSVD_SPLIT_NB_CASES(NBCALL)                                                          \
+    switch (p.nb) {                                                                          \
+        case 1: NBCALL(1)                                                                    \
+        case 2: NBCALL(2)                                                                    \
+        case 3: NBCALL(3)                                                                    \
+        case 4: NBCALL(4)                                                                    \
+        case 5: NBCALL(5)                                                                    \
+        case 6: NBCALL(6)                                                                    \
+        case 7: NBCALL(7)                                                                    \
+        case 8: NBCALL(8)                                                                    \
+        default: return hipErrorInvalidValue;                                                \
+    }
+
+template <typename T>
+static hipError_t split_partial_typed(int64_t m, int64_t n, const T *A, int64_t lda, void *part,
+                                      const SplitPlan &p, hipStream_t st) {
+#define GSVD_CALL(NB_, S_) split_partial_inst<T, NB_, S_>(m, n, A, lda, part, p, st)
+#define GSVD_NB(NB_) { GSVD_SPLIT_S_CASES(GSVD_CALL, NB_) }
+    GSVD_SPLIT_NB_CASES(GSVD_NB)
+#undef GSVD_NB
+#undef GSVD_CALL
+}
+
+template <typename T>
+static hipError_t split_batched_typed(const BatchMat *tab, const int *order, int first, int count,
+                                      int max_nsplit, const SplitPlan &p, hipStream_t st) {
+#define GSVD_CALL(NB_, S_) split_batched_inst<T, NB_, S_>(tab, order, first, count, max_nsplit, p, st)
+#define GSVD_NB(NB_) { GSVD_SPLIT_S_CASES(GSVD_CALL, NB_) }
+    GSVD_SPLIT_NB_CASES(GSVD_NB)
+#undef GSVD_NB
+#undef GSVD_CALL
+}
+
+#undef GSVD_SPLIT_S_CASES
+#undef GSVD_SPLIT_NB_CASES
+
+}  // namespace gsvd

@@ -73,6 +73,15 @@ hipError_t split_launch(int working, int64_t m, int64_t n, const void *A, int64_
 hipError_t split_batched_launch(int working, const BatchMat *tab, const int *order, int first,
                                 int count, int max_nsplit, const SplitPlan &p, hipStream_t st);
 hipError_t split_reduce_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st);
+// the per-type partial-sum launchers behind split_launch / split_batched_launch
+hipError_t split_partial_f64(int64_t m, int64_t n, const double *A, int64_t lda, void *part,
+                             const SplitPlan &p, hipStream_t st);
+hipError_t split_partial_f32(int64_t m, int64_t n, const float *A, int64_t lda, void *part,
+                             const SplitPlan &p, hipStream_t st);
+hipError_t split_batched_f64(const BatchMat *tab, const int *order, int first, int count,
+                             int max_nsplit, const SplitPlan &p, hipStream_t st);
+hipError_t split_batched_f32(const BatchMat *tab, const int *order, int first, int count,
+                             int max_nsplit, const SplitPlan &p, hipStream_t st);
 
 // Eigensolver stage (eig.hip).
 size_t eig_lds_bytes(int working, int64_t n);
