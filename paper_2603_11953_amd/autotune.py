@@ -1,0 +1,236 @@
+"""Tune the library's launch shapes and slice counts on the GPU in use.
+
+Writes ``csrc/tune_table.inc`` (the rows behind ``tune_slab_rows`` and
+``tune_slices``); rebuild the library afterwards (``python
+paper_2603_11953_amd/build.py``).
+
+Slab height (rows of A per Gram workgroup).  For every working precision, Gram
+form (plain / split), call kind (one problem / batched), n bucket and m bucket,
+the Gram stage is timed through the C-ABI over a ladder of slab heights on
+seeded Gaussian inputs, and the fastest height is kept.
+
+Slice count of the split Gram.  A perturbation dM of the Gram with
+|dM_ij| <= eps sqrt(M_ii M_jj) moves the eigenvalues of the column-scaled Gram
+H = D^-1 M D^-1 by at most n eps, i.e. each sigma_i by a relative
+n eps kappa(B)^2 / 2 at most; the sigma tolerance 50 n u kappa(B) therefore asks
+for eps <= 100 u / kappa(B).  For each working precision and n bucket the split
+Gram of seeded A = B D test matrices (the paper's recipe, kappa(B) = kappa_ref,
+strongly graded D) is compared with the plain higher-precision Gram of the same
+matrices; the smallest S whose measured eps is below 50 u / kappa_ref is kept,
+plus one slice of margin.
+
+Run on the GPU:  python -m paper_2603_11953_amd.autotune [--quick] [--write]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+TABLE = os.path.join(HERE, "csrc", "tune_table.inc")
+
+N_BUCKETS = (16, 32, 64, 96, 128)
+# (tuning size, upper edge) of each m bucket: tuned near the bucket's middle
+M_BUCKETS = ((20_000, 50_000), (160_000, 500_000), (1_000_000, 2_000_000), (4_000_000, 2**62))
+SINGLE_LADDER = (0, 256, 512, 1024, 2048, 4096, 8192)
+BATCH_LADDER = (512, 1024, 2048, 4096, 8192, 16384)
+KAPPA_REF = {1: 1e3, 0: 1e2}  # FP64 working: kappa(B) up to 1e3; FP32 working: 1e2
+
+
+def _gs():
+    sys.path.insert(0, ROOT)
+    import paper_2603_11953_amd as gs
+    return gs
+
+
+def _time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _gram_fn(gs, A, Mhi, Mlo, work, o):
+    m, n = A.shape
+    ob = ctypes.byref(o)
+
+    def f():
+        rc = gs.gsvd_gram(m, n, A.data_ptr(), m, Mhi.data_ptr(), Mlo.data_ptr(), n,
+                          work.data_ptr(), work.numel(), ob, gs._stream(None))
+        if rc != 0:
+            raise RuntimeError(f"gsvd_gram {rc}")
+    return f
+
+
+def tune_single(gs, quick):
+    import torch
+    rows = []
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(11953)
+    for working, dt in ((1, torch.float64), (0, torch.float32)):
+        for gram in (gs.GSVD_GRAM_PLAIN, gs.GSVD_GRAM_SPLIT):
+            for n in N_BUCKETS:
+                for m, m_edge in (M_BUCKETS[:2] if quick else M_BUCKETS):
+                    A = torch.randn(n, m, device=dev, dtype=dt, generator=gen).t()
+                    Mhi = torch.empty(n, n, device=dev, dtype=torch.float64)
+                    Mlo = torch.empty_like(Mhi)
+                    best = None
+                    for slab in SINGLE_LADDER:
+                        if slab and slab > m:
+                            continue
+                        o = gs.opts(working, gram, slab_rows=slab)
+                        need = gs.gsvd_gram_workspace_size(m, n, ctypes.byref(o))
+                        work = gs.workspace(need, dev)
+                        ms = _time(_gram_fn(gs, A, Mhi, Mlo, work, o), 3 if quick else 5)
+                        if best is None or ms < best[1]:
+                            best = (slab, ms)
+                        del work
+                    rows.append(dict(working=working, gram=gram, batched=0, n_max=n, m_max=m_edge,
+                                     slab_rows=best[0], ms=round(best[1], 4), m_tuned=m))
+                    print(f"[tune] single w={working} gram={gram} n<={n} m={m}: slab {best[0]} "
+                          f"({best[1]:.3f} ms)", flush=True)
+                    del A
+    return rows
+
+
+def tune_batched(gs, quick):
+    import torch
+    rows = []
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(11954)
+    count = 16 if quick else 48
+    for working, dt in ((1, torch.float64), (0, torch.float32)):
+        for gram in (gs.GSVD_GRAM_PLAIN, gs.GSVD_GRAM_SPLIT):
+            for n in N_BUCKETS:
+                if working == 1 and n > 96:
+                    continue  # the FP64 eigensolver stops at n = 96
+                ms_ = torch.randint(10_000, 200_001, (count,), generator=torch.Generator().manual_seed(n))
+                As = [torch.randn(n, int(m), device=dev, dtype=dt, generator=gen).t() for m in ms_]
+                best = None
+                for slab in BATCH_LADDER:
+                    b = gs.Batch(As, gram=gram, want_u=False, slab_rows=slab)
+                    ms = _time(b.run, 2 if quick else 3)
+                    if best is None or ms < best[1]:
+                        best = (slab, ms)
+                    del b
+                rows.append(dict(working=working, gram=gram, batched=1, n_max=n, m_max=2**62,
+                                 slab_rows=best[0], ms=round(best[1], 4)))
+                print(f"[tune] batched w={working} gram={gram} n<={n}: slab {best[0]} "
+                      f"({best[1]:.3f} ms for {count} problems)", flush=True)
+                del As
+    return rows
+
+
+def tune_slices(gs, quick):
+    """Smallest slice count meeting the Gram accuracy budget, plus one."""
+    import numpy as np
+    import torch
+    from gen import matrices as g
+    rows = []
+    dev = torch.device("cuda:0")
+    for working, dt in ((1, "f64"), (0, "f32")):
+        u = 2.0 ** -53 if working == 1 else 2.0 ** -24
+        kref = KAPPA_REF[working]
+        budget = 50 * u / kref
+        smax = 12 if working == 1 else 8
+        for n in N_BUCKETS:
+            worst = np.zeros(smax + 1)
+            for seed in range(1 if quick else 3):
+                A = g.make_a(g.MatrixSpec(m=100_000, n=n, kappa_b=kref,
+                                          kappa_d=1e12 if working == 1 else 1e6, mode_b=3, mode_d=5,
+                                          seed=12_000 + 31 * n + seed, dtype=dt, shuffle=True,
+                                          w1="gauss"))
+                dA = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev).t()
+                m = A.shape[0]
+                Mhi = torch.empty(n, n, device=dev, dtype=torch.float64)
+                Mlo = torch.empty_like(Mhi)
+                o = gs.opts(working, gs.GSVD_GRAM_PLAIN)
+                work = gs.workspace(gs.gsvd_gram_workspace_size(m, n, ctypes.byref(o)), dev)
+                _gram_fn(gs, dA, Mhi, Mlo, work, o)()
+                torch.cuda.synchronize()
+                ref = Mhi.cpu().numpy() + Mlo.cpu().numpy()
+                d = np.sqrt(np.diag(Mhi.cpu().numpy()))
+                for S in range(1, smax + 1):
+                    o = gs.opts(working, gs.GSVD_GRAM_SPLIT, n_slices=S)
+                    work = gs.workspace(gs.gsvd_gram_workspace_size(m, n, ctypes.byref(o)), dev)
+                    Sh, Sl = torch.empty_like(Mhi), torch.empty_like(Mhi)
+                    _gram_fn(gs, dA, Sh, Sl, work, o)()
+                    torch.cuda.synchronize()
+                    diff = (Sh.cpu().numpy() - Mhi.cpu().numpy()) + (Sl.cpu().numpy() - Mlo.cpu().numpy())
+                    eps = float(np.max(np.abs(diff) / np.outer(d, d)))
+                    worst[S] = max(worst[S], eps)
+            ok = [S for S in range(1, smax + 1) if worst[S] <= budget]
+            pick = min(smax, (ok[0] + 1) if ok else smax)
+            rows.append(dict(working=working, n_max=n, slices=pick,
+                             eps=[float(f"{e:.3g}") for e in worst[1:]], budget=budget))
+            print(f"[tune] slices w={working} n<={n}: eps(S) = "
+                  + " ".join(f"{S}:{worst[S]:.1e}" for S in range(1, smax + 1))
+                  + f"; budget {budget:.1e} -> S = {pick}", flush=True)
+    return rows
+
+
+def render(slab_rows, slice_rows, meta):
+    # the largest m bucket of each (precision, form, kind, n) also covers every taller matrix
+    top = {}
+    for r in slab_rows:
+        k = (r["working"], r["gram"], r["batched"], r["n_max"])
+        top[k] = max(top.get(k, 0), r["m_max"])
+    for r in slab_rows:
+        if r["m_max"] == top[(r["working"], r["gram"], r["batched"], r["n_max"])]:
+            r["m_max"] = 2**62
+    names = {1: "GSVD_F64", 0: "GSVD_F32"}
+    grams = {1: "GSVD_GRAM_PLAIN", 2: "GSVD_GRAM_SPLIT"}
+    out = ["// Generated by paper_2603_11953_amd/autotune.py -- do not edit by hand.",
+           f"// {meta}",
+           "static const TuneSlab kTuneSlab[] = {"]
+    for r in slab_rows:
+        m_max = "INT64_MAX" if r["m_max"] >= 2**62 else str(r["m_max"])
+        note = f"{r['ms']} ms at m = {r['m_tuned']}" if "m_tuned" in r else f"{r['ms']} ms"
+        out.append(f"    {{{names[r['working']]}, {grams[r['gram']]}, {r['batched']}, {r['n_max']}, "
+                   f"{m_max}, {r['slab_rows']}}},  // {note}")
+    out.append("};")
+    out.append("static const TuneSlices kTuneSlices[] = {")
+    for r in slice_rows:
+        out.append(f"    {{{names[r['working']]}, {r['n_max']}, {r['slices']}}},")
+    out.append("};")
+    return "\n".join(out) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--quick", action="store_true", help="fewer sizes and repetitions")
+    ap.add_argument("--write", action="store_true", help="write the table (to --out)")
+    ap.add_argument("--out", default=TABLE, help="table path (default: the library's csrc)")
+    ap.add_argument("--json", default="", help="also dump the measurements to this file")
+    args = ap.parse_args()
+    gs = _gs()
+    t0 = time.time()
+    slab_rows = tune_single(gs, args.quick) + tune_batched(gs, args.quick)
+    slice_rows = tune_slices(gs, args.quick)
+    import torch
+    meta = (f"{torch.cuda.get_device_name(0)}; {'quick' if args.quick else 'full'} run, "
+            f"{time.time() - t0:.0f} s")
+    text = render(slab_rows, slice_rows, meta)
+    print(text)
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump({"slab": slab_rows, "slices": slice_rows, "meta": meta}, f, indent=1)
+    if args.write:
+        with open(args.out, "w") as f:
+            f.write(text)
+        print(f"[tune] wrote {args.out}; rebuild the library to use it")
+
+
+if __name__ == "__main__":
+    main()

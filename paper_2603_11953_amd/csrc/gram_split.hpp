@@ -24,12 +24,13 @@
 // is set two bits above what the chunk needs, so flushes are rare.
 //
 // Layout: the chunk's digits sit in LDS as int8 planes, column-major (the 64
-// rows of a column are 64 contiguous bytes).  A 16x16 tile (I, J) of M takes
+// rows of a column are 64 contiguous bytes, columns 80 bytes apart).  A 16x16
+// tile (I, J) of M takes
 // its A operand from columns 16 I .. 16 I + 15 and its B operand from columns
 // 16 J .. 16 J + 15: lane l reads the 16 bytes of rows 16 (l / 16) .. + 15 of
 // column 16 I + l % 16 (resp. 16 J + l % 16); the integer result gives lane l,
-// register q the entry (4 (l / 16) + q, l % 16).  The tiles I <= J of the upper
-// triangle are dealt round-robin to the wavefronts of the workgroup.
+// register q the entry (4 (l / 16) + q, l % 16).  Each wavefront owns one tile
+// I <= J of the upper triangle.
 //
 // The slab / partial / fixed-order reduction structure is the one of the plain
 // form, so the result is reproducible bit for bit.
@@ -45,6 +46,10 @@ namespace gsvd {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int SP_KT = 64;           // rows per chunk (one MFMA k-depth)
+// byte stride of a column in a digit plane: 64 digits plus 16 bytes of padding,
+// so the 16 lanes of an operand read (16 columns, 16 bytes each) fall into
+// 16 distinct groups of 4 banks
+constexpr int SP_CS = SP_KT + 16;
 constexpr int SP_FLUSH_EVERY = 128;  // chunks between forced flushes (int32 bound)
 constexpr int SP_HEAD = 2;          // extra exponent bits when an exponent is (re)set
 constexpr int SP_NOEXP = -100000;   // exponent of a column not seen non-zero yet
@@ -143,7 +148,7 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
     constexpr int NT = 64 * NW;
     constexpr int N16 = 16 * NB;
     constexpr int NPAIR = NB * (NB + 1) / 2;
-    constexpr int SL = N16 * SP_KT;  // bytes per digit plane
+    constexpr int SL = N16 * SP_CS;  // bytes per digit plane
     constexpr int CPP = NT / 16;     // columns loaded per pass
     constexpr int NPASS = (N16 + CPP - 1) / CPP;
     extern __shared__ unsigned char smem[];
@@ -267,7 +272,7 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
                 unsigned long long hi[4], lo[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) fixed128((double)vals[p][q], E, hi[q], lo[q]);
-                signed char *pd = planes + c * SP_KT + lr;
+                signed char *pd = planes + c * SP_CS + lr;
 #define GSVD_SPLIT_PLANE(R)                                                                  \
     if constexpr (R <= SS) *reinterpret_cast<unsigned *>(pd + (R - 1) * SL) = pack4<R>(hi, lo);
                 GSVD_SPLIT_PLANE(1) GSVD_SPLIT_PLANE(2) GSVD_SPLIT_PLANE(3) GSVD_SPLIT_PLANE(4)
@@ -286,10 +291,10 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
             v4i bop[SS];
 #pragma unroll
             for (int t = 0; t < SS; ++t)
-                bop[t] = *reinterpret_cast<const v4i *>(planes + t * SL + cb * SP_KT + koff);
+                bop[t] = *reinterpret_cast<const v4i *>(planes + t * SL + cb * SP_CS + koff);
 #pragma unroll
             for (int r = 0; r < SS; ++r) {
-                const v4i aop = *reinterpret_cast<const v4i *>(planes + r * SL + ca * SP_KT + koff);
+                const v4i aop = *reinterpret_cast<const v4i *>(planes + r * SL + ca * SP_CS + koff);
 #pragma unroll
                 for (int t = 0; t < SS - r; ++t)
                     diag[r + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, bop[t], diag[r + t], 0,

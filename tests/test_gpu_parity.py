@@ -285,3 +285,19 @@ def test_two_sided_jacobi_is_O_u_while_alg2_tracks_kappa_b():
     assert max(errs["jacobi2"]) <= 8 * u, errs            # O(u): the cast of sigma dominates
     assert max(errs["alg2"]) <= 50 * 64 * u * 1e4, errs   # O(u) kappa(B)
     assert np.median(errs["jacobi2"]) < np.median(errs["alg2"]), errs
+
+
+@pytest.mark.parametrize("form", ["plain", "split"])
+def test_full_size_fp32_workload(form):
+    """The FP32 workload at full size (m = 4e6, n = 128, kappa(B) = 1e2, kappa(D) = 1e6), in the
+    launch configuration of a single gsvd_thin call: every sigma against the oracle, U on
+    sampled rows (orthogonality of the full U and the residual on a row sample)."""
+    import paper_2603_11953_amd as gs
+    spec = g.spec_tall_f32()
+    A = g.make_a(spec)
+    o = ref.svd(A)
+    say("full size fp32", form, A.shape)
+    S, V, Uo, info = _thin(A, gram=gs.GSVD_GRAM_SPLIT if form == "split" else gs.GSVD_GRAM_PLAIN)
+    assert info == 0
+    rows = np.random.default_rng(3).integers(0, spec.m, 20_000)
+    check_thin(A, S, V, Uo, o, rows=rows, label=f"fp32 4e6x128 {form}")
