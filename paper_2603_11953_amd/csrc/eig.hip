@@ -39,8 +39,12 @@
 namespace gsvd {
 
 constexpr int GRP = 8;  // lanes per Jacobi pair: half a DPP row
-constexpr int MAXREG = 16;  // entries of R per lane while it moves into Y: n^2 / lanes <= 16
-                            // for n <= 128 with 1024 lanes and for n < 32 with 8 (n+1)/2
+// Workgroup size bound and staging depth by register depth: up to RPL = 8
+// (n <= 64) 1024 lanes and n^2 / lanes <= 16 entries of R per lane while it
+// moves into Y; beyond, 512 lanes (the Jacobi needs 4 N2 = 512 of them) so each
+// lane may hold the larger register blocks, and n^2 / lanes <= 32.
+__host__ __device__ constexpr int eig_bound(int rpl) { return rpl > 8 ? 512 : 1024; }
+__host__ __device__ constexpr int eig_maxreg(int rpl) { return rpl > 8 ? 32 : 16; }
 
 // Column stride of R and V in LDS during the Jacobi: n rounded up to a
 // multiple of 256 bytes.
@@ -49,6 +53,28 @@ __host__ __device__ __forceinline__ int jac_ld(int n) {
     constexpr int q = 256 / (int)sizeof(TS);
     return (n + q - 1) / q * q;
 }
+
+// rows per lane in the Jacobi: n rounded up to 16, over 8 lanes (an even count,
+// for the two-row vector accesses)
+__host__ __device__ constexpr int eig_rpl(int n) { return 2 * ((n + 15) / 16); }
+
+// n rounded up to a power of two (at least 2): the column count of the Jacobi ordering
+__host__ __device__ constexpr int eig_pow2(int n) {
+    int p = 2;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+template <typename TS>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    typedef double2 type;
+};
+template <>
+struct Vec2<float> {
+    typedef float2 type;
+};
 
 struct EigShared {
     int flag_rot;
@@ -108,7 +134,7 @@ struct EigSmem {
     dd_t rowk[GSVD_KMAX_N];
 };
 
-// Algorithm 2 for one n x n Gram (one workgroup; n <= GRP * RPL).
+// Algorithm 2 for one n x n Gram (one workgroup; n <= GRP * RPL, RPL even).
 template <typename TW, typename TS, bool DDGRAM, int RPL>
 __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                                          const double *__restrict__ Mlo, int64_t ldm,
@@ -220,6 +246,7 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
     //      LDS, V = I next to it.  The Cholesky square overlaps both, so every
     //      lane first lifts its share of R into registers.
     const int emax = sh.emax;
+    constexpr int MAXREG = eig_maxreg(RPL);
     double rv[MAXREG];
 #pragma unroll
     for (int c = 0; c < MAXREG; ++c) {
@@ -254,88 +281,129 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
     }
     __syncthreads();
 
-    // ---- 4. one-sided Jacobi on the columns of Y = R, rotations accumulated in V
-    const int N = n + (n & 1);  // even number of players; player n is a dummy
-    const int npair = N / 2;
+    // ---- 4. one-sided Jacobi on the columns of Y = R, rotations accumulated in V.
+    //      Ordering: the columns are padded (virtually) to N2 = 2^k >= n.  Level L
+    //      splits them into sets of s = N2 >> L columns; in each set the lower half
+    //      stays resident in the registers of h = s / 2 groups while the upper half
+    //      travels: at step t group i of the set pairs its resident column with
+    //      traveler (i + t) mod h, so the h steps cover every cross pair of the
+    //      two halves with h disjoint pairs each.  The next level recurses into
+    //      both halves; N2 - 1 steps cover every pair once.  Only the traveling
+    //      column of a pair goes through LDS each step (half the traffic of an
+    //      ordering that moves both).  Pairs with a padding column are skipped.
+    const int N2 = eig_pow2(n);
     const int grp = tid / GRP, gl = tid % GRP;
     const int ngrp = nthr / GRP;
+    typedef typename Vec2<TS>::type tv2;
+    constexpr int RP2 = RPL / 2;  // row pairs per lane: rows 2 gl + 16 b, + 1
+    // register b holds row pair (b + rot) mod RP2: groups that share an LDS cycle
+    // read different 128-row-byte blocks
+    const int rot = RP2 > 1 ? (grp & 3) % RP2 : 0;
+    auto rowof = [&](int b) {
+        int blk = b + rot;
+        if (blk >= RP2) blk -= RP2;
+        return 2 * gl + 16 * blk;
+    };
     bool converged = (n == 1);
     for (int sw = 0; sw < max_sweeps && !converged; ++sw) {
-        for (int step = 0; step < N - 1; ++step) {
-            for (int pr = grp; pr < npair; pr += ngrp) {
-                // round robin: position 0 holds player 0, position t >= 1 holds
-                // player 1 + (t - 1 + step) mod (N - 1); pair pr = positions pr, N-1-pr
-                int a = 0;
-                if (pr != 0) {
-                    a = pr - 1 + step;
-                    if (a >= N - 1) a -= N - 1;
-                    a += 1;
-                }
-                int b = N - 2 - pr + step;
-                if (b >= N - 1) b -= N - 1;
-                b += 1;
-                const int p = a < b ? a : b, q = a < b ? b : a;
-                if (q >= n) continue;  // dummy player (uniform within the group)
-                TS *yp = Y + p * ld, *yq = Y + q * ld;
-                TS *vp = Vs + p * ld, *vq = Vs + q * ld;
-                // register i holds row block (i + rot) mod RPL: the four groups that
-                // share an LDS cycle read different 64-byte blocks, so different banks.
-                // Rows up to GRP * RPL <= ld exist (zero padding), so no bounds checks;
-                // all four columns are fetched before any use.
-                const int rot = grp & 3;
-                TS x0[RPL], x1[RPL], w0[RPL], w1[RPL];
+        for (int s2 = N2; s2 >= 2; s2 >>= 1) {
+            const int h = s2 >> 1;
+            const int set = grp / h, li = grp - set * h;
+            const int res = set * s2 + li;
+            const bool act = grp < (N2 >> 1) && res < n && grp < ngrp;
+            TS x0[RPL], w0[RPL];
+            if (act) {
+                const TS *yr = Y + res * ld, *vr = Vs + res * ld;
 #pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    int blk = i + rot;
-                    if (blk >= RPL) blk -= RPL;
-                    if (blk >= RPL) blk -= RPL;
-                    if (blk >= RPL) blk -= RPL;
-                    const int r = gl + GRP * blk;
-                    x0[i] = yp[r];
-                    x1[i] = yq[r];
-                    w0[i] = vp[r];
-                    w1[i] = vq[r];
+                for (int b = 0; b < RP2; ++b) {
+                    const int r = rowof(b);
+                    const tv2 y = *reinterpret_cast<const tv2 *>(yr + r);
+                    const tv2 v = *reinterpret_cast<const tv2 *>(vr + r);
+                    x0[2 * b] = y.x;
+                    x0[2 * b + 1] = y.y;
+                    w0[2 * b] = v.x;
+                    w0[2 * b + 1] = v.y;
                 }
-                double al = 0, be = 0, ga = 0;
+            }
+            for (int t = 0; t < h; ++t) {
+                int tj = li + t;
+                if (tj >= h) tj -= h;
+                const int trv = set * s2 + h + tj;
+                if (act && trv < n) {  // uniform within the group
+                    TS *yq = Y + trv * ld, *vq = Vs + trv * ld;
+                    TS x1[RPL], w1[RPL];
 #pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    const double a0 = (double)x0[i], a1 = (double)x1[i];
-                    al = __builtin_fma(a0, a0, al);
-                    be = __builtin_fma(a1, a1, be);
-                    ga = __builtin_fma(a0, a1, ga);
-                }
-                al = group_sum(al);
-                be = group_sum(be);
-                ga = group_sum(ga);
-                if (ga * ga > tol2 * (al * be)) {
-                    const double zeta = (be - al) * rcp_nr(2.0 * ga);
-                    const double az = __builtin_fabs(zeta);
-                    double t;
-                    if (az > 1e150) {
-                        t = 0.5 * rcp_nr(zeta);
-                    } else {
-                        const double x = __builtin_fma(zeta, zeta, 1.0);
-                        const double root = x * rsq_nr(x);
-                        t = rcp_nr(az + root);
-                        if (zeta < 0) t = -t;
+                    for (int b = 0; b < RP2; ++b) {
+                        const int r = rowof(b);
+                        const tv2 y = *reinterpret_cast<const tv2 *>(yq + r);
+                        const tv2 v = *reinterpret_cast<const tv2 *>(vq + r);
+                        x1[2 * b] = y.x;
+                        x1[2 * b + 1] = y.y;
+                        w1[2 * b] = v.x;
+                        w1[2 * b + 1] = v.y;
                     }
-                    const double c = rsq_nr(__builtin_fma(t, t, 1.0));
-                    const double s = c * t;
+                    double al = 0, be = 0, ga = 0;
 #pragma unroll
                     for (int i = 0; i < RPL; ++i) {
-                        int blk = i + rot;
-                        if (blk >= RPL) blk -= RPL;
-                        if (blk >= RPL) blk -= RPL;
-                        if (blk >= RPL) blk -= RPL;
-                        const int r = gl + GRP * blk;
                         const double a0 = (double)x0[i], a1 = (double)x1[i];
-                        const double u = (double)w0[i], w = (double)w1[i];
-                        yp[r] = (TS)(c * a0 - s * a1);
-                        yq[r] = (TS)(s * a0 + c * a1);
-                        vp[r] = (TS)(c * u - s * w);
-                        vq[r] = (TS)(s * u + c * w);
+                        al = __builtin_fma(a0, a0, al);
+                        be = __builtin_fma(a1, a1, be);
+                        ga = __builtin_fma(a0, a1, ga);
                     }
-                    if (gl == 0) sh.flag_rot = 1;
+                    al = group_sum(al);
+                    be = group_sum(be);
+                    ga = group_sum(ga);
+                    if (ga * ga > tol2 * (al * be)) {
+                        const double zeta = (be - al) * rcp_nr(2.0 * ga);
+                        const double az = __builtin_fabs(zeta);
+                        double tn;
+                        if (az > 1e150) {
+                            tn = 0.5 * rcp_nr(zeta);
+                        } else {
+                            const double x = __builtin_fma(zeta, zeta, 1.0);
+                            const double root = x * rsq_nr(x);
+                            tn = rcp_nr(az + root);
+                            if (zeta < 0) tn = -tn;
+                        }
+                        const double c = rsq_nr(__builtin_fma(tn, tn, 1.0));
+                        const double sn = c * tn;
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) {
+                            const double a0 = (double)x0[i], a1 = (double)x1[i];
+                            const double u = (double)w0[i], w = (double)w1[i];
+                            x0[i] = (TS)(c * a0 - sn * a1);
+                            x1[i] = (TS)(sn * a0 + c * a1);
+                            w0[i] = (TS)(c * u - sn * w);
+                            w1[i] = (TS)(sn * u + c * w);
+                        }
+#pragma unroll
+                        for (int b = 0; b < RP2; ++b) {
+                            const int r = rowof(b);
+                            tv2 y, v;
+                            y.x = x1[2 * b];
+                            y.y = x1[2 * b + 1];
+                            v.x = w1[2 * b];
+                            v.y = w1[2 * b + 1];
+                            *reinterpret_cast<tv2 *>(yq + r) = y;
+                            *reinterpret_cast<tv2 *>(vq + r) = v;
+                        }
+                        if (gl == 0) sh.flag_rot = 1;
+                    }
+                }
+                __syncthreads();  // the travelers move on
+            }
+            if (act) {  // the resident goes back to its slot for the next level
+                TS *yr = Y + res * ld, *vr = Vs + res * ld;
+#pragma unroll
+                for (int b = 0; b < RP2; ++b) {
+                    const int r = rowof(b);
+                    tv2 y, v;
+                    y.x = x0[2 * b];
+                    y.y = x0[2 * b + 1];
+                    v.x = w0[2 * b];
+                    v.y = w0[2 * b + 1];
+                    *reinterpret_cast<tv2 *>(yr + r) = y;
+                    *reinterpret_cast<tv2 *>(vr + r) = v;
                 }
             }
             __syncthreads();
@@ -405,7 +473,7 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
 }
 
 template <typename TW, typename TS, bool DDGRAM, int RPL>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(eig_bound(RPL))
 eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__restrict__ Mlo,
                         int64_t ldm, TW *__restrict__ S, TW *__restrict__ V, int64_t ldv,
                         TW *__restrict__ W, int64_t ldw, int *__restrict__ info, double tol2,
@@ -417,10 +485,10 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
 }
 
 // Batched: one workgroup per problem, the largest first (order is ascending in
-// n); the register depth RPL = ceil(n / GRP) is chosen per problem.  tol <= 0
+// n); the register depth RPL = eig_rpl(n) is chosen per problem.  tol <= 0
 // selects sqrt(n) u_w.
 template <typename TW, typename TS, bool DDGRAM, int MAXRPL>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(eig_bound(MAXRPL))
 eig_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order, int batch,
                    double tol, int max_sweeps) {
     extern __shared__ double lds[];
@@ -433,15 +501,13 @@ eig_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ ord
 #define GSVD_EIG_BODY(R)                                                                        \
     case R:                                                                                     \
         if (R <= MAXRPL)                                                                        \
-            eig_body<TW, TS, DDGRAM, (R <= MAXRPL ? R : 1)>(                                    \
+            eig_body<TW, TS, DDGRAM, (R <= MAXRPL ? R : 2)>(                                    \
                 n, d.Mhi, Mlo, n, (TW *)d.S, (TW *)d.V, d.ldv, (TW *)d.W, n, d.info, tol2,      \
                 max_sweeps, sm, lds);                                                           \
         break;
-    switch ((n + GRP - 1) / GRP) {
-        GSVD_EIG_BODY(1) GSVD_EIG_BODY(2) GSVD_EIG_BODY(3) GSVD_EIG_BODY(4)
-        GSVD_EIG_BODY(5) GSVD_EIG_BODY(6) GSVD_EIG_BODY(7) GSVD_EIG_BODY(8)
-        GSVD_EIG_BODY(9) GSVD_EIG_BODY(10) GSVD_EIG_BODY(11) GSVD_EIG_BODY(12)
-        GSVD_EIG_BODY(13) GSVD_EIG_BODY(14) GSVD_EIG_BODY(15) GSVD_EIG_BODY(16)
+    switch (eig_rpl(n)) {
+        GSVD_EIG_BODY(2) GSVD_EIG_BODY(4) GSVD_EIG_BODY(6) GSVD_EIG_BODY(8)
+        GSVD_EIG_BODY(10) GSVD_EIG_BODY(12) GSVD_EIG_BODY(14) GSVD_EIG_BODY(16)
         default: break;
     }
 #undef GSVD_EIG_BODY
@@ -457,11 +523,12 @@ size_t eig_lds_bytes(int working, int64_t n) {
 int eig_max_n(int working) { return working == 1 ? GSVD_KMAX_N_F64 : GSVD_KMAX_N; }
 
 int eig_threads(int64_t n) {
-    // the Jacobi uses GRP (n+1)/2 lanes; the Cholesky and the repacking use all
-    // of them, so small problems get a small workgroup and larger ones 1024 lanes
-    const int N = (int)(n + (n & 1));
-    int t = GRP * (N / 2);
-    if (n >= 32) t = 1024;
+    // the Jacobi uses GRP N2 / 2 lanes (N2 = n rounded up to a power of two); the
+    // Cholesky and the repacking use all of them, so small problems get a small
+    // workgroup and larger ones 1024 lanes
+    const int N2 = eig_pow2((int)n);
+    int t = GRP * (N2 / 2);
+    if (n >= 32) t = eig_bound(eig_rpl((int)n));
     if (t < 64) t = 64;
     if (t > 1024) t = 1024;
     return ((t + 63) / 64) * 64;
@@ -488,22 +555,14 @@ static hipError_t launch_t(int64_t n, const double *Mhi, const double *Mlo, int6
     case R:                                                                                    \
         return launch_rpl<TW, TS, DD, R>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2,     \
                                          max_sweeps, lds, thr, st);
-    switch ((int)((n + GRP - 1) / GRP)) {
-        GSVD_EIG_CASE(1)
+    switch (eig_rpl((int)n)) {
         GSVD_EIG_CASE(2)
-        GSVD_EIG_CASE(3)
         GSVD_EIG_CASE(4)
-        GSVD_EIG_CASE(5)
         GSVD_EIG_CASE(6)
-        GSVD_EIG_CASE(7)
         GSVD_EIG_CASE(8)
-        GSVD_EIG_CASE(9)
         GSVD_EIG_CASE(10)
-        GSVD_EIG_CASE(11)
         GSVD_EIG_CASE(12)
-        GSVD_EIG_CASE(13)
         GSVD_EIG_CASE(14)
-        GSVD_EIG_CASE(15)
         GSVD_EIG_CASE(16)
         default: return hipErrorInvalidValue;
     }
@@ -516,7 +575,8 @@ hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *M
     const size_t lds = eig_lds_bytes(working, n);
     const int thr = eig_threads(n);
     if (n < 1 || n > eig_max_n(working)) return hipErrorInvalidValue;
-    if ((n * n + thr - 1) / thr > MAXREG) return hipErrorInvalidValue;
+    if ((n * n + thr - 1) / thr > eig_maxreg(eig_rpl((int)n))) return hipErrorInvalidValue;
+    if (thr / GRP < eig_pow2((int)n) / 2) return hipErrorInvalidValue;  // one group per pair
     const double tol2 = tol * tol;
     if (working == 1) {
         if (Mlo == nullptr) return hipErrorInvalidValue;
@@ -527,29 +587,36 @@ hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *M
                                          max_sweeps, lds, thr, st);
 }
 
+template <typename TW, typename TS, bool DD, int MAXRPL>
+static hipError_t eig_batched_t(const BatchMat *tab, const int *order, int batch, size_t lds,
+                                int thr, double tol, int max_sweeps, hipStream_t st) {
+    auto k = eig_batched_kernel<TW, TS, DD, MAXRPL>;
+    hipError_t err = hipFuncSetAttribute((const void *)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k, dim3((unsigned)batch), dim3(thr), lds, st, tab, order, batch, tol,
+                       max_sweeps);
+    return hipGetLastError();
+}
+
 hipError_t eig_batched_launch(int working, const BatchMat *tab, const int *order, int batch,
                               int max_n, double tol, int max_sweeps, hipStream_t st) {
     if (batch < 1 || max_n < 1 || max_n > eig_max_n(working)) return hipErrorInvalidValue;
     const size_t lds = eig_lds_bytes(working, max_n);
-    const int thr = eig_threads(max_n);
-    if ((max_n * max_n + thr - 1) / thr > MAXREG) return hipErrorInvalidValue;
-    hipError_t err;
-    if (working == 1) {
-        auto k = eig_batched_kernel<double, double, true, GSVD_KMAX_N_F64 / GRP>;
-        err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-        if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k, dim3((unsigned)batch), dim3(thr), lds, st, tab, order, batch, tol,
-                           max_sweeps);
-    } else {
-        auto k = eig_batched_kernel<float, float, false, GSVD_KMAX_N / GRP>;
-        err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-        if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k, dim3((unsigned)batch), dim3(thr), lds, st, tab, order, batch, tol,
-                           max_sweeps);
-    }
-    return hipGetLastError();
+    // every problem runs with the lanes and register depth of the largest one
+    const bool big = eig_rpl(max_n) > 8;
+    const int thr = big ? eig_bound(16) : eig_threads(max_n);
+    if ((max_n * max_n + thr - 1) / thr > eig_maxreg(big ? 16 : 8)) return hipErrorInvalidValue;
+    if (thr / GRP < eig_pow2(max_n) / 2) return hipErrorInvalidValue;  // one group per pair
+    if (working == 1)
+        return big ? eig_batched_t<double, double, true, 12>(tab, order, batch, lds, thr, tol,
+                                                               max_sweeps, st)
+                   : eig_batched_t<double, double, true, 8>(tab, order, batch, lds, thr, tol,
+                                                              max_sweeps, st);
+    return big ? eig_batched_t<float, float, false, 16>(tab, order, batch, lds, thr, tol,
+                                                         max_sweeps, st)
+               : eig_batched_t<float, float, false, 8>(tab, order, batch, lds, thr, tol,
+                                                        max_sweeps, st);
 }
 
 }  // namespace gsvd
