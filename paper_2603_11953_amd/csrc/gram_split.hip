@@ -70,7 +70,7 @@ SplitPlan split_plan(int64_t m, int64_t n, int S, int64_t slab_rows) {
     if (rps < SP_KT) rps = SP_KT;
     p.rows_per_split = rps;
     p.nsplit = (m + rps - 1) / rps;
-    p.lds_bytes = 2 * 16 * p.nb * sizeof(int) + (size_t)S * 16 * p.nb * SP_CS;
+    p.lds_bytes = (size_t)sp_lds(p.nb, S);
     p.part_bytes = (size_t)p.nsplit * p.npair * 64 * 8 * sizeof(double);
     return p;
 }

@@ -137,91 +137,165 @@ __host__ __device__ constexpr int sp_waves(int nb) {
     return (nb * (nb + 1) / 2 + sp_groups(nb) - 1) / sp_groups(nb);
 }
 
+// Producer wavefronts per workgroup: they load A, keep the column exponents and
+// write the digit planes; the other wavefronts (one per tile) run the products.
+constexpr int SP_PROD = 4;
+constexpr int SP_LDS_MAX = 160 * 1024 - 1024;
+
+__host__ __device__ constexpr int sp_threads(int nb) { return 64 * (sp_waves(nb) + SP_PROD); }
+
+// bytes of one plane buffer (all slices of one chunk) plus its exponents
+__host__ __device__ constexpr int sp_buf_bytes(int nb, int ss) {
+    return ss * 16 * nb * SP_CS + 16 * nb * 4;
+}
+// two buffers (producers one chunk ahead of the consumers) when they fit LDS
+__host__ __device__ constexpr int sp_bufs(int nb, int ss) {
+    return 2 * sp_buf_bytes(nb, ss) + 64 <= SP_LDS_MAX ? 2 : 1;
+}
+__host__ __device__ constexpr int sp_lds(int nb, int ss) {
+    return sp_bufs(nb, ss) * sp_buf_bytes(nb, ss) + 64;
+}
+
 // The partial Gram of slab `split` of one matrix, tiles of workgroup `grp`.
+//
+// Producers (the last SP_PROD wavefronts) take chunk i: lane l of producer
+// wavefront w holds rows 4 (l % 16) .. + 3 of column 16 p + 4 w + l / 16 for
+// every pass p, so the 16 lanes of a DPP row hold one column and agree on its
+// exponent by a DPP max without any barrier.  A column whose exponent grows
+// records the chunk in the buffer's flag (a monotone LDS maximum).  Consumers
+// (one wavefront per tile) take chunk i - 1 from the other buffer: they flush
+// their integer sums when the flag names that chunk (or every 128 chunks),
+// reload their tile's exponents, and run the products.  One barrier per chunk.
+// When two buffers do not fit LDS, producers and consumers alternate on one.
 template <typename T, int NB, int SS>
 __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t lda, int64_t m,
                                                 int n, int64_t rows_per_split, int64_t split,
                                                 int grp, double *__restrict__ part) {
     constexpr bool DD = sizeof(T) == 8;
-    constexpr int SMAX = SS;  // slice count, fixed at compile time
-    constexpr int NW = sp_waves(NB);
-    constexpr int NT = 64 * NW;
+    constexpr int NW = sp_waves(NB);   // consumer wavefronts
     constexpr int N16 = 16 * NB;
     constexpr int NPAIR = NB * (NB + 1) / 2;
-    constexpr int SL = N16 * SP_CS;  // bytes per digit plane
-    constexpr int CPP = NT / 16;     // columns loaded per pass
-    constexpr int NPASS = (N16 + CPP - 1) / CPP;
+    constexpr int SL = N16 * SP_CS;    // bytes per digit plane
+    constexpr int NBUF = sp_bufs(NB, SS);
+    constexpr int BB = sp_buf_bytes(NB, SS);
+    constexpr int NPASS = NB;          // producer passes of 16 columns
+    constexpr bool PREF = NPASS * (int)sizeof(T) <= 32;  // next chunk held in registers
     extern __shared__ unsigned char smem[];
-    int *expo = reinterpret_cast<int *>(smem);  // [N16] current E_j
-    int *need = expo + N16;                     // [N16] this chunk's need
-    signed char *planes = reinterpret_cast<signed char *>(smem + 2 * N16 * sizeof(int));
+    int *flagc = reinterpret_cast<int *>(smem + NBUF * BB);  // [2]
+    auto planes_of = [&](int b) { return reinterpret_cast<signed char *>(smem + b * BB); };
+    auto expo_of = [&](int b) { return reinterpret_cast<int *>(smem + b * BB + SS * SL); };
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wavefront
+    const bool producer = wave >= NW;
     const int64_t r0 = split * rows_per_split;
     const int64_t r1 = (r0 + rows_per_split < m) ? r0 + rows_per_split : m;
     const int nchunk = (int)((r1 - r0 + SP_KT - 1) / SP_KT);
 
-    // this wavefront's tile (I, J), I <= J
+    if (tid < 2) flagc[tid] = 0;
+    __syncthreads();
+
+    // ---------------- producer state
+    const int pcol = 4 * (wave - NW) + (lane >> 4);  // + 16 p
+    const int prow = 4 * (lane & 15);
+    T cur[NPASS][4], nxt[PREF ? NPASS : 1][4];
+    int er[NPASS];
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) er[p] = SP_NOEXP;
+    auto fetch = [&](T (&v)[NPASS][4], int chunk) {
+        const int64_t base = r0 + (int64_t)chunk * SP_KT + prow;
+#pragma unroll
+        for (int p = 0; p < NPASS; ++p) {
+            const int c = 16 * p + pcol;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = base + q;
+                v[p][q] = (c < n && r < r1) ? A[r + (int64_t)c * lda] : (T)0;
+            }
+        }
+    };
+    auto produce = [&](int i, int b) {
+        if constexpr (PREF) {
+            if (i == 0) fetch(cur, 0);
+            if (i + 1 < nchunk) fetch(nxt, i + 1);
+        } else {
+            fetch(cur, i);
+        }
+        signed char *planes = planes_of(b);
+        int *expo = expo_of(b);
+#pragma unroll
+        for (int p = 0; p < NPASS; ++p) {
+            const int c = 16 * p + pcol;
+            int e = SP_NOEXP;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) e = max(e, need_exp((double)cur[p][q]));
+            e = row_max_i(e);  // the 16 lanes of column c
+            const bool grow = e > er[p];
+            if (grow) er[p] = e + SP_HEAD;
+            const int E = er[p];
+            if ((lane & 15) == 0) {
+                expo[c] = E;
+                if (grow) atomicMax(&flagc[b], i + 1);
+            }
+            unsigned long long hi[4], lo[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fixed128((double)cur[p][q], E, hi[q], lo[q]);
+            signed char *pd = planes + c * SP_CS + prow;
+#define GSVD_SPLIT_PLANE(R)                                                                  \
+    if constexpr (R <= SS) *reinterpret_cast<unsigned *>(pd + (R - 1) * SL) = pack4<R>(hi, lo);
+            GSVD_SPLIT_PLANE(1) GSVD_SPLIT_PLANE(2) GSVD_SPLIT_PLANE(3) GSVD_SPLIT_PLANE(4)
+            GSVD_SPLIT_PLANE(5) GSVD_SPLIT_PLANE(6) GSVD_SPLIT_PLANE(7) GSVD_SPLIT_PLANE(8)
+            GSVD_SPLIT_PLANE(9) GSVD_SPLIT_PLANE(10) GSVD_SPLIT_PLANE(11) GSVD_SPLIT_PLANE(12)
+#undef GSVD_SPLIT_PLANE
+        }
+        if constexpr (PREF) {
+#pragma unroll
+            for (int p = 0; p < NPASS; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cur[p][q] = nxt[p][q];
+        }
+    };
+
+    // ---------------- consumer state: this wavefront's tile (I, J), I <= J
     const int pidx = grp * NW + wave;
-    const bool has_tile = pidx < NPAIR;
+    const bool has_tile = !producer && pidx < NPAIR;
     int bi = 0, bj = 0;
     if (has_tile) sp_decode_pair(pidx, NB, bi, bj);
     const int ca = 16 * bi + (lane & 15), cb = 16 * bj + (lane & 15);
     const int koff = 16 * (lane >> 4);
+    int ei[4] = {SP_NOEXP, SP_NOEXP, SP_NOEXP, SP_NOEXP}, ej = SP_NOEXP;
 
-    // loading: pass p covers columns CPP p .. CPP p + CPP - 1; thread t takes
-    // column CPP p + t / 16 and rows 4 (t % 16) .. + 3 of the chunk
-    const int lc = tid >> 4, lr = 4 * (tid & 15);
-    T vals[NPASS][4];
-    auto fetch = [&](int chunk) {
-        const int64_t base = r0 + (int64_t)chunk * SP_KT + lr;
+    v4i diag[SS];
 #pragma unroll
-        for (int p = 0; p < NPASS; ++p) {
-            const int c = CPP * p + lc;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t r = base + q;
-                vals[p][q] = (c < n && r < r1) ? A[r + (int64_t)c * lda] : (T)0;
-            }
-        }
-    };
-
-    v4i diag[SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) diag[s] = v4i{0, 0, 0, 0};
+    for (int s = 0; s < SS; ++s) diag[s] = v4i{0, 0, 0, 0};
 
     // partial slot of this slab's tile: [split][tile][lane][q][hi, lo]
     double *dst = part + (((size_t)split * NPAIR + (has_tile ? pidx : 0)) * 64 + lane) * 8;
-    // flush: add the integer sums (with the current exponents) to the slot
+    // flush: add the integer sums (with the exponents in force) to the slot
     auto flush = [&](bool first) {
-        if (!has_tile) return;
-        const int ej = expo[cb];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int ei = expo[16 * bi + 4 * (lane >> 4) + q];
             dd_t tot{0.0, 0.0};
-            if (ei > SP_NOEXP && ej > SP_NOEXP) {
+            if (ei[q] > SP_NOEXP && ej > SP_NOEXP) {
                 if (DD) {
 #pragma unroll
-                    for (int g0 = 0; g0 < SMAX; g0 += 4) {
-                        {
-                            // exact: |I_s| < 2^31, so the group sum is a
-                            // multiple of 2^-21 below 2^32 (53 bits)
-                            double v = 0.0;
+                    for (int g0 = 0; g0 < SS; g0 += 4) {
+                        // exact: |I_s| < 2^31, so the group sum is a
+                        // multiple of 2^-21 below 2^32 (53 bits)
+                        double v = 0.0;
 #pragma unroll
-                            for (int u = 3; u >= 0; --u)
-                                if (g0 + u < SMAX) v = v * 0x1p-7 + (double)diag[g0 + u][q];
-                            tot = dd_add(tot, dd_t{ldexp(v, -7 * (g0 + 2)), 0.0});
-                        }
+                        for (int u = 3; u >= 0; --u)
+                            if (g0 + u < SS) v = v * 0x1p-7 + (double)diag[g0 + u][q];
+                        tot = dd_add(tot, dd_t{ldexp(v, -7 * (g0 + 2)), 0.0});
                     }
-                    tot.hi = ldexp(tot.hi, ei + ej);
-                    tot.lo = ldexp(tot.lo, ei + ej);
+                    tot.hi = ldexp(tot.hi, ei[q] + ej);
+                    tot.lo = ldexp(tot.lo, ei[q] + ej);
                 } else {
                     double v = 0.0;
 #pragma unroll
-                    for (int s0 = SMAX - 1; s0 >= 0; --s0) v = v * 0x1p-7 + (double)diag[s0][q];
-                    tot.hi = ldexp(v, ei + ej - 14);
+                    for (int s0 = SS - 1; s0 >= 0; --s0) v = v * 0x1p-7 + (double)diag[s0][q];
+                    tot.hi = ldexp(v, ei[q] + ej - 14);
                 }
             }
             if (!first) tot = dd_add(tot, dd_t{dst[2 * q], dst[2 * q + 1]});
@@ -229,85 +303,74 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
             dst[2 * q + 1] = tot.lo;
         }
 #pragma unroll
-        for (int s = 0; s < SMAX; ++s) diag[s] = v4i{0, 0, 0, 0};
+        for (int s = 0; s < SS; ++s) diag[s] = v4i{0, 0, 0, 0};
     };
-
-    for (int c = tid; c < N16; c += NT) expo[c] = SP_NOEXP;
     bool first_flush = true;
     int since_flush = 0;
-    if (nchunk > 0) fetch(0);
-    for (int ch = 0; ch < nchunk; ++ch) {
-        __syncthreads();  // the previous chunk's planes and needs are no longer read
-        // ---- exponents this chunk needs
-#pragma unroll
-        for (int p = 0; p < NPASS; ++p) {
-            const int c = CPP * p + lc;
-            int e = SP_NOEXP;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) e = max(e, need_exp((double)vals[p][q]));
-            e = row_max_i(e);  // the 16 lanes holding column c
-            if ((tid & 15) == 0 && c < N16) need[c] = e;
-        }
-        __syncthreads();
-        int grow = 0;
-        for (int c = tid; c < N16; c += NT) grow |= need[c] > expo[c];
-        grow = __syncthreads_or(grow);
-        if (grow || since_flush == SP_FLUSH_EVERY) {
-            if (since_flush > 0) {
-                flush(first_flush);
-                first_flush = false;
-            }
+    auto consume = [&](int ci, int b) {
+        const bool newexp = flagc[b] == ci + 1;
+        if ((newexp || since_flush == SP_FLUSH_EVERY) && since_flush > 0) {
+            flush(first_flush);
+            first_flush = false;
             since_flush = 0;
-            __syncthreads();  // every wavefront has read the old exponents
-            for (int c = tid; c < N16; c += NT)
-                if (need[c] > expo[c]) expo[c] = need[c] + SP_HEAD;
-            __syncthreads();
         }
-        // ---- digits of the chunk
+        const signed char *planes = planes_of(b);
+        if (newexp) {
+            const int *expo = expo_of(b);
+            ej = expo[cb];
 #pragma unroll
-        for (int p = 0; p < NPASS; ++p) {
-            const int c = CPP * p + lc;
-            if (c < N16) {
-                const int E = expo[c];
-                unsigned long long hi[4], lo[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) fixed128((double)vals[p][q], E, hi[q], lo[q]);
-                signed char *pd = planes + c * SP_CS + lr;
-#define GSVD_SPLIT_PLANE(R)                                                                  \
-    if constexpr (R <= SS) *reinterpret_cast<unsigned *>(pd + (R - 1) * SL) = pack4<R>(hi, lo);
-                GSVD_SPLIT_PLANE(1) GSVD_SPLIT_PLANE(2) GSVD_SPLIT_PLANE(3) GSVD_SPLIT_PLANE(4)
-                GSVD_SPLIT_PLANE(5) GSVD_SPLIT_PLANE(6) GSVD_SPLIT_PLANE(7) GSVD_SPLIT_PLANE(8)
-                GSVD_SPLIT_PLANE(9) GSVD_SPLIT_PLANE(10) GSVD_SPLIT_PLANE(11)
-                GSVD_SPLIT_PLANE(12)
-#undef GSVD_SPLIT_PLANE
-            }
+            for (int q = 0; q < 4; ++q) ei[q] = expo[16 * bi + 4 * (lane >> 4) + q];
         }
-        __syncthreads();
-        if (ch + 1 < nchunk) fetch(ch + 1);  // overlaps the MFMA phase
-
-        // ---- this wavefront's tile: the SS B-operand planes stay in registers,
-        //      each A-operand plane r meets the planes t <= SS - 1 - r
-        if (has_tile) {
-            v4i bop[SS];
+        // the SS B-operand planes stay in registers; A-operand plane r meets t <= SS - 1 - r
+        v4i bop[SS];
 #pragma unroll
-            for (int t = 0; t < SS; ++t)
-                bop[t] = *reinterpret_cast<const v4i *>(planes + t * SL + cb * SP_CS + koff);
+        for (int t = 0; t < SS; ++t)
+            bop[t] = *reinterpret_cast<const v4i *>(planes + t * SL + cb * SP_CS + koff);
 #pragma unroll
-            for (int r = 0; r < SS; ++r) {
-                const v4i aop = *reinterpret_cast<const v4i *>(planes + r * SL + ca * SP_CS + koff);
+        for (int r = 0; r < SS; ++r) {
+            const v4i aop = *reinterpret_cast<const v4i *>(planes + r * SL + ca * SP_CS + koff);
 #pragma unroll
-                for (int t = 0; t < SS - r; ++t)
-                    diag[r + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, bop[t], diag[r + t], 0,
-                                                                       0, 0);
-            }
+            for (int t = 0; t < SS - r; ++t)
+                diag[r + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, bop[t], diag[r + t], 0, 0, 0);
         }
         ++since_flush;
+    };
+
+    // The two roles run separate loops (so their register state need not
+    // coexist), with the same number of barriers per chunk: NBUF == 2, one
+    // barrier per iteration over nchunk + 1 iterations; NBUF == 1, two per chunk.
+    if (producer) {
+        if constexpr (NBUF == 2) {
+            for (int it = 0; it <= nchunk; ++it) {
+                if (it < nchunk) produce(it, it & 1);
+                __syncthreads();
+            }
+        } else {
+            for (int it = 0; it < nchunk; ++it) {
+                produce(it, 0);
+                __syncthreads();
+                __syncthreads();
+            }
+        }
+    } else {
+        if constexpr (NBUF == 2) {
+            for (int it = 0; it <= nchunk; ++it) {
+                if (has_tile && it >= 1) consume(it - 1, (it - 1) & 1);
+                __syncthreads();
+            }
+        } else {
+            for (int it = 0; it < nchunk; ++it) {
+                __syncthreads();
+                if (has_tile) consume(it, 0);
+                __syncthreads();
+            }
+        }
     }
-    flush(first_flush);
+    if (has_tile) flush(first_flush);
 }
 
 template <typename T, int NB, int SS>
-__global__ void __launch_bounds__(64 * sp_waves(NB))
+__global__ void __launch_bounds__(sp_threads(NB))
 gram_split_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int64_t rows_per_split,
                   double *__restrict__ part) {
     gram_split_body<T, NB, SS>(A, lda, m, n, rows_per_split, blockIdx.y, blockIdx.x, part);
@@ -315,7 +378,7 @@ gram_split_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int64_
 
 // Batched: blockIdx.z picks the problem order[first + z], blockIdx.y its slab.
 template <typename T, int NB, int SS>
-__global__ void __launch_bounds__(64 * sp_waves(NB))
+__global__ void __launch_bounds__(sp_threads(NB))
 gram_split_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order,
                           int first) {
     const BatchMat &d = tab[order[first + blockIdx.z]];
@@ -334,7 +397,7 @@ static hipError_t split_partial_inst(int64_t m, int64_t n, const T *A, int64_t l
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)p.lds_bytes);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k, dim3(sp_groups(NB), (unsigned)p.nsplit), dim3(64 * sp_waves(NB)),
+    hipLaunchKernelGGL(k, dim3(sp_groups(NB), (unsigned)p.nsplit), dim3(sp_threads(NB)),
                        p.lds_bytes, st, A, lda, m, (int)n, p.rows_per_split, (double *)part);
     return hipGetLastError();
 }
@@ -348,7 +411,7 @@ static hipError_t split_batched_inst(const BatchMat *tab, const int *order, int 
                                          (int)p.lds_bytes);
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k, dim3(sp_groups(NB), (unsigned)max_nsplit, (unsigned)count),
-                       dim3(64 * sp_waves(NB)), p.lds_bytes, st, tab, order, first);
+                       dim3(sp_threads(NB)), p.lds_bytes, st, tab, order, first);
     return hipGetLastError();
 }
 
