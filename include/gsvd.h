@@ -44,14 +44,14 @@ enum {
     GSVD_GRAM_AUTO = 0,   /* library choice (currently PLAIN) */
     GSVD_GRAM_PLAIN = 1,  /* FP32 A: exact FP64 products, FP64 sums; FP64 A: double-double */
     GSVD_GRAM_SPLIT = 2   /* operand splitting: per slab of rows and column, a power-of-two
-                             exponent above the column's largest entry (raised, with two
+                             exponent E above the column's largest entry (raised, with two
                              bits of headroom, when a larger entry arrives); each entry cut
-                             into n_slices base-128 digits of its two's-complement fixed-point
-                             form; digit pairs r + t <= n_slices + 1 multiplied exactly on the
-                             int8 matrix cores, sums in double-double (FP64 A) or FP64 (FP32
-                             A).  Each entry is represented to within 2^(-7 n_slices) of its
-                             column exponent, i.e. at most 2^(4 - 7 n_slices) of the slab's
-                             column maximum */
+                             into n_slices balanced base-256 digits (signed bytes) of its
+                             96-bit fixed-point form; digit pairs r + t <= n_slices + 1
+                             multiplied exactly on the int8 matrix cores, sums in
+                             double-double (FP64 A) or FP64 (FP32 A).  Each entry is
+                             represented to within about 2^(-8 n_slices) of 2^E, i.e. at most
+                             2^(6 - 8 n_slices) of the slab's column maximum */
 };
 
 /* eigensolver of Alg. 1 step 3 */

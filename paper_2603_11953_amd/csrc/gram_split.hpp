@@ -2,26 +2,27 @@
 // (the "split" form of Alg. 1 steps 1-2).
 //
 // A workgroup owns a slab of rows and keeps, per column j, an exponent E_j
-// with |a_kj| < 2^(E_j - 1) for every row seen so far.  Each entry is written
-// as a signed 128-bit fixed-point number F = a 2^(128 - E_j) (|F| < 2^127) and
-// cut into base-128 digits of F's two's-complement form,
-//     a = 2^E_j sum_{r=1..S} d_r 2^(-7 r) + tail,  d_1 in [-64, 63], d_r in [0, 127] (r > 1),
-// 0 <= tail < 2^(E_j - 7 S).  Digit r sits at bits 128 - 7 r .. 134 - 7 r of F
-// whatever S is, so each digit is one bitfield extract.  The contribution of
-// the rows to M(i, j) is
-//     2^(E_i + E_j) sum_{s=2..S+1} 2^(-7 s) I_s,   I_s = sum_{r+t=s} sum_k d_r,ki d_t,kj,
+// with |a_kj| < 2^(E_j - 3) for every row seen so far.  Each entry is written
+// as the 96-bit fixed-point integer X = sign(a) floor(|a| 2^(96 - E_j))
+// (|X| < 2^93; three exact FP64 floor steps give its 32-bit words) and cut into
+// balanced base-256 digits: adding 0x80 to every byte of X (with carries)
+// and taking each byte minus 128 gives
+//     a = 2^E_j sum_{r=1..S} d_r 2^(-8 r) + tail,  d_r in [-128, 127],
+// |tail| <= (128 / 255) 2^(E_j - 8 S) + 2^(E_j - 96), every digit a signed byte.
+// The contribution of the rows to M(i, j) is
+//     2^(E_i + E_j) sum_{s=2..S+1} 2^(-8 s) I_s,   I_s = sum_{r+t=s} sum_k d_r,ki d_t,kj,
 // keeping the slice pairs r + t <= S + 1 (the dropped pairs are below the last
 // kept digit).  The I_s are exact integers accumulated by
 // v_mfma_i32_16x16x64_i8 in int32 registers across chunks of 64 rows.
 //
 // The integer sums stay in registers until an exponent has to grow (a chunk
-// holds an entry >= 2^(E_j - 1)), until 128 chunks have been added (the int32
-// bound: 128 chunks x 64 rows x at most 16 pairs x 127^2 < 2^31), or until the
-// slab ends.  Then
-// they are "flushed": combined exactly (Horner over groups of four diagonals,
-// each group exact in FP64) into double-double (FP64 A) or FP64 (FP32 A), and
-// added to the workgroup's own slot of the partial-sum buffer.  A new exponent
-// is set two bits above what the chunk needs, so flushes are rare.
+// holds an entry >= 2^(E_j - 3)), until 128 chunks have been added (the int32
+// bound: 128 chunks x 64 rows x at most 12 pairs x 128^2 < 2^31), or until the
+// slab ends.  Then they are "flushed": combined exactly (Horner over groups of
+// three diagonals, each group exact in FP64) into double-double (FP64 A) or
+// FP64 (FP32 A), and added to the workgroup's own slot of the partial-sum
+// buffer.  A new exponent is set two bits above what the chunk needs, so
+// flushes are rare.
 //
 // Layout: the chunk's digits sit in LDS as int8 planes, column-major (the 64
 // rows of a column are 64 contiguous bytes, columns 80 bytes apart).  A 16x16
@@ -78,55 +79,55 @@ __device__ __forceinline__ int row_max_i(int x) {
     return x;
 }
 
-// exponent needed by a: the smallest e with |a| < 2^(e - 1); SP_NOEXP for a = 0
-__device__ __forceinline__ int need_exp(double a) { return a != 0.0 ? ilogb(a) + 2 : SP_NOEXP; }
+// exponent needed by a: the smallest e with |a| < 2^(e - 3); SP_NOEXP for a = 0
+__device__ __forceinline__ int need_exp(double a) { return a != 0.0 ? ilogb(a) + 4 : SP_NOEXP; }
 
-// F = a 2^(128 - E) truncated toward minus infinity, as two's complement (hi, lo)
-__device__ __forceinline__ void fixed128(double a, int E, unsigned long long &hi,
-                                         unsigned long long &lo) {
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(a);
-    const int ea = (int)((bits >> 52) & 0x7ff);
-    unsigned long long mant = bits & 0xfffffffffffffull;
-    if (ea != 0) mant |= 1ull << 52;
-    // |a| = mant 2^(max(ea, 1) - 1075); |F| = mant 2^sh
-    const int sh = (ea != 0 ? ea : 1) - 1075 + 128 - E;
-    unsigned long long h = 0, l = 0;
-    if (mant != 0 && sh > -53) {
-        if (sh >= 64) {
-            h = mant << (sh - 64);
-        } else if (sh > 0) {
-            l = mant << sh;
-            h = mant >> (64 - sh);
-        } else {
-            l = mant >> (-sh);
-        }
+// The balanced base-256 digits of a (exponent E, |a| < 2^(E - 3)) as the bytes
+// of three words, digit 1 in the top byte of w2 and digit 12 in the low byte of
+// w0.  |a| 2^(96 - E) is taken 32 bits at a time: each floor and subtraction is
+// exact (the remainder keeps a subset of the 53 bits of |a|), so the words are
+// floor(|a| 2^(96 - E)); a negative a negates the 96-bit integer.
+template <int NW3>
+__device__ __forceinline__ void balanced96(double a, int E, unsigned &w2, unsigned &w1,
+                                           unsigned &w0) {
+    const double x = __builtin_fabs(a);
+    const double y0 = ldexp(x, 32 - E);  // < 2^29
+    const double f0 = __builtin_floor(y0);
+    unsigned h = (unsigned)f0, mid = 0, low = 0;
+    if constexpr (NW3 >= 2) {
+        const double y1 = (y0 - f0) * 0x1p32;
+        const double f1 = __builtin_floor(y1);
+        mid = (unsigned)f1;
+        if constexpr (NW3 >= 3) low = (unsigned)__builtin_floor((y1 - f1) * 0x1p32);
     }
-    if (bits >> 63) {  // negate the 128-bit value
-        h = ~h;
-        l = ~l;
-        l += 1;
-        if (l == 0) h += 1;
+    unsigned long long lo64 = ((unsigned long long)mid << 32) | low;
+    if (a < 0.0) {  // two's complement of the 96-bit value
+        lo64 = ~lo64 + 1ull;
+        h = ~h + (lo64 == 0ull ? 1u : 0u);
     }
-    hi = h;
-    lo = l;
+    // + 0x80 in every byte (carries through the words), then each byte ^ 0x80
+    const unsigned long long c64 = 0x8080808080808080ull;
+    const unsigned long long s64 = lo64 + c64;
+    const unsigned carry = s64 < lo64 ? 1u : 0u;
+    w2 = (h + 0x80808080u + carry) ^ 0x80808080u;
+    const unsigned long long d64 = s64 ^ c64;
+    w1 = (unsigned)(d64 >> 32);
+    w0 = (unsigned)d64;
 }
 
-// digit r (1-based) of F: bits 128 - 7 r .. 134 - 7 r, the first one signed
-template <int R>
-__device__ __forceinline__ int digit(unsigned long long hi, unsigned long long lo) {
-    constexpr int p = 128 - 7 * R;  // lowest bit of the digit
-    if (R == 1) return (int)((long long)hi >> 57);
-    if (p >= 64) return (int)((hi >> (p - 64)) & 127ull);
-    if (p + 7 <= 64) return (int)((lo >> p) & 127ull);
-    return (int)(((lo >> p) | (hi << (64 - p))) & 127ull);
-}
-
-template <int R>
-__device__ __forceinline__ unsigned pack4(const unsigned long long *hi, const unsigned long long *lo) {
-    unsigned w = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) w |= ((unsigned)digit<R>(hi[q], lo[q]) & 0xffu) << (8 * q);
-    return w;
+// 4x4 byte transpose: o_j byte q = w_q byte j (v_perm_b32 picks bytes of
+// {S0 (high word), S1 (low word)})
+__device__ __forceinline__ void transpose4(unsigned w0, unsigned w1, unsigned w2, unsigned w3,
+                                           unsigned &o0, unsigned &o1, unsigned &o2,
+                                           unsigned &o3) {
+    const unsigned t0 = __builtin_amdgcn_perm(w1, w0, 0x05010400u);
+    const unsigned t1 = __builtin_amdgcn_perm(w1, w0, 0x07030602u);
+    const unsigned t2 = __builtin_amdgcn_perm(w3, w2, 0x05010400u);
+    const unsigned t3 = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
+    o0 = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+    o1 = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+    o2 = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+    o3 = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
 }
 
 // Tiles of the upper triangle per workgroup: one per wavefront, at most 12
@@ -238,16 +239,22 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
                 expo[c] = E;
                 if (grow) atomicMax(&flagc[b], i + 1);
             }
-            unsigned long long hi[4], lo[4];
+            constexpr int NW3 = (SS + 3) / 4;  // 32-bit digit words needed
+            unsigned w[3][4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) fixed128((double)cur[p][q], E, hi[q], lo[q]);
+            for (int q = 0; q < 4; ++q) balanced96<NW3>((double)cur[p][q], E, w[0][q], w[1][q], w[2][q]);
             signed char *pd = planes + c * SP_CS + prow;
-#define GSVD_SPLIT_PLANE(R)                                                                  \
-    if constexpr (R <= SS) *reinterpret_cast<unsigned *>(pd + (R - 1) * SL) = pack4<R>(hi, lo);
-            GSVD_SPLIT_PLANE(1) GSVD_SPLIT_PLANE(2) GSVD_SPLIT_PLANE(3) GSVD_SPLIT_PLANE(4)
-            GSVD_SPLIT_PLANE(5) GSVD_SPLIT_PLANE(6) GSVD_SPLIT_PLANE(7) GSVD_SPLIT_PLANE(8)
-            GSVD_SPLIT_PLANE(9) GSVD_SPLIT_PLANE(10) GSVD_SPLIT_PLANE(11) GSVD_SPLIT_PLANE(12)
-#undef GSVD_SPLIT_PLANE
+#pragma unroll
+            for (int k = 0; k < NW3; ++k) {
+                unsigned o[4];
+                transpose4(w[k][0], w[k][1], w[k][2], w[k][3], o[0], o[1], o[2], o[3]);
+                // word k holds digits 4 k + 1 (top byte) .. 4 k + 4 (low byte)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = 4 * k + (3 - j);  // zero-based digit index of byte j
+                    if (r < SS) *reinterpret_cast<unsigned *>(pd + r * SL) = o[j];
+                }
+            }
         }
         if constexpr (PREF) {
 #pragma unroll
@@ -280,22 +287,22 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
             if (ei[q] > SP_NOEXP && ej > SP_NOEXP) {
                 if (DD) {
 #pragma unroll
-                    for (int g0 = 0; g0 < SS; g0 += 4) {
+                    for (int g0 = 0; g0 < SS; g0 += 3) {
                         // exact: |I_s| < 2^31, so the group sum is a
-                        // multiple of 2^-21 below 2^32 (53 bits)
+                        // multiple of 2^-16 below 2^32 (48 bits)
                         double v = 0.0;
 #pragma unroll
-                        for (int u = 3; u >= 0; --u)
-                            if (g0 + u < SS) v = v * 0x1p-7 + (double)diag[g0 + u][q];
-                        tot = dd_add(tot, dd_t{ldexp(v, -7 * (g0 + 2)), 0.0});
+                        for (int u = 2; u >= 0; --u)
+                            if (g0 + u < SS) v = v * 0x1p-8 + (double)diag[g0 + u][q];
+                        tot = dd_add(tot, dd_t{ldexp(v, -8 * (g0 + 2)), 0.0});
                     }
                     tot.hi = ldexp(tot.hi, ei[q] + ej);
                     tot.lo = ldexp(tot.lo, ei[q] + ej);
                 } else {
                     double v = 0.0;
 #pragma unroll
-                    for (int s0 = SS - 1; s0 >= 0; --s0) v = v * 0x1p-7 + (double)diag[s0][q];
-                    tot.hi = ldexp(v, ei[q] + ej - 14);
+                    for (int s0 = SS - 1; s0 >= 0; --s0) v = v * 0x1p-8 + (double)diag[s0][q];
+                    tot.hi = ldexp(v, ei[q] + ej - 16);
                 }
             }
             if (!first) tot = dd_add(tot, dd_t{dst[2 * q], dst[2 * q + 1]});

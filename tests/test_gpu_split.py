@@ -1,11 +1,12 @@
 """Parity of the operand-split Gram (integer slices on the int8 matrix cores) with the oracle.
 
 Error model of the split form.  Rows are processed in slabs (the same slab
-plan as the library: about m / 1024 rows, rounded up to 64); within a slab the
-exponent E_j of column j never exceeds ilogb(slab max of column j) + 4.  Each
-entry is cut to S base-128 digits with a tail below 2^(E - 7 S), and digit pairs
-r + t > S + 1 are dropped (sum below (S + 1) 2^(E_i + E_j - 7 S)), so a row adds
-an error of at most (S + 3) 2^(E_i + E_j - 7 S), plus double-double rounding.
+plan as the library: about m / 1024 rows, rounded up to 64, unless a slab
+height is given); within a slab the exponent E_j of column j never exceeds
+ilogb(slab max of column j) + 6.  Each entry is cut to S balanced base-256
+digits with a tail below (128 / 255) 2^(E - 8 S) + 2^(E - 96), and digit pairs
+r + t > S + 1 are dropped (sum below S 2^(E_i + E_j - 8 S - 2)), so a row adds
+an error of at most (S + 3) 2^(E_i + E_j - 8 S), plus double-double rounding.
 """
 import numpy as np
 import pytest
@@ -30,9 +31,9 @@ def _split_bound(A, S):
     Ap = np.vstack([A, np.zeros((pad, n))])
     smax = Ap.reshape(-1, rps, n).max(axis=1)  # slab column maxima
     with np.errstate(divide="ignore"):
-        e = np.where(smax > 0, np.floor(np.log2(np.where(smax > 0, smax, 1.0))) + 4, -np.inf)
+        e = np.where(smax > 0, np.floor(np.log2(np.where(smax > 0, smax, 1.0))) + 6, -np.inf)
     p2 = np.where(np.isfinite(e), 2.0 ** e, 0.0)  # 2^E per slab and column
-    return (S + 3) * 2.0 ** (-7 * S) * rps * (p2.T @ p2)
+    return (S + 3) * 2.0 ** (-8 * S) * rps * (p2.T @ p2)
 
 
 def _gram_split(A, S):
@@ -42,8 +43,8 @@ def _gram_split(A, S):
 
     import paper_2603_11953_amd as gs
     w = gs.GSVD_F64 if A.dtype == np.float64 else gs.GSVD_F32
-    o = gs.opts(w, gs.GSVD_GRAM_SPLIT, n_slices=S)
     m, n = A.shape
+    o = gs.opts(w, gs.GSVD_GRAM_SPLIT, n_slices=S, slab_rows=_slab_rows(m))
     dA = to_dev(A)
     Mhi = gs.colmajor_empty(n, n, torch.float64, dA.device)
     Mlo = gs.colmajor_empty(n, n, torch.float64, dA.device)
@@ -79,9 +80,9 @@ def test_split_gram_exact_on_short_integer_entries():
     """Entries that fit in the first few digits are cut without a tail, and when every pair of
     non-zero digits is kept the Gram of such a matrix must be exact."""
     rng = np.random.default_rng(5)
-    # 20-bit integers times 2^c: a column's exponent is at most c + 24, so its entries
-    # sit in digits 1..4 (bits above E - 28 <= c - 4, two's complement included);
-    # S = 7 keeps every pair r + t <= 8, i.e. all 16 pairs of those digits
+    # 20-bit integers times 2^c: a column's exponent is at most c + 25, so the 96-bit
+    # fixed-point value of every entry has its low 71 bits zero and only digits 1..4
+    # can be non-zero; S = 7 keeps every pair r + t <= 8, i.e. all 16 pairs of them
     A = rng.integers(-(2 ** 20), 2 ** 20, size=(3000, 24)).astype(np.float64)
     A *= 2.0 ** rng.integers(-30, 30, size=24)[None, :]
     A = np.asfortranarray(A)
