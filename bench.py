@@ -304,6 +304,7 @@ def main():
     plain = measure(gs.GSVD_GRAM_PLAIN)
     log("split form")
     split = measure(gs.GSVD_GRAM_SPLIT)
+    split_cfg = gs.gram_config(m, n, gs.GSVD_F64, gs.GSVD_GRAM_SPLIT)
 
     flops = m * n * (n + 1) + 2 * m * n * n
     gflops = flops / (plain["ms_step"] * 1e-3) / 1e9
@@ -337,7 +338,8 @@ def main():
         "gram_hbm_gbps": round(gram_bytes / (plain["ms_gram"] * 1e-3) / 1e9, 2),
         "phases_ms": phases(plain),
         "split": {
-            "gram": "int8-slices-10 (operand split on the int8 matrix cores, dd sums)",
+            "gram": f"int8-slices-{split_cfg['n_slices']} (operand split on the int8 matrix cores, dd sums)",
+            "slab_rows": split_cfg["slab_rows"],
             "ms_per_step": round(split["ms_step"], 5),
             "value": round(flops / (split["ms_step"] * 1e-3) / 1e9, 3),
             "gram_hbm_gbps": round(gram_bytes / (split["ms_gram"] * 1e-3) / 1e9, 2),

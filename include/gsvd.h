@@ -137,6 +137,18 @@ int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda,
  * 10 o, 11 stream.
  * ------------------------------------------------------------------------- */
 size_t gsvd_gram_workspace_size(int64_t m, int64_t n, const gsvd_opts *o);
+
+/*
+ * gsvd_gram_config: the launch shape gsvd_gram (and the Gram stage of
+ * gsvd_thin) takes for this (m, n, o), resolved from the options and the
+ * tuning table, without running anything.  Writes the slab height (rows of A
+ * per partial sum) to *slab_rows, the number of slabs to *n_slabs and, for
+ * GSVD_GRAM_SPLIT, the int8 slice count to *n_slices (0 for the plain form).
+ * Any output pointer may be NULL.  Returns 0, or -(position) of a bad argument
+ * (1 m, 2 n, 3 o), or GSVD_ERR_UNSUPPORTED as gsvd_gram would.
+ */
+int gsvd_gram_config(int64_t m, int64_t n, const gsvd_opts *o, int64_t *slab_rows,
+                     int64_t *n_slabs, int *n_slices);
 int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda,
               double *dMhi, double *dMlo, int64_t ldm,
               void *work, size_t work_bytes, const gsvd_opts *o, void *stream);

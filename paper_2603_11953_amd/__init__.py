@@ -20,7 +20,7 @@ __all__ = [
     "GSVD_EIG_AUTO", "GSVD_EIG_JACOBI2", "GSVD_EIG_CHOL_JACOBI1", "GSVD_WANT_U", "GSVD_MAX_N",
     "GsvdOpts", "GsvdError", "lib", "lib_path", "opts", "thin", "gram", "eig", "u_recover",
     "gsvd_opts_default", "gsvd_status_string", "gsvd_thin", "gsvd_thin_workspace_size",
-    "gsvd_gram", "gsvd_gram_workspace_size", "gsvd_eig", "gsvd_eig_workspace_size",
+    "gsvd_gram", "gsvd_gram_workspace_size", "gsvd_gram_config", "gram_config", "gsvd_eig", "gsvd_eig_workspace_size",
     "gsvd_u_recover", "gsvd_thin_batched", "gsvd_thin_batched_workspace_size", "thin_batched",
     "Batch",
 ]
@@ -78,6 +78,8 @@ def _load() -> ctypes.CDLL:
     L.gsvd_thin.restype = ci
     L.gsvd_gram_workspace_size.argtypes = [i64, i64, op]
     L.gsvd_gram_workspace_size.restype = sz
+    L.gsvd_gram_config.argtypes = [i64, i64, op, vp, vp, vp]
+    L.gsvd_gram_config.restype = ci
     L.gsvd_gram.argtypes = [i64, i64, vp, i64, vp, vp, i64, vp, sz, op, vp]
     L.gsvd_gram.restype = ci
     L.gsvd_eig_workspace_size.argtypes = [i64, op]
@@ -101,6 +103,7 @@ gsvd_thin = lib.gsvd_thin
 gsvd_thin_workspace_size = lib.gsvd_thin_workspace_size
 gsvd_gram = lib.gsvd_gram
 gsvd_gram_workspace_size = lib.gsvd_gram_workspace_size
+gsvd_gram_config = lib.gsvd_gram_config
 gsvd_eig = lib.gsvd_eig
 gsvd_eig_workspace_size = lib.gsvd_eig_workspace_size
 gsvd_u_recover = lib.gsvd_u_recover
@@ -110,6 +113,18 @@ gsvd_thin_batched_workspace_size = lib.gsvd_thin_batched_workspace_size
 
 def gsvd_status_string(code: int) -> str:
     return lib.gsvd_status_string(int(code)).decode()
+
+
+def gram_config(m: int, n: int, working: int = GSVD_F64, gram: int = GSVD_GRAM_AUTO,
+                **kw) -> dict:
+    """The Gram launch shape the library resolves for (m, n) and these options:
+    slab height, slab count and (split form) int8 slice count."""
+    o = opts(working, gram, **kw)
+    rows, slabs, sl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+    rc = lib.gsvd_gram_config(m, n, ctypes.byref(o), ctypes.addressof(rows),
+                              ctypes.addressof(slabs), ctypes.addressof(sl))
+    _check(rc, "gsvd_gram_config")
+    return {"slab_rows": rows.value, "n_slabs": slabs.value, "n_slices": sl.value}
 
 
 def opts(working: int, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, *,

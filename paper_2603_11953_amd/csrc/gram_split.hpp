@@ -140,10 +140,14 @@ __host__ __device__ constexpr int sp_waves(int nb) {
 
 // Producer wavefronts per workgroup: they load A, keep the column exponents and
 // write the digit planes; the other wavefronts (one per tile) run the products.
-constexpr int SP_PROD = 4;
+// The producers fill the workgroup up to 16 wavefronts, at most one per four
+// columns (each producer wavefront takes four columns per pass).
+__host__ __device__ constexpr int sp_prod(int nb) {
+    return (16 - sp_waves(nb)) < 4 * nb ? (16 - sp_waves(nb)) : 4 * nb;
+}
 constexpr int SP_LDS_MAX = 160 * 1024 - 1024;
 
-__host__ __device__ constexpr int sp_threads(int nb) { return 64 * (sp_waves(nb) + SP_PROD); }
+__host__ __device__ constexpr int sp_threads(int nb) { return 64 * (sp_waves(nb) + sp_prod(nb)); }
 
 // bytes of one plane buffer (all slices of one chunk) plus its exponents
 __host__ __device__ constexpr int sp_buf_bytes(int nb, int ss) {
@@ -159,9 +163,9 @@ __host__ __device__ constexpr int sp_lds(int nb, int ss) {
 
 // The partial Gram of slab `split` of one matrix, tiles of workgroup `grp`.
 //
-// Producers (the last SP_PROD wavefronts) take chunk i: lane l of producer
-// wavefront w holds rows 4 (l % 16) .. + 3 of column 16 p + 4 w + l / 16 for
-// every pass p, so the 16 lanes of a DPP row hold one column and agree on its
+// Producers (the last sp_prod(NB) wavefronts) take chunk i: lane l of producer
+// wavefront w holds rows 4 (l % 16) .. + 3 of column 4 P p + 4 w + l / 16 for
+// every pass p (P producer wavefronts), so the 16 lanes of a DPP row hold one column and agree on its
 // exponent by a DPP max without any barrier.  A column whose exponent grows
 // records the chunk in the buffer's flag (a monotone LDS maximum).  Consumers
 // (one wavefront per tile) take chunk i - 1 from the other buffer: they flush
@@ -179,7 +183,8 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
     constexpr int SL = N16 * SP_CS;    // bytes per digit plane
     constexpr int NBUF = sp_bufs(NB, SS);
     constexpr int BB = sp_buf_bytes(NB, SS);
-    constexpr int NPASS = NB;          // producer passes of 16 columns
+    constexpr int CPP = 4 * sp_prod(NB);            // columns per producer pass
+    constexpr int NPASS = (N16 + CPP - 1) / CPP;  // producer passes
     constexpr bool PREF = NPASS * (int)sizeof(T) <= 32;  // next chunk held in registers
     extern __shared__ unsigned char smem[];
     int *flagc = reinterpret_cast<int *>(smem + NBUF * BB);  // [2]
@@ -198,7 +203,7 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
     __syncthreads();
 
     // ---------------- producer state
-    const int pcol = 4 * (wave - NW) + (lane >> 4);  // + 16 p
+    const int pcol = 4 * (wave - NW) + (lane >> 4);  // + CPP p
     const int prow = 4 * (lane & 15);
     T cur[NPASS][4], nxt[PREF ? NPASS : 1][4];
     int er[NPASS];
@@ -208,7 +213,7 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
         const int64_t base = r0 + (int64_t)chunk * SP_KT + prow;
 #pragma unroll
         for (int p = 0; p < NPASS; ++p) {
-            const int c = 16 * p + pcol;
+            const int c = CPP * p + pcol;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t r = base + q;
@@ -227,7 +232,8 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
         int *expo = expo_of(b);
 #pragma unroll
         for (int p = 0; p < NPASS; ++p) {
-            const int c = 16 * p + pcol;
+            const int c = CPP * p + pcol;
+            if (CPP * (p + 1) > N16 && c >= N16) continue;  // a whole DPP row: uniform in the row
             int e = SP_NOEXP;
 #pragma unroll
             for (int q = 0; q < 4; ++q) e = max(e, need_exp((double)cur[p][q]));

@@ -84,6 +84,30 @@ size_t gsvd_gram_workspace_size(int64_t m, int64_t n, const gsvd_opts *o) {
     return align_up(gram_part_bytes(m, n, o, false));
 }
 
+int gsvd_gram_config(int64_t m, int64_t n, const gsvd_opts *o, int64_t *slab_rows,
+                     int64_t *n_slabs, int *n_slices) {
+    if (m < 1) return -1;
+    if (n < 1 || n > GSVD_MAX_N || n > m) return -2;
+    if (int e = check_opts(o, 3)) return e;
+    if (int e = check_supported(o)) return e;
+    int64_t rows, slabs;
+    int S = 0;
+    if (use_split(o)) {
+        const SplitPlan p = split_plan_of(o, m, n, false);
+        rows = p.rows_per_split;
+        slabs = p.nsplit;
+        S = p.S;
+    } else {
+        const GramPlan p = gram_plan_of(o, m, n, false);
+        rows = p.rows_per_split;
+        slabs = p.nsplit;
+    }
+    if (slab_rows) *slab_rows = rows;
+    if (n_slabs) *n_slabs = slabs;
+    if (n_slices) *n_slices = S;
+    return GSVD_OK;
+}
+
 int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda, double *dMhi, double *dMlo,
               int64_t ldm, void *work, size_t work_bytes, const gsvd_opts *o, void *stream) {
     if (m < 1) return -1;

@@ -50,6 +50,31 @@ def test_workspace_sizes_positive_and_aligned():
             assert t > 0 and t % 256 == 0 and g % 256 == 0 and t >= g + 2 * n * n * 8
 
 
+def test_gram_config_resolves_the_launch_shape():
+    for w in (gs.GSVD_F32, gs.GSVD_F64):
+        smax = 12 if w == gs.GSVD_F64 else 8
+        for m, n in ((64, 1), (2000, 20), (1_000_000, 64), (4_000_000, 128)):
+            for gram in (gs.GSVD_GRAM_PLAIN, gs.GSVD_GRAM_SPLIT):
+                c = gs.gram_config(m, n, w, gram)
+                # the slabs cover the rows once: none is empty
+                assert c["slab_rows"] >= 1 and c["n_slabs"] >= 1
+                assert c["slab_rows"] * c["n_slabs"] >= m > c["slab_rows"] * (c["n_slabs"] - 1)
+                if gram == gs.GSVD_GRAM_PLAIN:
+                    assert c["n_slices"] == 0
+                else:
+                    assert 1 <= c["n_slices"] <= smax
+                    assert gs.gram_config(m, n, w, gram, n_slices=3)["n_slices"] == 3
+            c = gs.gram_config(1_000_000, 64, w, gs.GSVD_GRAM_SPLIT, slab_rows=4096)
+            assert c["slab_rows"] == 4096 and c["n_slabs"] == -(-1_000_000 // 4096)
+    o = gs.opts(gs.GSVD_F64)
+    out = ctypes.c_int64()
+    assert gs.gsvd_gram_config(0, 4, ctypes.byref(o), None, None, None) == -1
+    assert gs.gsvd_gram_config(3, 4, ctypes.byref(o), ctypes.addressof(out), None, None) == -2
+    assert gs.gsvd_gram_config(10, 4, None, None, None, None) == -3
+    o = gs.opts(gs.GSVD_F32, gs.GSVD_GRAM_SPLIT, n_slices=9)
+    assert gs.gsvd_gram_config(1000, 4, ctypes.byref(o), None, None, None) == -101
+
+
 FAKE = 0x7F0000000000  # never dereferenced: validation fails first
 
 
