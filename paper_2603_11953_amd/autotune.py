@@ -7,7 +7,8 @@ paper_2603_11953_amd/build.py``).
 Slab height (rows of A per Gram workgroup).  For every working precision, Gram
 form (plain / split), call kind (one problem / batched), n bucket and m bucket,
 the Gram stage is timed through the C-ABI over a ladder of slab heights on
-seeded Gaussian inputs, and the fastest height is kept.
+seeded Gaussian inputs (each height over at least 10 ms of work, best of three
+passes that alternate over the ladder), and the fastest height is kept.
 
 Slice count of the split Gram.  A perturbation dM of the Gram with
 |dM_ij| <= eps sqrt(M_ii M_jj) moves the eigenvalues of the column-scaled Gram
@@ -61,6 +62,23 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def _best(fns, quick):
+    """Fastest of several launch shapes: each is timed over at least 10 ms of
+    work (5 ms with --quick), and the passes over the shapes alternate, so a
+    clock or cache transient does not favour one shape; the best pass counts."""
+    target = 5.0 if quick else 10.0
+    reps = {}
+    for k, fn in fns.items():
+        once = _time(fn, 2)
+        reps[k] = max(5, min(2000, int(target / max(once, 1e-3))))
+    best = {k: float("inf") for k in fns}
+    for _ in range(2 if quick else 3):
+        for k, fn in fns.items():
+            best[k] = min(best[k], _time(fn, reps[k]))
+    k = min(best, key=best.get)
+    return k, best[k]
+
+
 def _gram_fn(gs, A, Mhi, Mlo, work, o):
     m, n = A.shape
     ob = ctypes.byref(o)
@@ -85,17 +103,16 @@ def tune_single(gs, quick):
                     A = torch.randn(n, m, device=dev, dtype=dt, generator=gen).t()
                     Mhi = torch.empty(n, n, device=dev, dtype=torch.float64)
                     Mlo = torch.empty_like(Mhi)
-                    best = None
+                    fns, works = {}, []
                     for slab in SINGLE_LADDER:
                         if slab and slab > m:
                             continue
                         o = gs.opts(working, gram, slab_rows=slab)
                         need = gs.gsvd_gram_workspace_size(m, n, ctypes.byref(o))
-                        work = gs.workspace(need, dev)
-                        ms = _time(_gram_fn(gs, A, Mhi, Mlo, work, o), 3 if quick else 5)
-                        if best is None or ms < best[1]:
-                            best = (slab, ms)
-                        del work
+                        works.append(gs.workspace(need, dev))
+                        fns[slab] = _gram_fn(gs, A, Mhi, Mlo, works[-1], o)
+                    best = _best(fns, quick)
+                    del fns, works
                     rows.append(dict(working=working, gram=gram, batched=0, n_max=n, m_max=m_edge,
                                      slab_rows=best[0], ms=round(best[1], 4), m_tuned=m))
                     print(f"[tune] single w={working} gram={gram} n<={n} m={m}: slab {best[0]} "
@@ -117,13 +134,10 @@ def tune_batched(gs, quick):
                     continue  # the FP64 eigensolver stops at n = 96
                 ms_ = torch.randint(10_000, 200_001, (count,), generator=torch.Generator().manual_seed(n))
                 As = [torch.randn(n, int(m), device=dev, dtype=dt, generator=gen).t() for m in ms_]
-                best = None
-                for slab in BATCH_LADDER:
-                    b = gs.Batch(As, gram=gram, want_u=False, slab_rows=slab)
-                    ms = _time(b.run, 2 if quick else 3)
-                    if best is None or ms < best[1]:
-                        best = (slab, ms)
-                    del b
+                batches = {slab: gs.Batch(As, gram=gram, want_u=False, slab_rows=slab)
+                           for slab in BATCH_LADDER}
+                best = _best({slab: b.run for slab, b in batches.items()}, quick)
+                del batches
                 rows.append(dict(working=working, gram=gram, batched=1, n_max=n, m_max=2**62,
                                  slab_rows=best[0], ms=round(best[1], 4)))
                 print(f"[tune] batched w={working} gram={gram} n<={n}: slab {best[0]} "
