@@ -159,6 +159,57 @@ def make_a(spec: MatrixSpec) -> np.ndarray:
     return A
 
 
+def small_factor(spec: MatrixSpec) -> tuple[np.ndarray, np.random.Generator]:
+    """Y = (Sigma W2 W3) D of the spec, n x n, with the spec's column permutation applied
+    (the draws of make_a without W1), and the generator after those draws."""
+    n = spec.n
+    rng = rng_for(spec.seed)
+    sig = latm1(spec.mode_b, spec.kappa_b, n, rng)
+    sig = sig * np.sqrt(n / np.sum(sig * sig))
+    W2 = _orth_factor(rng.standard_normal((n, n)))
+    X = unit_columns(sig[:, None] * W2)
+    d = latm1(spec.mode_d, spec.kappa_d, n, rng)
+    Y = X * d[None, :]
+    if spec.shuffle:
+        Y = Y[:, rng.permutation(n)]
+    return np.asfortranarray(Y), rng
+
+
+def make_a_device(spec: MatrixSpec, device):
+    """A = W1 Y built on the GPU for workloads too large for the host recipe.
+
+    Y is :func:`small_factor` (numpy, FP64).  W1 is an m x n Gaussian from a torch
+    generator seeded with spec.seed, made orthonormal by a QR factorization when
+    spec.w1 == "qr" (then sigma(A) equals sigma(Y) up to the rounding of the product),
+    else scaled by 1/sqrt(m).  Returns (A, Y): A a column-major (strides (1, m)) torch
+    tensor in the spec's dtype, Y the numpy factor.
+    """
+    import torch
+    m, n = spec.m, spec.n
+    if m < n or n < 1:
+        raise ValueError("need m >= n >= 1")
+    Y, _ = small_factor(spec)
+    gen = torch.Generator(device=device).manual_seed(int(spec.seed))
+    G = torch.randn((n, m), generator=gen, device=device, dtype=torch.float64)  # W1^T
+    if spec.w1 == "qr":
+        Q, _ = torch.linalg.qr(G.t(), mode="reduced")
+        del G
+        W1t = Q.t().contiguous()
+        del Q
+    elif spec.w1 == "gauss":
+        W1t = G.mul_(1.0 / np.sqrt(m))
+    else:
+        raise ValueError(spec.w1)
+    Yt = torch.from_numpy(np.ascontiguousarray(Y.T)).to(device)
+    At = Yt @ W1t  # (n x m) row-major = A column-major
+    del W1t
+    if spec.dtype == "f32":
+        At = At.to(torch.float32)
+    elif spec.dtype != "f64":
+        raise ValueError(spec.dtype)
+    return At.t(), Y
+
+
 # --------------------------------------------------------------------------
 # matrices with an exactly known SVD
 # --------------------------------------------------------------------------

@@ -80,18 +80,23 @@ enum {
 #define GSVD_INFO_NO_CONVERGE 2   /* Jacobi did not converge within max_sweeps */
 #define GSVD_INFO_NONFINITE 3     /* A (hence M_h) holds a NaN or Inf */
 
-#define GSVD_MAX_N 128            /* largest n the current kernels accept */
+#define GSVD_MAX_N 512            /* largest n of the single-problem calls; n > 128 runs
+                                     the wide kernels (64-column panel pairs, blocked
+                                     Cholesky, block Jacobi) */
+#define GSVD_MAX_N_EIG_F32 128    /* FP32 working: largest n of the eigensolver stage
+                                     (larger n returns GSVD_ERR_UNSUPPORTED) */
+#define GSVD_MAX_N_BATCHED_F64 96 /* largest n of a batched problem, FP64 working */
+#define GSVD_MAX_N_BATCHED_F32 128 /* largest n of a batched problem, FP32 working */
 #define GSVD_MAX_SLICES 12        /* largest n_slices of the split Gram, FP64 A */
 #define GSVD_MAX_SLICES_F32 8     /* largest n_slices of the split Gram, FP32 A */
-#define GSVD_MAX_N_EIG_F64 96     /* FP64 working: largest n of the eigensolver stage
-                                     (larger n returns GSVD_ERR_UNSUPPORTED) */
 
 typedef struct {
     int working;        /* GSVD_F32 or GSVD_F64 */
     int gram;           /* GSVD_GRAM_* */
     int eig;            /* GSVD_EIG_* */
     int n_slices;       /* split Gram only: 1..GSVD_MAX_SLICES (FP64 A) or
-                           1..GSVD_MAX_SLICES_F32 (FP32 A); 0 = 10 (FP64), 6 (FP32) */
+                           1..GSVD_MAX_SLICES_F32 (FP32 A); 0 = the tuning table's
+                           count (the smallest meeting the accuracy budget) */
     double jacobi_tol;  /* rotation threshold: a pair p, q is rotated when
                            |g_pq| > tol * sqrt(g_pp g_qq); 0 = the eigensolver's default */
     int max_sweeps;     /* 0 = 30 */
@@ -190,8 +195,8 @@ int gsvd_u_recover(int64_t m, int64_t n, const void *dA, int64_t lda,
  *  - dA, dS, dV, dU: DEVICE arrays of `batch` device pointers (dU may be NULL
  *    without GSVD_WANT_U).  hM, hN, hLda, hLdv, hLdu: HOST arrays of `batch`
  *    entries (hLdu may be NULL without GSVD_WANT_U).  dInfo: device int[batch].
- *  - Every problem: m >= n >= 1, n <= GSVD_MAX_N_EIG_F64 (FP64 working) or
- *    GSVD_MAX_N (FP32 working); 1 <= batch <= 65535.  One set of options for
+ *  - Every problem: m >= n >= 1, n <= GSVD_MAX_N_BATCHED_F64 (FP64 working) or
+ *    GSVD_MAX_N_BATCHED_F32 (FP32 working); 1 <= batch <= 65535.  One set of options for
  *    all; the per-problem default Jacobi threshold is sqrt(n) u.
  *  - The whole plan travels in kernel arguments: the call performs no
  *    host-to-device copy, allocation or synchronisation, so it can be

@@ -29,7 +29,7 @@ GSVD_F32, GSVD_F64 = 0, 1
 GSVD_GRAM_AUTO, GSVD_GRAM_PLAIN, GSVD_GRAM_SPLIT = 0, 1, 2
 GSVD_EIG_AUTO, GSVD_EIG_JACOBI2, GSVD_EIG_CHOL_JACOBI1 = 0, 1, 2
 GSVD_WANT_U = 1
-GSVD_MAX_N = 128
+GSVD_MAX_N = 512
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libgsvd.so")

@@ -46,6 +46,8 @@ inline int eig_mode_of(const gsvd_opts *o) {
     return o->working == GSVD_F32 ? GSVD_EIG_JACOBI2 : GSVD_EIG_CHOL_JACOBI1;
 }
 
+inline bool use_split(const gsvd_opts *o) { return o->gram == GSVD_GRAM_SPLIT; }
+
 inline int check_supported(const gsvd_opts *o) {
     if (o->gram == GSVD_GRAM_SPLIT && o->n_slices > max_slices(o->working))
         return GSVD_ERR_UNSUPPORTED;
@@ -54,13 +56,25 @@ inline int check_supported(const gsvd_opts *o) {
     return 0;
 }
 
+// n > 128: the wide Gram and U kernels (64-column panels)
+inline bool wide_n(int64_t n) { return n > GSVD_KMAX_N; }
+// FP64 working beyond the one-workgroup eigensolver: the multi-launch Algorithm 2
+inline bool wide_eig(const gsvd_opts *o, int64_t n) {
+    return o->working == GSVD_F64 && n > GSVD_KMAX_N_F64;
+}
+
 inline int check_eig_supported(const gsvd_opts *o, int64_t n) {
     if (int e = check_supported(o)) return e;
-    if (o->working == GSVD_F64 && n > GSVD_MAX_N_EIG_F64) return GSVD_ERR_UNSUPPORTED;
+    if (o->working == GSVD_F32 && n > GSVD_MAX_N_EIG_F32) return GSVD_ERR_UNSUPPORTED;
     return 0;
 }
 
-inline bool use_split(const gsvd_opts *o) { return o->gram == GSVD_GRAM_SPLIT; }
+// the Gram forms in force for n: the wide split Gram is not built
+inline int check_gram_supported(const gsvd_opts *o, int64_t n) {
+    if (int e = check_supported(o)) return e;
+    if (wide_n(n) && use_split(o)) return GSVD_ERR_UNSUPPORTED;
+    return 0;
+}
 
 // slice count of the split Gram: the caller's, else the tuning table's
 inline int slices_of(const gsvd_opts *o, int64_t n) {
@@ -86,6 +100,7 @@ inline SplitPlan split_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool ba
 
 // workspace bytes for the partial sums of whichever Gram form o selects
 inline size_t gram_part_bytes(int64_t m, int64_t n, const gsvd_opts *o, bool batched) {
+    if (wide_n(n)) return use_split(o) ? 0 : gram_wide_plan(m, n, o->slab_rows).part_bytes;
     if (use_split(o)) return split_plan_of(o, m, n, batched).part_bytes;
     return gram_plan_of(o, m, n, batched).part_bytes;
 }
@@ -99,6 +114,7 @@ inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
 }
 
 inline size_t eig_work_bytes(const gsvd_opts *o, int64_t n) {
+    if (wide_eig(o, n)) return eig_wide_work_bytes(n);
     return eig_mode_of(o) == GSVD_EIG_JACOBI2 ? j2_work_bytes(n) : 0;
 }
 
@@ -107,6 +123,8 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
                           int *info, void *work, hipStream_t st) {
     const double tol = jacobi_tol_of(o, n);
     const int sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    if (wide_eig(o, n))
+        return eig_wide_launch(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps, work, st);
     if (eig_mode_of(o) == GSVD_EIG_JACOBI2)
         return eig_jacobi2_launch(o->working, n, Mhi, ldm, S, V, ldv, W, ldw, info, tol, sweeps,
                                   work, st);
@@ -114,5 +132,12 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
 }
 
 inline int sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 30; }
+
+inline hipError_t urecover_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A,
+                               int64_t lda, const void *W, int64_t ldw, void *U, int64_t ldu,
+                               hipStream_t st) {
+    if (wide_n(n)) return urecover_wide_launch(o->working, m, n, A, lda, W, ldw, U, ldu, st);
+    return urecover_launch(o->working, m, n, A, lda, W, ldw, U, ldu, st);
+}
 
 }  // namespace gsvd

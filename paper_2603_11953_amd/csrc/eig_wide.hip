@@ -1,0 +1,592 @@
+// Eigensolver stage for n > 96 with FP64 working: Algorithm 2 of the paper
+// spread over many workgroups and a sequence of launches on one stream.
+//
+//   1. Column scaling (init kernels): e_j = ilogb(sqrt(m_jj)), the power of two
+//      D~ of A = B D; H = D~^-1 M_h D~^-1 formed exactly in double-double;
+//      checks for non-finite entries (info 3) and non-positive diagonals (info 1).
+//   2. Cholesky H = R_H^T R_H in double-double (Alg. 2 step 1), blocked by
+//      panels of 64 columns: for each panel
+//        potrf  one workgroup factors the 64 x 64 diagonal block in LDS
+//               (right-looking);
+//        panel  R(k, j) = R_kk^-T H(k, j) for the columns j right of the panel
+//               (forward substitution, right-looking: one workgroup per 16
+//               columns, one lane per entry, 64 steps);
+//        update H(i, j) -= R(k, i)^T R(k, j) for the trailing upper triangle
+//               (32 x 32 tiles, one lane per entry, 64-deep dd sums).
+//      A non-positive pivot stops the factorization with info 1.
+//   3. X = fl64(R_H) D~ 2^-e_max (Alg. 2 step 2; exact scalings).
+//   4. One-sided Jacobi on the columns of X (Alg. 2 step 3), block form: the
+//      columns are cut into blocks of 8; a step pairs the blocks by a round-
+//      robin tournament and gives each pair of blocks (16 columns of X and the
+//      same 16 columns of V, all n rows) to one workgroup, which holds them in
+//      LDS and rotates the 64 pairs across the two blocks (8 rounds of 8
+//      disjoint pairs, one wavefront each); the first step of a tournament
+//      round, where every block appears once, also rotates the 28 pairs inside
+//      each block (7 more rounds).  So every pair of columns is visited once
+//      per round, as in a cyclic sweep.  The three inner products are summed
+//      by an xor butterfly, which leaves bitwise identical sums in every lane;
+//      every rotation is applied to the columns of X and of V as it is found,
+//      as in the one-workgroup kernel.  One launch per
+//      step; after each tournament round a one-lane kernel marks convergence
+//      when no rotation passed the test |x_p^T x_q| > tol ||x_p|| ||x_q||, and
+//      later launches return at once.
+//   5. sigma_p = ||x_p|| 2^e_max, ordering, sign of the V columns (entry of
+//      largest magnitude positive, lowest index on ties), W = fl(V Sigma^-1).
+//   The same outputs and info codes as the one-workgroup kernel for n <= 96.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "dd_device.hpp"
+#include "gsvd_internal.hpp"
+
+namespace gsvd {
+
+namespace {
+
+constexpr int CB = 64;       // Cholesky panel width
+constexpr int JB = 8;        // Jacobi block width (columns)
+constexpr int JC = 2 * JB;   // columns held by one workgroup
+constexpr int JT = 64 * JB;  // Jacobi workgroup size: one wavefront per column pair of a round
+constexpr int UT = 1024;     // update-kernel workgroup (32 x 32 tile)
+
+struct Ctl {
+    int bad;      // info code of a failed check (1 or 3), 0 otherwise
+    int emax;     // max e_j
+    int rot;      // rotations in the current tournament round
+    int done;     // converged
+    int notconv;  // max_sweeps reached without convergence
+    int abort;    // the output kernel must not write
+};
+
+struct WLayout {
+    size_t ctl, sexp, rank, sig, sgn, hh, hl, x, v, total;
+};
+
+__host__ __device__ inline size_t wal(size_t x) { return (x + 255) / 256 * 256; }
+
+WLayout wlayout(int64_t n) {
+    WLayout L{};
+    size_t o = 0;
+    const size_t nn = (size_t)n * (size_t)n;
+    L.ctl = o;  o = wal(o + sizeof(Ctl));
+    L.sexp = o; o = wal(o + (size_t)n * sizeof(int));
+    L.rank = o; o = wal(o + (size_t)n * sizeof(int));
+    L.sig = o;  o = wal(o + (size_t)n * sizeof(double));
+    L.sgn = o;  o = wal(o + (size_t)n * sizeof(double));
+    L.hh = o;   o = wal(o + nn * sizeof(double));
+    L.hl = o;   o = wal(o + nn * sizeof(double));
+    L.x = o;    o = wal(o + nn * sizeof(double));
+    L.v = o;    o = wal(o + nn * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+// A control word written by an earlier launch (no lane of the reading launch
+// writes it first, so every lane reads the same value).
+__device__ __forceinline__ int wg_read(const int *p) {
+    return __builtin_amdgcn_readfirstlane(*reinterpret_cast<const volatile int *>(p));
+}
+
+// ---- 1. scaling exponents, checks, H, V = I
+
+__global__ void __launch_bounds__(1024)
+weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, int *sexp) {
+    __shared__ int bad, emax;
+    if (threadIdx.x == 0) {
+        bad = 0;
+        emax = -100000;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double mjj = Mhi[j + (int64_t)j * ldm];
+        if (!(mjj > 0.0) || !__builtin_isfinite(mjj)) {
+            atomicMax(&bad, __builtin_isfinite(mjj) ? 1 : 3);
+            sexp[j] = 0;
+        } else {
+            const int e = ilogb(__builtin_sqrt(mjj));
+            sexp[j] = e;
+            atomicMax(&emax, e);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->bad = bad;
+        ctl->emax = emax;
+        ctl->rot = 0;
+        ctl->done = 0;
+        ctl->notconv = 0;
+        ctl->abort = 0;
+    }
+}
+
+// one workgroup per column j: finiteness of column j, H(:, j) (upper part), V(:, j) = e_j
+__global__ void __launch_bounds__(256)
+weig_fill_kernel(int n, const double *__restrict__ Mhi, const double *__restrict__ Mlo,
+                 int64_t ldm, Ctl *ctl, const int *__restrict__ sexp, double *__restrict__ Hh,
+                 double *__restrict__ Hl, double *__restrict__ Vw) {
+    const int j = blockIdx.x;
+    bool nonfinite = false;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double h = Mhi[i + (int64_t)j * ldm];
+        const double l = Mlo[i + (int64_t)j * ldm];
+        if (!__builtin_isfinite(h) || !__builtin_isfinite(l)) nonfinite = true;
+        if (i <= j) {
+            const int sc = -(sexp[i] + sexp[j]);
+            Hh[i + (size_t)j * n] = ldexp(h, sc);
+            Hl[i + (size_t)j * n] = ldexp(l, sc);
+        }
+        Vw[i + (size_t)j * n] = i == j ? 1.0 : 0.0;
+    }
+    if (nonfinite) atomicMax(&ctl->bad, 3);
+}
+
+// ---- 2. blocked dd Cholesky
+
+// Factor the diagonal block [k0, k0 + 64) in place (upper triangle).
+__global__ void __launch_bounds__(1024)
+weig_potrf_kernel(int n, int k0, Ctl *ctl, double *__restrict__ Hh, double *__restrict__ Hl) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
+    dd_t *Rs = reinterpret_cast<dd_t *>(wsm);  // CB x CB, column-major
+    if (wg_read(&ctl->bad)) return;
+    const int nb = (n - k0 < CB) ? n - k0 : CB;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < CB * CB; q += blockDim.x) {
+        const int i = q % CB, j = q / CB;
+        dd_t v{0.0, 0.0};
+        if (i < nb && j < nb && i <= j)
+            v = dd_t{Hh[(k0 + i) + (size_t)(k0 + j) * n], Hl[(k0 + i) + (size_t)(k0 + j) * n]};
+        Rs[q] = v;
+    }
+    __syncthreads();
+    bool fail = false;
+    const int tx = tid & 31, ty = tid >> 5;
+    for (int k = 0; k < nb; ++k) {
+        const dd_t hkk = Rs[k + k * CB];
+        if (!(hkk.hi > 0.0)) {  // uniform: every lane read the same LDS word
+            fail = true;
+            break;
+        }
+        const dd_t rkk = dd_sqrt(hkk);
+        __syncthreads();
+        for (int j = k + 1 + tid; j < nb; j += blockDim.x) Rs[k + j * CB] = dd_div(Rs[k + j * CB], rkk);
+        if (tid == 0) Rs[k + k * CB] = rkk;
+        __syncthreads();
+        for (int j = k + 1 + ty; j < nb; j += 32)
+            for (int i = k + 1 + tx; i <= j; i += 32)
+                Rs[i + j * CB] = dd_sub(Rs[i + j * CB], dd_mul(Rs[k + i * CB], Rs[k + j * CB]));
+        __syncthreads();
+    }
+    if (fail) {
+        if (tid == 0) atomicMax(&ctl->bad, 1);
+        return;
+    }
+    for (int q = tid; q < CB * CB; q += blockDim.x) {
+        const int i = q % CB, j = q / CB;
+        if (i < nb && j < nb && i <= j) {
+            Hh[(k0 + i) + (size_t)(k0 + j) * n] = Rs[q].hi;
+            Hl[(k0 + i) + (size_t)(k0 + j) * n] = Rs[q].lo;
+        }
+    }
+}
+
+// R(k0 + i, j) for the 16 columns j0 .. j0 + 15 right of the panel: solve
+// R_kk^T x = H(k0 .. k0 + 63, j) by forward substitution, right-looking:
+// step t divides x_t by R(t, t), then x_i -= R(t, i) x_t for i > t.
+__global__ void __launch_bounds__(1024)
+weig_panel_kernel(int n, int k0, const Ctl *ctl, double *__restrict__ Hh,
+                  double *__restrict__ Hl) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
+    dd_t *Rk = reinterpret_cast<dd_t *>(wsm);  // CB x CB, column-major (upper)
+    dd_t *Hs = Rk + CB * CB;                    // CB x 16
+    if (wg_read(&ctl->bad)) return;
+    const int tid = threadIdx.x;
+    const int j0 = k0 + CB + 16 * blockIdx.x;
+    for (int q = tid; q < CB * CB; q += blockDim.x) {
+        const int i = q % CB, j = q / CB;
+        Rk[q] = i <= j ? dd_t{Hh[(k0 + i) + (size_t)(k0 + j) * n], Hl[(k0 + i) + (size_t)(k0 + j) * n]}
+                       : dd_t{0.0, 0.0};
+    }
+    const int i = tid % CB, c = tid / CB;  // 64 rows x 16 columns
+    const int j = j0 + c;
+    const bool jv = j < n;
+    Hs[i + c * CB] = jv ? dd_t{Hh[(k0 + i) + (size_t)j * n], Hl[(k0 + i) + (size_t)j * n]}
+                        : dd_t{0.0, 0.0};
+    __syncthreads();
+    for (int t = 0; t < CB; ++t) {
+        if (i == t) Hs[t + c * CB] = dd_div(Hs[t + c * CB], Rk[t + t * CB]);
+        __syncthreads();
+        if (i > t) Hs[i + c * CB] = dd_sub(Hs[i + c * CB], dd_mul(Rk[t + i * CB], Hs[t + c * CB]));
+        __syncthreads();
+    }
+    if (jv) {
+        Hh[(k0 + i) + (size_t)j * n] = Hs[i + c * CB].hi;
+        Hl[(k0 + i) + (size_t)j * n] = Hs[i + c * CB].lo;
+    }
+}
+
+// H(i, j) -= sum_{t < CB} R(k0 + t, i) R(k0 + t, j), k1 <= i <= j < n, in 32 x 32 tiles
+__global__ void __launch_bounds__(UT)
+weig_update_kernel(int n, int k0, int ntile, const Ctl *ctl, double *__restrict__ Hh,
+                   double *__restrict__ Hl) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
+    dd_t *Ri = reinterpret_cast<dd_t *>(wsm);  // CB x 32
+    dd_t *Rj = Ri + CB * 32;
+    if (wg_read(&ctl->bad)) return;
+    // tile (ti, tj), ti <= tj, of the trailing square
+    int ti = 0, rem = blockIdx.x;
+    while (rem >= ntile - ti) {
+        rem -= ntile - ti;
+        ++ti;
+    }
+    const int tj = ti + rem;
+    const int k1 = k0 + CB;
+    const int i0 = k1 + 32 * ti, j0 = k1 + 32 * tj;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < CB * 32; q += blockDim.x) {
+        const int t = q % CB, c = q / CB;
+        const int ci = i0 + c, cj = j0 + c;
+        Ri[q] = ci < n ? dd_t{Hh[(k0 + t) + (size_t)ci * n], Hl[(k0 + t) + (size_t)ci * n]}
+                       : dd_t{0.0, 0.0};
+        Rj[q] = cj < n ? dd_t{Hh[(k0 + t) + (size_t)cj * n], Hl[(k0 + t) + (size_t)cj * n]}
+                       : dd_t{0.0, 0.0};
+    }
+    __syncthreads();
+    const int li = tid % 32, lj = tid / 32;
+    const int i = i0 + li, j = j0 + lj;
+    if (i < n && j < n && i <= j) {
+        dd_t s{0.0, 0.0};
+        for (int t = 0; t < CB; ++t) s = dd_add(s, dd_mul(Ri[t + li * CB], Rj[t + lj * CB]));
+        const dd_t h{Hh[i + (size_t)j * n], Hl[i + (size_t)j * n]};
+        const dd_t r = dd_sub(h, s);
+        Hh[i + (size_t)j * n] = r.hi;
+        Hl[i + (size_t)j * n] = r.lo;
+    }
+}
+
+// ---- 3. X = fl64(R_H) D~ 2^-emax (upper triangle; zeros below)
+__global__ void __launch_bounds__(256)
+weig_cast_kernel(int n, const Ctl *ctl, const int *__restrict__ sexp,
+                 const double *__restrict__ Hh, double *__restrict__ X) {
+    if (wg_read(&ctl->bad)) return;
+    const int j = blockIdx.x;
+    const int sc = sexp[j] - ctl->emax;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        X[i + (size_t)j * n] = i <= j ? ldexp(Hh[i + (size_t)j * n], sc) : 0.0;
+}
+
+// ---- 4. block one-sided Jacobi
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// round-robin tournament on m (even) players: pair g of round r
+__device__ __forceinline__ void rr_pair(int r, int g, int m, int &p, int &q) {
+    if (g == 0) {
+        p = r;
+        q = m - 1;
+    } else {
+        p = (r + g) % (m - 1);
+        q = (r - g + (m - 1)) % (m - 1);
+    }
+}
+
+template <int RPL>
+__global__ void __launch_bounds__(JT)
+weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
+                 double *__restrict__ Vw, double tol2) {
+    extern __shared__ __attribute__((aligned(16))) double jsm[];
+    constexpr int LDL = 64 * RPL;  // rows of a column in LDS (n rounded up to 64)
+    double *Xl = jsm;              // JC columns of X
+    double *Vl = jsm + JC * LDL;   // the same JC columns of V
+    if (wg_read(&ctl->bad) || wg_read(&ctl->done)) return;
+    int P, Qb;
+    rr_pair(step, blockIdx.x, nblk, P, Qb);
+    const int nbb = (n + JB - 1) / JB;
+    // the bye of an odd block count: its partner still rotates its own pairs in the
+    // first step (the bye's columns read as zeros, and zero columns never rotate)
+    if ((P >= nbb && Qb >= nbb) || ((P >= nbb || Qb >= nbb) && step != 0)) return;
+    const int tid = threadIdx.x;
+    auto gcol = [&](int c) { return c < JB ? JB * P + c : JB * Qb + (c - JB); };
+    for (int q = tid; q < JC * LDL; q += JT) {
+        const int r = q % LDL, c = q / LDL;
+        const int g = gcol(c);
+        const bool in = r < n && g < n;
+        Xl[q] = in ? X[r + (size_t)g * n] : 0.0;
+        Vl[q] = in ? Vw[r + (size_t)g * n] : 0.0;
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    bool any = false;
+    // rounds 0 .. JB-2 (first step only): pairs inside block P (wavefronts
+    // 0 .. JB/2-1) and inside block Q; then JB rounds of cross pairs (i, JB + (i + r) mod JB)
+    const int r0 = step == 0 ? 0 : JB - 1;
+    for (int round = r0; round < 2 * JB - 1; ++round) {
+        int p, q;
+        if (round < JB - 1) {
+            const int h = wave / (JB / 2), g = wave % (JB / 2);
+            rr_pair(round, g, JB, p, q);
+            p += JB * h;
+            q += JB * h;
+        } else {
+            p = wave;
+            q = JB + (wave + round - (JB - 1)) % JB;
+        }
+        double *xp = Xl + p * LDL + lane, *xq = Xl + q * LDL + lane;
+        double a0[RPL], a1[RPL];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            a0[i] = xp[64 * i];
+            a1[i] = xq[64 * i];
+            al = __builtin_fma(a0[i], a0[i], al);
+            be = __builtin_fma(a1[i], a1[i], be);
+            ga = __builtin_fma(a0[i], a1[i], ga);
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (ga * ga > tol2 * (al * be)) {  // uniform: the sums agree bitwise across lanes
+            const double zeta = (be - al) / (2.0 * ga);
+            const double az = __builtin_fabs(zeta);
+            double tn;
+            if (az > 1e150) {
+                tn = 0.5 / zeta;
+            } else {
+                tn = 1.0 / (az + __builtin_sqrt(__builtin_fma(zeta, zeta, 1.0)));
+                if (zeta < 0) tn = -tn;
+            }
+            const double c = 1.0 / __builtin_sqrt(__builtin_fma(tn, tn, 1.0));
+            const double sn = c * tn;
+            double *vp = Vl + p * LDL + lane, *vq = Vl + q * LDL + lane;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                xp[64 * i] = c * a0[i] - sn * a1[i];
+                xq[64 * i] = sn * a0[i] + c * a1[i];
+                const double u = vp[64 * i], w = vq[64 * i];
+                vp[64 * i] = c * u - sn * w;
+                vq[64 * i] = sn * u + c * w;
+            }
+            any = true;
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < JC * LDL; q += JT) {
+        const int r = q % LDL, c = q / LDL;
+        const int g = gcol(c);
+        if (r < n && g < n) {
+            X[r + (size_t)g * n] = Xl[q];
+            Vw[r + (size_t)g * n] = Vl[q];
+        }
+    }
+    if (any && lane == 0) atomicAdd(&ctl->rot, 1);
+}
+
+// end of a tournament round (one lane)
+__global__ void weig_sweep_kernel(Ctl *ctl, int last) {
+    if (threadIdx.x != 0 || ctl->bad || ctl->done) return;
+    if (ctl->rot == 0) {
+        ctl->done = 1;
+    } else {
+        ctl->rot = 0;
+        if (last) ctl->notconv = 1;
+    }
+}
+
+// ---- 5. sigma, signs, ordering, outputs
+
+// one wavefront per column p: ||x_p|| and the row of the largest |V(:, p)|
+__global__ void __launch_bounds__(1024)
+weig_sigma_kernel(int n, const Ctl *ctl, const double *__restrict__ X,
+                  const double *__restrict__ Vw, double *__restrict__ sig,
+                  double *__restrict__ sgn) {
+    if (wg_read(&ctl->bad)) return;
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (p >= n) return;
+    double ss = 0.0, best = -1.0;
+    int barg = 0;
+    for (int r = lane; r < n; r += 64) {
+        const double x = X[r + (size_t)p * n];
+        ss = __builtin_fma(x, x, ss);
+        const double av = __builtin_fabs(Vw[r + (size_t)p * n]);
+        if (av > best) {
+            best = av;
+            barg = r;
+        }
+    }
+    ss = wave_sum(ss);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oa = __shfl_xor(barg, off);
+        if (ob > best || (ob == best && oa < barg)) {
+            best = ob;
+            barg = oa;
+        }
+    }
+    if (lane == 0) {
+        sig[p] = ldexp(__builtin_sqrt(ss), ctl->emax);
+        sgn[p] = Vw[barg + (size_t)p * n] < 0 ? -1.0 : 1.0;
+    }
+}
+
+// ranks (descending, stable) and the final info code
+__global__ void __launch_bounds__(1024)
+weig_rank_kernel(int n, Ctl *ctl, const double *__restrict__ sig, int *__restrict__ rank,
+                 int *__restrict__ info) {
+    __shared__ int bad;
+    const int b0 = wg_read(&ctl->bad);
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    if (b0 == 0) {
+        for (int p = threadIdx.x; p < n; p += blockDim.x) {
+            const double sp = sig[p];
+            int rk = 0;
+            for (int q = 0; q < n; ++q) {
+                const double sq = sig[q];
+                rk += (sq > sp) || (sq == sp && q < p);
+            }
+            rank[p] = rk;
+            if (!(sp > 0.0)) atomicMax(&bad, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int code = b0;
+        if (code == 0 && ctl->notconv) code = 2;
+        if (code == 0) code = bad;
+        ctl->abort = code != 0;
+        *info = code;
+    }
+}
+
+// one workgroup per column p of the Jacobi: V(:, rank p), W(:, rank p), S(rank p)
+__global__ void __launch_bounds__(256)
+weig_out_kernel(int n, const Ctl *ctl, const double *__restrict__ Vw,
+                const double *__restrict__ sig, const double *__restrict__ sgn,
+                const int *__restrict__ rank, double *__restrict__ S, double *__restrict__ V,
+                int64_t ldv, double *__restrict__ W, int64_t ldw) {
+    if (wg_read(&ctl->abort)) return;
+    const int p = blockIdx.x;
+    const int pos = rank[p];
+    const double sp = sig[p], sg = sgn[p];
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const double v = sg * Vw[r + (size_t)p * n];
+        V[r + (size_t)pos * ldv] = v;
+        W[r + (size_t)pos * ldw] = v / sp;
+    }
+    if (threadIdx.x == 0) S[pos] = sp;
+}
+
+template <int RPL>
+hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double tol2,
+                        int max_sweeps, hipStream_t st) {
+    const size_t lds = (size_t)2 * JC * 64 * RPL * sizeof(double);
+    auto k = weig_step_kernel<RPL>;
+    hipError_t err = hipFuncSetAttribute((const void *)k,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        for (int s = 0; s < nblk - 1; ++s) {
+            hipLaunchKernelGGL(k, dim3((unsigned)(nblk / 2)), dim3(JT), lds, st, n, nblk, s, ctl,
+                               X, Vw, tol2);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
+        hipLaunchKernelGGL(weig_sweep_kernel, dim3(1), dim3(64), 0, st, ctl,
+                           sw + 1 == max_sweeps ? 1 : 0);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+size_t eig_wide_work_bytes(int64_t n) { return wlayout(n).total; }
+
+hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, int64_t ldm, void *S,
+                           void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
+                           int max_sweeps, void *work, hipStream_t st) {
+    if (n64 < 2 || n64 > GSVD_WIDE_MAX_N || Mlo == nullptr || work == nullptr || max_sweeps < 1)
+        return hipErrorInvalidValue;
+    const int n = (int)n64;
+    const WLayout L = wlayout(n);
+    char *base = (char *)work;
+    Ctl *ctl = reinterpret_cast<Ctl *>(base + L.ctl);
+    int *sexp = reinterpret_cast<int *>(base + L.sexp);
+    int *rank = reinterpret_cast<int *>(base + L.rank);
+    double *sig = reinterpret_cast<double *>(base + L.sig);
+    double *sgn = reinterpret_cast<double *>(base + L.sgn);
+    double *Hh = reinterpret_cast<double *>(base + L.hh);
+    double *Hl = reinterpret_cast<double *>(base + L.hl);
+    double *X = reinterpret_cast<double *>(base + L.x);
+    double *Vw = reinterpret_cast<double *>(base + L.v);
+    hipError_t err;
+#define WCHK()                                                  \
+    do {                                                        \
+        if ((err = hipGetLastError()) != hipSuccess) return err; \
+    } while (0)
+
+    hipLaunchKernelGGL(weig_diag_kernel, dim3(1), dim3(1024), 0, st, n, Mhi, ldm, ctl, sexp);
+    WCHK();
+    hipLaunchKernelGGL(weig_fill_kernel, dim3((unsigned)n), dim3(256), 0, st, n, Mhi, Mlo, ldm, ctl,
+                       sexp, Hh, Hl, Vw);
+    WCHK();
+    const size_t lds_potrf = (size_t)CB * CB * sizeof(dd_t);
+    const size_t lds_panel = (size_t)CB * (CB + 16) * sizeof(dd_t);
+    const size_t lds_update = (size_t)2 * CB * 32 * sizeof(dd_t);
+    if ((err = hipFuncSetAttribute((const void *)weig_potrf_kernel,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_potrf)) ||
+        (err = hipFuncSetAttribute((const void *)weig_panel_kernel,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_panel)) ||
+        (err = hipFuncSetAttribute((const void *)weig_update_kernel,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_update)))
+        return err;
+    for (int k0 = 0; k0 < n; k0 += CB) {
+        hipLaunchKernelGGL(weig_potrf_kernel, dim3(1), dim3(1024), lds_potrf, st, n, k0, ctl, Hh, Hl);
+        WCHK();
+        const int right = n - (k0 + CB);
+        if (right > 0) {
+            hipLaunchKernelGGL(weig_panel_kernel, dim3((unsigned)((right + 15) / 16)), dim3(1024),
+                               lds_panel, st, n, k0, ctl, Hh, Hl);
+            WCHK();
+            const int nt = (right + 31) / 32;
+            hipLaunchKernelGGL(weig_update_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(UT),
+                               lds_update, st, n, k0, nt, ctl, Hh, Hl);
+            WCHK();
+        }
+    }
+    hipLaunchKernelGGL(weig_cast_kernel, dim3((unsigned)n), dim3(256), 0, st, n, ctl, sexp, Hh, X);
+    WCHK();
+    const int nbb = (n + JB - 1) / JB;
+    const int nblk = nbb + (nbb & 1);
+    const double tol2 = tol * tol;
+    const int rpl = (n + 63) / 64;
+    switch (rpl) {
+        case 2: err = launch_steps<2>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
+        case 3: err = launch_steps<3>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
+        case 4: err = launch_steps<4>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
+        case 5: err = launch_steps<5>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
+        case 6: err = launch_steps<6>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
+        case 7: err = launch_steps<7>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
+        case 8: err = launch_steps<8>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(weig_sigma_kernel, dim3((unsigned)((n + 15) / 16)), dim3(1024), 0, st, n, ctl,
+                       X, Vw, sig, sgn);
+    WCHK();
+    hipLaunchKernelGGL(weig_rank_kernel, dim3(1), dim3(1024), 0, st, n, ctl, sig, rank, info);
+    WCHK();
+    hipLaunchKernelGGL(weig_out_kernel, dim3((unsigned)n), dim3(256), 0, st, n, ctl, Vw, sig, sgn,
+                       rank, (double *)S, (double *)V, ldv, (double *)W, ldw);
+    WCHK();
+#undef WCHK
+    return hipSuccess;
+}
+
+}  // namespace gsvd

@@ -18,6 +18,10 @@ namespace {
 
 hipError_t gram_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A, int64_t lda,
                     double *Mhi, double *Mlo, int64_t ldm, void *part, hipStream_t st) {
+    if (wide_n(n)) {
+        WidePlan p = gram_wide_plan(m, n, o->slab_rows);
+        return gram_wide_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
+    }
     if (use_split(o)) {
         SplitPlan p = split_plan_of(o, m, n, false);
         return split_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
@@ -89,10 +93,14 @@ int gsvd_gram_config(int64_t m, int64_t n, const gsvd_opts *o, int64_t *slab_row
     if (m < 1) return -1;
     if (n < 1 || n > GSVD_MAX_N || n > m) return -2;
     if (int e = check_opts(o, 3)) return e;
-    if (int e = check_supported(o)) return e;
+    if (int e = check_gram_supported(o, n)) return e;
     int64_t rows, slabs;
     int S = 0;
-    if (use_split(o)) {
+    if (wide_n(n)) {
+        const WidePlan p = gram_wide_plan(m, n, o->slab_rows);
+        rows = p.rows_per_split;
+        slabs = p.nsplit;
+    } else if (use_split(o)) {
         const SplitPlan p = split_plan_of(o, m, n, false);
         rows = p.rows_per_split;
         slabs = p.nsplit;
@@ -121,7 +129,7 @@ int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda, double *dMhi, d
     const size_t need = gsvd_gram_workspace_size(m, n, o);
     if (work == nullptr || !aligned(work, kAlign)) return -8;
     if (work_bytes < need) return -9;
-    if (int e = check_supported(o)) return e;
+    if (int e = check_gram_supported(o, n)) return e;
     hipError_t err = gram_any(o, m, n, dA, lda, dMhi, dMlo, ldm, work, (hipStream_t)stream);
     return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
 }
@@ -165,8 +173,7 @@ int gsvd_u_recover(int64_t m, int64_t n, const void *dA, int64_t lda, const void
     if (dU == nullptr) return -7;
     if (ldu < m) return -8;
     if (int e = check_opts(o, 9)) return e;
-    hipError_t err = gsvd::urecover_launch(o->working, m, n, dA, lda, dW, ldw, dU, ldu,
-                                           (hipStream_t)stream);
+    hipError_t err = urecover_any(o, m, n, dA, lda, dW, ldw, dU, ldu, (hipStream_t)stream);
     return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
 }
 
@@ -194,6 +201,7 @@ int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void 
     if (work_bytes < L.total) return -11;
     if (dInfo == nullptr) return -12;
     if (int e = check_eig_supported(o, n)) return e;
+    if (int e = check_gram_supported(o, n)) return e;
 
     hipStream_t st = (hipStream_t)stream;
     char *base = (char *)work;
@@ -205,7 +213,7 @@ int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void 
     err = eig_any(o, n, Mhi, Mlo, n, dS, dV, ldv, W, n, dInfo, base + L.eigw, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (want_u) {
-        err = gsvd::urecover_launch(o->working, m, n, dA, lda, W, n, dU, ldu, st);
+        err = urecover_any(o, m, n, dA, lda, W, n, dU, ldu, st);
         if (err != hipSuccess) return GSVD_ERR_HIP;
     }
     return GSVD_OK;

@@ -10,6 +10,7 @@ namespace gsvd {
 
 constexpr int GSVD_KMAX_N = 128;      // largest n the kernels are sized for
 constexpr int GSVD_KMAX_N_F64 = 96;   // FP64 working: R and V (FP64) must share LDS
+constexpr int GSVD_WIDE_MAX_N = 512;  // largest n of the wide (panel-pair) path
 
 // One problem of a batch as the batched kernels see it (device memory, written
 // by the batch set-up kernel).  Every pointer is a device address.
@@ -49,6 +50,23 @@ hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t
 hipError_t gram_batched_launch(int working, const BatchMat *tab, const int *order, int first,
                                int count, int max_nsplit, const GramPlan &p, hipStream_t st);
 hipError_t gram_reduce_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st);
+
+// Launch geometry of the wide plain Gram (gram_wide.hip, n > 128): 64-column
+// panels, one workgroup per (panel pair, slab).
+struct WidePlan {
+    int np;                  // panels
+    int npair;               // panel pairs I <= J
+    int64_t rows_per_split;  // rows of A per slab
+    int64_t nsplit;          // slabs
+    size_t part_bytes;       // workspace for the per-slab partial sums
+};
+
+// slab_rows > 0 fixes the slab height (rounded up to a multiple of 16); 0 picks
+// about 2048 workgroups in all.
+WidePlan gram_wide_plan(int64_t m, int64_t n, int64_t slab_rows = 0);
+hipError_t gram_wide_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
+                            double *Mhi, double *Mlo, int64_t ldm, void *part, const WidePlan &p,
+                            hipStream_t st);
 
 // Launch geometry of the operand-split Gram (gram_split.hip).
 struct SplitPlan {
@@ -95,6 +113,13 @@ hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *M
 hipError_t eig_batched_launch(int working, const BatchMat *tab, const int *order, int batch,
                               int max_n, double tol, int max_sweeps, hipStream_t st);
 
+// Algorithm 2 for FP64 working and n > 96 (eig_wide.hip): a sequence of
+// launches (blocked dd Cholesky, block one-sided Jacobi) over device scratch.
+size_t eig_wide_work_bytes(int64_t n);
+hipError_t eig_wide_launch(int64_t n, const double *Mhi, const double *Mlo, int64_t ldm, void *S,
+                           void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
+                           int max_sweeps, void *work, hipStream_t st);
+
 // Two-sided Jacobi eigensolver for FP32 working (eig_jacobi2.hip).  V needs
 // j2_work_bytes(n) of device scratch (0 while it fits LDS, n <= 96).
 size_t j2_work_bytes(int64_t n);
@@ -113,5 +138,8 @@ hipError_t urecover_launch(int working, int64_t m, int64_t n, const void *A, int
 hipError_t urecover_batched_launch(int working, const BatchMat *tab, const int *order, int first,
                                    int count, int nt, int64_t max_m, hipStream_t st);
 int urecover_batched_max_nt(int working);
+// n > 128: workgroups of 256 rows x 128 columns, W staged in k-chunks.
+hipError_t urecover_wide_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
+                                const void *W, int64_t ldw, void *U, int64_t ldu, hipStream_t st);
 
 }  // namespace gsvd

@@ -145,11 +145,21 @@ def test_single_hip_runtime_in_process():
     assert len(paths) == 1, paths
 
 
-def test_fp64_eigensolver_limit():
-    o = gs.opts(gs.GSVD_F64)
-    rc = gs.gsvd_thin(1000, 97, FAKE, 1000, FAKE, FAKE, 97, FAKE, 1000, FAKE, 1 << 40, FAKE,
+def test_wide_limits():
+    """n in 129..512 runs the wide kernels; the FP32 eigensolver stops at n = 128."""
+    o = gs.opts(gs.GSVD_F32)
+    rc = gs.gsvd_thin(1000, 129, FAKE, 1000, FAKE, FAKE, 129, FAKE, 1000, FAKE, 1 << 40, FAKE,
                       ctypes.byref(o), None)
     assert rc == -101
+    o = gs.opts(gs.GSVD_F64)
+    for n in (97, 129, 512):
+        t = gs.gsvd_thin_workspace_size(4 * n, n, ctypes.byref(o))
+        e = gs.gsvd_eig_workspace_size(n, ctypes.byref(o))
+        assert t % 256 == 0 and e > 4 * n * n * 8 and t > e
+    assert gs.gsvd_eig_workspace_size(96, ctypes.byref(o)) == 0
+    c = gs.gram_config(2_000_000, 512, gs.GSVD_F64, gs.GSVD_GRAM_PLAIN)
+    assert c["n_slices"] == 0 and c["slab_rows"] % 16 == 0
+    assert c["slab_rows"] * c["n_slabs"] >= 2_000_000 > c["slab_rows"] * (c["n_slabs"] - 1)
 
 
 def _batch_call(batch=3, M=(1000, 2000, 500), N=(16, 64, 8), lda=None, ldv=None, ldu=None,
