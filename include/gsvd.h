@@ -103,7 +103,9 @@ typedef struct {
     unsigned flags;     /* GSVD_WANT_U ... */
     int64_t slab_rows;  /* rows of A per Gram workgroup ("slab"); 0 = the library's tuning
                            table (written by paper_2603_11953_amd/autotune.py), falling
-                           back to about 512 (plain) / 1024 (split) slabs per matrix */
+                           back to about 512 (plain) / 1024 (split) slabs per matrix.
+                           n > 128, split form: a cap on the rows per pass of the int8
+                           digit planes (multiples of 8192; 0 = about 1 GiB of planes) */
 } gsvd_opts;
 
 /* Fill *o with the defaults for the given working precision (WANT_U set). */

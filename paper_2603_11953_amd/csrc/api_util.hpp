@@ -69,11 +69,10 @@ inline int check_eig_supported(const gsvd_opts *o, int64_t n) {
     return 0;
 }
 
-// the Gram forms in force for n: the wide split Gram is not built
+// the Gram forms in force for n (every form exists for every n up to GSVD_MAX_N)
 inline int check_gram_supported(const gsvd_opts *o, int64_t n) {
-    if (int e = check_supported(o)) return e;
-    if (wide_n(n) && use_split(o)) return GSVD_ERR_UNSUPPORTED;
-    return 0;
+    (void)n;
+    return check_supported(o);
 }
 
 // slice count of the split Gram: the caller's, else the tuning table's
@@ -100,7 +99,9 @@ inline SplitPlan split_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool ba
 
 // workspace bytes for the partial sums of whichever Gram form o selects
 inline size_t gram_part_bytes(int64_t m, int64_t n, const gsvd_opts *o, bool batched) {
-    if (wide_n(n)) return use_split(o) ? 0 : gram_wide_plan(m, n, o->slab_rows).part_bytes;
+    if (wide_n(n))
+        return use_split(o) ? split_wide_plan(m, n, slices_of(o, n), o->slab_rows).part_bytes
+                            : gram_wide_plan(m, n, o->slab_rows).part_bytes;
     if (use_split(o)) return split_plan_of(o, m, n, batched).part_bytes;
     return gram_plan_of(o, m, n, batched).part_bytes;
 }

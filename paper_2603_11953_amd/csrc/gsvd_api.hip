@@ -18,6 +18,10 @@ namespace {
 
 hipError_t gram_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A, int64_t lda,
                     double *Mhi, double *Mlo, int64_t ldm, void *part, hipStream_t st) {
+    if (wide_n(n) && use_split(o)) {
+        SplitWidePlan p = split_wide_plan(m, n, slices_of(o, n), o->slab_rows);
+        return split_wide_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
+    }
     if (wide_n(n)) {
         WidePlan p = gram_wide_plan(m, n, o->slab_rows);
         return gram_wide_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
@@ -96,7 +100,12 @@ int gsvd_gram_config(int64_t m, int64_t n, const gsvd_opts *o, int64_t *slab_row
     if (int e = check_gram_supported(o, n)) return e;
     int64_t rows, slabs;
     int S = 0;
-    if (wide_n(n)) {
+    if (wide_n(n) && use_split(o)) {
+        const SplitWidePlan p = split_wide_plan(m, n, slices_of(o, n), o->slab_rows);
+        rows = 2048;  // the exponent slab of the wide split form
+        slabs = (m + rows - 1) / rows;
+        S = p.S;
+    } else if (wide_n(n)) {
         const WidePlan p = gram_wide_plan(m, n, o->slab_rows);
         rows = p.rows_per_split;
         slabs = p.nsplit;

@@ -68,6 +68,24 @@ hipError_t gram_wide_launch(int working, int64_t m, int64_t n, const void *A, in
                             double *Mhi, double *Mlo, int64_t ldm, void *part, const WidePlan &p,
                             hipStream_t st);
 
+// Operand-split Gram for n > 128 (gram_split_wide.hip): slicing into int8 digit
+// planes in the workspace, then int8 SYRK per 64-column panel pair, in passes
+// of rows_per_pass rows.  The workspace holds the planes and exponents of one
+// pass and the per-group double-double slots.
+struct SplitWidePlan {
+    int S;                   // slices per entry
+    int np, npair, npad;     // panels, panel pairs, n rounded up to 64
+    int64_t groups_per_pass; // 8192-row groups (one syrk workgroup row) per pass
+    int64_t rows_per_pass;
+    int64_t npass;
+    size_t plane_off, expo_off, slot_off, part_bytes;
+};
+// rows_cap > 0 caps the rows per pass (rounded down to a multiple of 8192, at least 8192)
+SplitWidePlan split_wide_plan(int64_t m, int64_t n, int S, int64_t rows_cap = 0);
+hipError_t split_wide_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
+                             double *Mhi, double *Mlo, int64_t ldm, void *work,
+                             const SplitWidePlan &p, hipStream_t st);
+
 // Launch geometry of the operand-split Gram (gram_split.hip).
 struct SplitPlan {
     int S;                   // slices per entry

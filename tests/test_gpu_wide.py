@@ -162,3 +162,118 @@ def test_wide_info_codes():
     assert _thin(Nn)[3] == 3
     say("wide info max_sweeps=1")
     assert _thin(A, max_sweeps=1)[3] == 2
+
+
+# ------------------------------------------------------------------ wide split Gram
+
+def _wide_split_bound(A, S):
+    """Error model of the wide split form: exponents per 2048-row slab,
+    E_j = ilogb(slab max of column j) + 4; each row adds at most (S + 3) 2^(E_i + E_j - 8 S)."""
+    A = np.abs(A.astype(np.float64))
+    m, n = A.shape
+    rps = 2048
+    Ap = np.vstack([A, np.zeros(((-m) % rps, n))])
+    smax = Ap.reshape(-1, rps, n).max(axis=1)
+    with np.errstate(divide="ignore"):
+        e = np.where(smax > 0, np.floor(np.log2(np.where(smax > 0, smax, 1.0))) + 4, -np.inf)
+    p2 = np.where(np.isfinite(e), 2.0 ** e, 0.0)
+    return (S + 3) * 2.0 ** (-8 * S) * rps * (p2.T @ p2)
+
+
+def _gram_split_wide(A, S, rows_cap=0):
+    import ctypes
+
+    import torch
+
+    import paper_2603_11953_amd as gs
+    w = gs.GSVD_F64 if A.dtype == np.float64 else gs.GSVD_F32
+    m, n = A.shape
+    o = gs.opts(w, gs.GSVD_GRAM_SPLIT, n_slices=S, slab_rows=rows_cap)
+    dA = to_dev(A)
+    Mhi = gs.colmajor_empty(n, n, torch.float64, dA.device)
+    Mlo = gs.colmajor_empty(n, n, torch.float64, dA.device)
+    work = gs.workspace(gs.gsvd_gram_workspace_size(m, n, ctypes.byref(o)), dA.device)
+    rc = gs.gsvd_gram(m, n, dA.data_ptr(), m, Mhi.data_ptr(), Mlo.data_ptr(), n, work.data_ptr(),
+                      work.numel(), ctypes.byref(o), gs._stream(None))
+    assert rc == 0, rc
+    torch.cuda.synchronize()
+    return to_np(Mhi), to_np(Mlo)
+
+
+@pytest.mark.parametrize("m,n,dt,S,cap", [
+    (3000, 129, "f64", 10, 0), (20_011, 512, "f64", 9, 0), (9001, 200, "f64", 4, 0),
+    (300, 300, "f64", 12, 0), (3 * 8192 + 123, 150, "f64", 9, 8192),
+    (5000, 257, "f32", 6, 0), (777, 300, "f32", 3, 0), (2 * 8192 + 5, 190, "f32", 8, 8192),
+])
+def test_wide_split_gram_parity(m, n, dt, S, cap):
+    """Panel-pair split Gram vs the dd oracle within the digit error model plus dd rounding;
+    cap > 0 forces several passes over the digit planes."""
+    A = g.make_a(g.MatrixSpec(m=m, n=n, kappa_b=30, kappa_d=1e6, mode_b=3, mode_d=5,
+                              seed=4000 + m + n, dtype=dt, shuffle=True, w1="gauss"))
+    say("wide split gram", m, n, dt, S, cap)
+    Mh, Ml = _gram_split_wide(A, S, cap)
+    oh, ol = ref.gram_dd(A)
+    diff = np.abs((Mh - oh) + (Ml - ol)) if dt == "f64" else np.abs((Mh - oh) - ol)
+    absA = np.abs(A.astype(np.float64))
+    rnd = (4 * m * (U_DD if dt == "f64" else 2.0 ** -53)) * (absA.T @ absA)
+    bound = _wide_split_bound(A, S) + rnd
+    assert np.array_equal(Mh, Mh.T)
+    assert np.all(diff <= bound + 1e-300), float(np.max(diff / np.maximum(bound, 1e-300)))
+
+
+def test_wide_split_gram_exact_on_short_integer_entries():
+    """20-bit integers times 2^c: only the first three digits are non-zero, S = 7 keeps all
+    their pairs, so the Gram must equal the oracle's bit for bit (checks the plane layout,
+    the LDS swizzle and the exact combination)."""
+    rng = np.random.default_rng(7)
+    A = rng.integers(-(2 ** 20), 2 ** 20, size=(5000, 200)).astype(np.float64)
+    A *= 2.0 ** rng.integers(-30, 30, size=200)[None, :]
+    A = np.asfortranarray(A)
+    say("wide split gram exact")
+    Mh, Ml = _gram_split_wide(A, 7, 8192)
+    oh, ol = ref.gram_dd(A)
+    assert np.array_equal(Mh, oh) and np.array_equal(Ml, ol)
+
+
+def test_wide_split_gram_deterministic_and_pass_invariant():
+    """Same result run to run; with exponents fixed per slab the sums are exact per slab, so the
+    pass structure only changes the dd rounding of the slot additions."""
+    A = g.make_a(g.MatrixSpec(m=5 * 8192 + 77, n=160, kappa_b=100, kappa_d=1e10, seed=8,
+                              shuffle=True, w1="gauss"))
+    say("wide split gram determinism")
+    r1 = _gram_split_wide(A, 9)
+    r2 = _gram_split_wide(A, 9)
+    assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+    r3 = _gram_split_wide(A, 9, 8192)
+    scale = np.abs(A).T @ np.abs(A)
+    assert np.all(np.abs((r3[0] - r1[0]) + (r3[1] - r1[1])) <= 64 * U_DD * scale)
+
+
+@pytest.mark.parametrize("spec", [
+    g.MatrixSpec(m=30_000, n=200, kappa_b=100, kappa_d=1e10, mode_b=3, mode_d=3, seed=11,
+                 shuffle=True),
+    g.MatrixSpec(m=9_001, n=131, kappa_b=1e3, kappa_d=1e12, mode_b=3, mode_d=3, seed=12,
+                 shuffle=True, w1="gauss"),
+], ids=["m3e4n200-f64", "m9001n131-f64-kb1e3"])
+def test_wide_thin_split_end_to_end(spec):
+    """The split form with the default slice count meets the plain form's tolerances."""
+    import paper_2603_11953_amd as gs
+    A = g.make_a(spec)
+    o = ref.svd(A)
+    say("wide thin split", spec.m, spec.n)
+    S, V, Uo, info = _thin(A, gram=gs.GSVD_GRAM_SPLIT)
+    assert info == 0
+    rep = check_thin(A, S, V, Uo, o, label=str(spec))
+    if o.kappa_b <= 100.5:
+        assert rep["u_orth_meets_50nu"], rep
+
+
+def test_wide_split_exact_spectrum_n512():
+    import paper_2603_11953_amd as gs
+    exps = [int(36 * b / 127) for b in range(128)]
+    E = g.hadamard_exact(5, 512, block_exps=exps, dtype="f64", seed=9, col_perm=True)
+    say("wide split hadamard 512")
+    S, V, Uo, info = _thin(E.A, gram=gs.GSVD_GRAM_SPLIT)
+    assert info == 0
+    err = np.abs(S - E.sigma) / E.sigma
+    assert err.max() <= sigma_tol(512, 2.0 ** -53, E.kappa_b), err.max()
