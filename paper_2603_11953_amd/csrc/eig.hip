@@ -35,6 +35,7 @@
 
 #include "dd_device.hpp"
 #include "gsvd_internal.hpp"
+#include "jacobi_math.hpp"
 
 namespace gsvd {
 
@@ -101,27 +102,6 @@ __device__ __forceinline__ double group_sum(double x) {
     x += dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
     x += dpp_d<0x141>(x);  // row_half_mirror
     return x;
-}
-
-// ---- reciprocal and reciprocal square root: hardware estimate + Newton
-
-__device__ __forceinline__ double rcp_nr(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
-    return __builtin_fma(r, e, r);
-}
-
-__device__ __forceinline__ double rsq_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double h = x * y;
-        const double e = __builtin_fma(-h, y, 1.0);  // 1 - x y^2
-        y = __builtin_fma(0.5 * y, e, y);
-    }
-    return y;
 }
 
 // Workgroup-shared state of the eigensolver besides the dynamic LDS square.

@@ -16,17 +16,22 @@
 //      A non-positive pivot stops the factorization with info 1.
 //   3. X = fl64(R_H) D~ 2^-e_max (Alg. 2 step 2; exact scalings).
 //   4. One-sided Jacobi on the columns of X (Alg. 2 step 3), block form: the
-//      columns are cut into blocks of 8; a step pairs the blocks by a round-
-//      robin tournament and gives each pair of blocks (16 columns of X and the
-//      same 16 columns of V, all n rows) to one workgroup, which holds them in
-//      LDS and rotates the 64 pairs across the two blocks (8 rounds of 8
-//      disjoint pairs, one wavefront each); the first step of a tournament
-//      round, where every block appears once, also rotates the 28 pairs inside
-//      each block (7 more rounds).  So every pair of columns is visited once
-//      per round, as in a cyclic sweep.  The three inner products are summed
-//      by an xor butterfly, which leaves bitwise identical sums in every lane;
-//      every rotation is applied to the columns of X and of V as it is found,
-//      as in the one-workgroup kernel.  One launch per
+//      columns are cut into blocks of 16; a step pairs the blocks by a round-
+//      robin tournament and gives each pair of blocks (32 columns of X, all n
+//      rows) to one workgroup, which holds them in LDS and rotates the 256
+//      pairs across the two blocks (16 rounds of 16 disjoint pairs, one
+//      wavefront each); the first step of a tournament round, where every
+//      block appears once, also rotates the 120 pairs inside each block (15
+//      more rounds).  So every pair of columns is visited once
+//      per round, as in a cyclic sweep.  In the cross rounds a block-P column
+//      stays in the registers of its wavefront and only the block-Q columns
+//      move through LDS.  The three inner products are summed by a cross-lane
+//      reduction that leaves bitwise identical sums in every lane; the rotation
+//      parameters use the hardware reciprocal and reciprocal square root
+//      refined by Newton steps, as in the one-workgroup kernel.  The
+//      rotations of a step accumulate in a 32 x 32 product Q, and the same 32
+//      columns of V, staged through LDS, are multiplied by Q once at the end of
+//      the step (one row per lane).  One launch per
 //      step; after each tournament round a one-lane kernel marks convergence
 //      when no rotation passed the test |x_p^T x_q| > tol ||x_p|| ||x_q||, and
 //      later launches return at once.
@@ -39,24 +44,27 @@
 
 #include "dd_device.hpp"
 #include "gsvd_internal.hpp"
+#include "jacobi_math.hpp"
 
 namespace gsvd {
 
 namespace {
 
 constexpr int CB = 64;       // Cholesky panel width
-constexpr int JB = 8;        // Jacobi block width (columns)
+constexpr int JB = 16;       // Jacobi block width (columns)
 constexpr int JC = 2 * JB;   // columns held by one workgroup
 constexpr int JT = 64 * JB;  // Jacobi workgroup size: one wavefront per column pair of a round
 constexpr int UT = 1024;     // update-kernel workgroup (32 x 32 tile)
 
+constexpr int MAXWG = 64;    // Jacobi workgroups per step: ceil(512 / 16) / 2 = 16 at most
+
 struct Ctl {
     int bad;      // info code of a failed check (1 or 3), 0 otherwise
     int emax;     // max e_j
-    int rot;      // rotations in the current tournament round
     int done;     // converged
     int notconv;  // max_sweeps reached without convergence
     int abort;    // the output kernel must not write
+    int rot[MAXWG];  // per step workgroup: some rotation in the current tournament round
 };
 
 struct WLayout {
@@ -98,6 +106,7 @@ weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, i
         emax = -100000;
     }
     __syncthreads();
+    for (int t = threadIdx.x; t < MAXWG; t += blockDim.x) ctl->rot[t] = 0;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const double mjj = Mhi[j + (int64_t)j * ldm];
         if (!(mjj > 0.0) || !__builtin_isfinite(mjj)) {
@@ -113,7 +122,6 @@ weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, i
     if (threadIdx.x == 0) {
         ctl->bad = bad;
         ctl->emax = emax;
-        ctl->rot = 0;
         ctl->done = 0;
         ctl->notconv = 0;
         ctl->abort = 0;
@@ -277,10 +285,31 @@ weig_cast_kernel(int n, const Ctl *ctl, const int *__restrict__ sexp,
 
 // ---- 4. block one-sided Jacobi
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the wavefront, the same bits in every lane: within each row of 16
+// lanes xor 1, xor 2 (quad permutes), the half-row mirror and the row mirror
+// (each step adds two lanes holding the same partials in swapped order), then
+// the four row sums read out of lanes 0, 16, 32, 48 and added in a fixed order.
 __device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-    return x;
+    x += dpp_d<0xB1>(x);
+    x += dpp_d<0x4E>(x);
+    x += dpp_d<0x141>(x);
+    x += dpp_d<0x140>(x);
+    return (readlane_d(x, 0) + readlane_d(x, 16)) + (readlane_d(x, 32) + readlane_d(x, 48));
 }
 
 // round-robin tournament on m (even) players: pair g of round r
@@ -301,7 +330,7 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
     extern __shared__ __attribute__((aligned(16))) double jsm[];
     constexpr int LDL = 64 * RPL;  // rows of a column in LDS (n rounded up to 64)
     double *Xl = jsm;              // JC columns of X
-    double *Vl = jsm + JC * LDL;   // the same JC columns of V
+    double *Qs = jsm + JC * LDL;   // JC x JC rotation product, column-major
     if (wg_read(&ctl->bad) || wg_read(&ctl->done)) return;
     int P, Qb;
     rr_pair(step, blockIdx.x, nblk, P, Qb);
@@ -311,89 +340,159 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
     if ((P >= nbb && Qb >= nbb) || ((P >= nbb || Qb >= nbb) && step != 0)) return;
     const int tid = threadIdx.x;
     auto gcol = [&](int c) { return c < JB ? JB * P + c : JB * Qb + (c - JB); };
-    for (int q = tid; q < JC * LDL; q += JT) {
-        const int r = q % LDL, c = q / LDL;
-        const int g = gcol(c);
-        const bool in = r < n && g < n;
-        Xl[q] = in ? X[r + (size_t)g * n] : 0.0;
-        Vl[q] = in ? Vw[r + (size_t)g * n] : 0.0;
-    }
+    constexpr int NLD = JC * LDL / JT;  // block values per lane
+    // stage the 16 columns of a matrix (X or V) into Xl: every load issued first
+    auto stage = [&](const double *__restrict__ src) {
+        double v[NLD];
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int q = tid + k * JT;
+            const int r = q % LDL, g = gcol(q / LDL);
+            v[k] = (r < n && g < n) ? src[r + (size_t)g * n] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) Xl[tid + k * JT] = v[k];
+    };
+    stage(X);
+    for (int q = tid; q < JC * JC; q += JT) Qs[q] = (q % JC == q / JC) ? 1.0 : 0.0;
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6;
     bool any = false;
-    // rounds 0 .. JB-2 (first step only): pairs inside block P (wavefronts
-    // 0 .. JB/2-1) and inside block Q; then JB rounds of cross pairs (i, JB + (i + r) mod JB)
-    const int r0 = step == 0 ? 0 : JB - 1;
-    for (int round = r0; round < 2 * JB - 1; ++round) {
-        int p, q;
-        if (round < JB - 1) {
-            const int h = wave / (JB / 2), g = wave % (JB / 2);
-            rr_pair(round, g, JB, p, q);
-            p += JB * h;
-            q += JB * h;
-        } else {
-            p = wave;
-            q = JB + (wave + round - (JB - 1)) % JB;
-        }
-        double *xp = Xl + p * LDL + lane, *xq = Xl + q * LDL + lane;
-        double a0[RPL], a1[RPL];
+    // one plane rotation of columns x0 (p) and x1 (q), held in registers; also on Q
+    auto rotate = [&](double (&x0)[RPL], double (&x1)[RPL], int p, int q) -> bool {
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
-            a0[i] = xp[64 * i];
-            a1[i] = xq[64 * i];
-            al = __builtin_fma(a0[i], a0[i], al);
-            be = __builtin_fma(a1[i], a1[i], be);
-            ga = __builtin_fma(a0[i], a1[i], ga);
+            al = __builtin_fma(x0[i], x0[i], al);
+            be = __builtin_fma(x1[i], x1[i], be);
+            ga = __builtin_fma(x0[i], x1[i], ga);
         }
         al = wave_sum(al);
         be = wave_sum(be);
         ga = wave_sum(ga);
-        if (ga * ga > tol2 * (al * be)) {  // uniform: the sums agree bitwise across lanes
-            const double zeta = (be - al) / (2.0 * ga);
-            const double az = __builtin_fabs(zeta);
-            double tn;
-            if (az > 1e150) {
-                tn = 0.5 / zeta;
-            } else {
-                tn = 1.0 / (az + __builtin_sqrt(__builtin_fma(zeta, zeta, 1.0)));
-                if (zeta < 0) tn = -tn;
-            }
-            const double c = 1.0 / __builtin_sqrt(__builtin_fma(tn, tn, 1.0));
-            const double sn = c * tn;
-            double *vp = Vl + p * LDL + lane, *vq = Vl + q * LDL + lane;
+        if (!(ga * ga > tol2 * (al * be))) return false;  // uniform: the sums agree bitwise
+        const double zeta = (be - al) * rcp_nr(2.0 * ga);
+        const double az = __builtin_fabs(zeta);
+        double tn;
+        if (az > 1e150) {
+            tn = 0.5 * rcp_nr(zeta);
+        } else {
+            const double x = __builtin_fma(zeta, zeta, 1.0);
+            tn = rcp_nr(az + x * rsq_nr(x));
+            if (zeta < 0) tn = -tn;
+        }
+        const double c = rsq_nr(__builtin_fma(tn, tn, 1.0));
+        const double sn = c * tn;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const double a0 = x0[i], a1 = x1[i];
+            x0[i] = c * a0 - sn * a1;
+            x1[i] = sn * a0 + c * a1;
+        }
+        if (lane < JC) {
+            const double u = Qs[lane + p * JC], w = Qs[lane + q * JC];
+            Qs[lane + p * JC] = c * u - sn * w;
+            Qs[lane + q * JC] = sn * u + c * w;
+        }
+        return true;
+    };
+    double x0[RPL], x1[RPL];
+    // first step of a round: the pairs inside block P (wavefronts 0 .. JB/2-1) and
+    // inside block Q, both columns from LDS
+    if (step == 0) {
+        for (int round = 0; round < JB - 1; ++round) {
+            const int h = wave / (JB / 2), g = wave % (JB / 2);
+            int p, q;
+            rr_pair(round, g, JB, p, q);
+            p += JB * h;
+            q += JB * h;
+            double *xp = Xl + p * LDL + lane, *xq = Xl + q * LDL + lane;
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
-                xp[64 * i] = c * a0[i] - sn * a1[i];
-                xq[64 * i] = sn * a0[i] + c * a1[i];
-                const double u = vp[64 * i], w = vq[64 * i];
-                vp[64 * i] = c * u - sn * w;
-                vq[64 * i] = sn * u + c * w;
+                x0[i] = xp[64 * i];
+                x1[i] = xq[64 * i];
             }
-            any = true;
+            if (rotate(x0, x1, p, q)) {
+                any = true;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    xp[64 * i] = x0[i];
+                    xq[64 * i] = x1[i];
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
-    for (int q = tid; q < JC * LDL; q += JT) {
-        const int r = q % LDL, c = q / LDL;
-        const int g = gcol(c);
-        if (r < n && g < n) {
-            X[r + (size_t)g * n] = Xl[q];
-            Vw[r + (size_t)g * n] = Vl[q];
+    // the cross pairs (i, JB + (i + r) mod JB): column i of block P stays in the
+    // registers of wavefront i for all JB rounds; the block-Q columns travel
+    {
+        const int p = wave;
+        double *xp = Xl + p * LDL + lane;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) x0[i] = xp[64 * i];
+        for (int r = 0; r < JB; ++r) {
+            const int q = JB + (wave + r) % JB;
+            double *xq = Xl + q * LDL + lane;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) x1[i] = xq[64 * i];
+            if (rotate(x0, x1, p, q)) {
+                any = true;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) xq[64 * i] = x1[i];
+            }
+            __syncthreads();  // the travelers move on
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) xp[64 * i] = x0[i];
+    }
+    __syncthreads();
+    // X back; then V(:, block pair) = V(:, block pair) Q with the V columns staged in LDS
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int q = tid + k * JT;
+        const int r = q % LDL, g = gcol(q / LDL);
+        if (r < n && g < n) X[r + (size_t)g * n] = Xl[q];
+    }
+    __syncthreads();
+    stage(Vw);
+    __syncthreads();
+    static_assert(JT >= GSVD_WIDE_MAX_N, "one row of V per lane");
+    if (tid < n) {
+        const int r = tid;
+#pragma unroll 1
+        for (int c0 = 0; c0 < JC; c0 += 16) {  // 16 output columns at a time
+            double out[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) out[c] = 0.0;
+#pragma unroll 4
+            for (int t = 0; t < JC; ++t) {
+                const double vt = Xl[r + t * LDL];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) out[c] = __builtin_fma(vt, Qs[t + (c0 + c) * JC], out[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int g = gcol(c0 + c);
+                if (g < n) Vw[r + (size_t)g * n] = out[c];
+            }
         }
     }
-    if (any && lane == 0) atomicAdd(&ctl->rot, 1);
+    // one plain store per workgroup into its own word (no contended atomics)
+    if (__syncthreads_or(any) && tid == 0) ctl->rot[blockIdx.x] = 1;
 }
 
-// end of a tournament round (one lane)
-__global__ void weig_sweep_kernel(Ctl *ctl, int last) {
-    if (threadIdx.x != 0 || ctl->bad || ctl->done) return;
-    if (ctl->rot == 0) {
-        ctl->done = 1;
-    } else {
-        ctl->rot = 0;
-        if (last) ctl->notconv = 1;
+// end of a tournament round (one wavefront): converged when no workgroup rotated;
+// the flags are cleared for the next round
+__global__ void __launch_bounds__(64) weig_sweep_kernel(Ctl *ctl, int nwg, int last) {
+    const int t = threadIdx.x;
+    if (ctl->bad || ctl->done) return;  // written by earlier launches only
+    const int r = t < nwg ? ctl->rot[t] : 0;
+    const bool anyrot = __any(r != 0);
+    if (t < nwg) ctl->rot[t] = 0;
+    if (t == 0) {
+        if (!anyrot) ctl->done = 1;
+        else if (last) ctl->notconv = 1;
     }
 }
 
@@ -486,7 +585,7 @@ weig_out_kernel(int n, const Ctl *ctl, const double *__restrict__ Vw,
 template <int RPL>
 hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double tol2,
                         int max_sweeps, hipStream_t st) {
-    const size_t lds = (size_t)2 * JC * 64 * RPL * sizeof(double);
+    const size_t lds = ((size_t)JC * 64 * RPL + JC * JC) * sizeof(double);
     auto k = weig_step_kernel<RPL>;
     hipError_t err = hipFuncSetAttribute((const void *)k,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -497,7 +596,7 @@ hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double
                                X, Vw, tol2);
             if ((err = hipGetLastError()) != hipSuccess) return err;
         }
-        hipLaunchKernelGGL(weig_sweep_kernel, dim3(1), dim3(64), 0, st, ctl,
+        hipLaunchKernelGGL(weig_sweep_kernel, dim3(1), dim3(64), 0, st, ctl, nblk / 2,
                            sw + 1 == max_sweeps ? 1 : 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
