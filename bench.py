@@ -18,6 +18,8 @@ records whether the paper's tolerances were met.
 
     batched      = 512 FP64 problems of uneven shape through gsvd_thin_batched
                    (eager and graph-replayed) vs 512 gsvd_thin calls
+    large        = FP64 m = 2e6, n = 512, kappa(B) = 1e3: plain vs split thin SVD with
+                   stage times and oracle-checked accuracy
 """
 from __future__ import annotations
 
@@ -36,6 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = "thin-SVD GFLOP/s & Gram HBM GB/s at σ rel-err tol; split/batched vs plain"
 FP64_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # FP64 lane-operations per second, 1 per FMA
 HBM_PEAK_GBPS = 8000.0
+INT8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak (POP/s x 1e-12)
 
 
 def parse():
@@ -51,6 +54,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched leg (512 FP64 problems of uneven shape)")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large leg (FP64 m = 2e6, n = 512, plain vs split)")
+    ap.add_argument("--large-m", type=int, default=2_000_000)
+    ap.add_argument("--large-steps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB buffer 3 times (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -94,6 +101,162 @@ def measured_traffic(m: int, n: int):
     if t.get("kernel_source_hash") != kernel_source_hash() or t.get("m") != m or t.get("n") != n:
         return None
     return t.get("bytes_per_launch")
+
+
+def timed_on(torch, stream, fn, k, w_):
+    """Average ms of fn over k calls after w_ warm-up calls, events on `stream`."""
+    for _ in range(w_):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(k):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / k
+
+
+def measure_thin(torch, gs, dA, gram_mode, steps, warmup, stream, log_fn):
+    """Time gsvd_thin (FP64, Algorithm 2) on the column-major device matrix dA, and its three
+    stages through gsvd_gram, gsvd_eig and gsvd_u_recover (same kernels, same shapes)."""
+    import ctypes
+    m, n = int(dA.shape[0]), int(dA.shape[1])
+    lda = int(dA.stride(1))
+    dev = dA.device
+    sp = ctypes.c_void_p(int(stream.cuda_stream))
+    o = gs.opts(gs.GSVD_F64, gram_mode, gs.GSVD_EIG_CHOL_JACOBI1)
+    ob = ctypes.byref(o)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    V = gs.colmajor_empty(n, n, torch.float64, dev)
+    U = gs.colmajor_empty(m, n, torch.float64, dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    work = gs.workspace(gs.gsvd_thin_workspace_size(m, n, ob), dev)
+
+    def step():
+        rc = gs.gsvd_thin(m, n, dA.data_ptr(), lda, S.data_ptr(), V.data_ptr(), n, U.data_ptr(),
+                          m, work.data_ptr(), work.numel(), info.data_ptr(), ob, sp)
+        if rc != 0:
+            raise RuntimeError(f"gsvd_thin: {rc} {gs.gsvd_status_string(rc)}")
+
+    Mhi = gs.colmajor_empty(n, n, torch.float64, dev)
+    Mlo = gs.colmajor_empty(n, n, torch.float64, dev)
+    Wm = gs.colmajor_empty(n, n, torch.float64, dev)
+    gwork = gs.workspace(gs.gsvd_gram_workspace_size(m, n, ob), dev)
+    ewn = gs.gsvd_eig_workspace_size(n, ob)
+    ework = gs.workspace(ewn, dev) if ewn else None
+    S2, V2, info2 = torch.empty_like(S), torch.empty_like(V), torch.zeros_like(info)
+    U2 = torch.empty_like(U)
+
+    def ph_gram():
+        assert gs.gsvd_gram(m, n, dA.data_ptr(), lda, Mhi.data_ptr(), Mlo.data_ptr(), n,
+                            gwork.data_ptr(), gwork.numel(), ob, sp) == 0
+
+    def ph_eig():
+        assert gs.gsvd_eig(n, Mhi.data_ptr(), Mlo.data_ptr(), n, S2.data_ptr(), V2.data_ptr(), n,
+                           Wm.data_ptr(), n, info2.data_ptr(),
+                           ework.data_ptr() if ework is not None else None,
+                           ework.numel() if ework is not None else 0, ob, sp) == 0
+
+    def ph_u():
+        assert gs.gsvd_u_recover(m, n, dA.data_ptr(), lda, Wm.data_ptr(), n, U2.data_ptr(), m,
+                                 ob, sp) == 0
+
+    ms_step = timed_on(torch, stream, step, steps, warmup)
+    ms_gram = timed_on(torch, stream, ph_gram, steps, 1)
+    ms_eig = timed_on(torch, stream, ph_eig, steps, 1)
+    ms_u = timed_on(torch, stream, ph_u, steps, 1)
+    log_fn(f"{'split' if gram_mode == gs.GSVD_GRAM_SPLIT else 'plain'} m={m} n={n}: step "
+           f"{ms_step:.4f} ms, gram {ms_gram:.4f} eig {ms_eig:.4f} u {ms_u:.4f}")
+    del U2, gwork, ework, work
+    return dict(ms_step=ms_step, ms_gram=ms_gram, ms_eig=ms_eig, ms_u=ms_u, S=S, V=V, U=U,
+                info=info)
+
+
+def large_leg(args, torch, gs, g, log_fn):
+    """The large workload: FP64 A = B D, m = 2e6, n = 512, kappa(B) = 1e3, kappa(D) = 1e12
+    (log-spaced), plain (double-double Gram) against split (int8 slices) thin SVD.
+
+    A = W1 Y is built on the GPU with W1 orthonormal (QR of a seeded Gaussian), so its
+    singular values are those of the 512 x 512 factor Y up to the rounding of the product;
+    the oracle computes sigma(Y) in double-double (in a thread, while the GPU legs run).
+    U's orthogonality is measured with the library's double-double Gram of U (parity-tested
+    against the oracle's Gram separately); the residual on sampled rows by the oracle."""
+    import threading
+
+    from oracle import ref
+    spec = g.spec_large_f64(m=args.large_m)
+    spec.w1 = "qr"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    dA, Y = g.make_a_device(spec, dev)
+    torch.cuda.synchronize()
+    m, n = spec.m, spec.n
+    log_fn(f"large: generated A {m}x{n} on the GPU in {time.time() - t0:.1f}s")
+    holder = {}
+    th = threading.Thread(target=lambda: holder.update(o=ref.svd(Y)))
+    th.start()
+    stream = torch.cuda.current_stream()
+    res = {}
+    for form, gram in (("plain", gs.GSVD_GRAM_PLAIN), ("split", gs.GSVD_GRAM_SPLIT)):
+        r = measure_thin(torch, gs, dA, gram, args.large_steps, 1, stream, log_fn)
+        res[form] = r
+    th.join()
+    oracle = holder["o"]
+    flops = m * n * (n + 1) + 2 * m * n * n
+    u = 2.0 ** -53
+    rows = np.unique(np.random.default_rng(1).integers(0, m, 4000))
+    idx = torch.from_numpy(rows).to(dev)
+    A_s = dA.index_select(0, idx).cpu().numpy()
+    out = {"workload": f"FP64 A=BD m={m} n={n} kappa(B)=1e3 kappa(D)=1e12 (log-spaced); "
+                       "plain double-double Gram vs split int8-slice Gram, Algorithm 2 "
+                       "eigensolver (blocked dd Cholesky, block one-sided Jacobi), MFMA U",
+           "m": m, "n": n, "kappa_b_oracle": oracle.kappa_b}
+    for form, r in res.items():
+        Sn = r["S"].cpu().numpy()
+        Vn = r["V"].t().contiguous().cpu().numpy().T
+        Mh, Ml = gs.gram(r["U"])
+        torch.cuda.synchronize()
+        E = (Mh.cpu().numpy() - np.eye(n)) + Ml.cpu().numpy()
+        orth = float(np.linalg.norm(E))
+        U_s = r["U"].index_select(0, idx).cpu().numpy()
+        resid = ref.resid(A_s, U_s, Sn, Vn)
+        err = float(ref.sigma_rel_err(Sn, oracle).max())
+        acc = {"info": int(r["info"].item()), "sigma_max_rel_err": err,
+               "sigma_tol_50nu_kappaB": 50 * n * u * oracle.kappa_b, "u_orth": orth,
+               "orth_tol_50nu": 50 * n * u, "resid_sampled_rows": resid}
+        # Algorithm 2 keeps U orthogonal to O(u) kappa(B) (Remark 2); the kappa(B)-free
+        # target 50 n u is reported beside it
+        acc["orth_tol_alg2_50nu_kappaB"] = 50 * n * u * oracle.kappa_b
+        acc["u_orth_meets_50nu"] = bool(orth <= 50 * n * u)
+        acc["meets_tol"] = bool(acc["info"] == 0 and err <= acc["sigma_tol_50nu_kappaB"]
+                                and orth <= acc["orth_tol_alg2_50nu_kappaB"]
+                                and resid <= 50 * n * u)
+        out[form] = {"ms_per_step": round(r["ms_step"], 4),
+                     "value_gflops": round(flops / (r["ms_step"] * 1e-3) / 1e9, 2),
+                     "phases_ms": {"gram": round(r["ms_gram"], 4), "eig": round(r["ms_eig"], 4),
+                                   "u": round(r["ms_u"], 4)},
+                     "accuracy": acc}
+        log_fn(f"large {form}: {acc}")
+    cfg = gs.gram_config(m, n, gs.GSVD_F64, gs.GSVD_GRAM_SPLIT)
+    out["split"]["gram"] = f"int8-slices-{cfg['n_slices']}"
+    out["split_speedup_vs_plain"] = round(res["plain"]["ms_step"] / res["split"]["ms_step"], 3)
+    out["split_gram_speedup_vs_plain"] = round(res["plain"]["ms_gram"] / res["split"]["ms_gram"], 3)
+    # rooflines of the two Gram forms at this size: dd FMA work on the FP64 vector units,
+    # digit-pair products on the int8 matrix cores
+    dd_ops = 10 * m * n * (n + 1) // 2
+    S_ = cfg["n_slices"]
+    i8_ops = 2 * m * (n * (n + 1) // 2) * (S_ * (S_ + 1) // 2)
+    out["plain"]["gram_alu_frac"] = round(dd_ops / (res["plain"]["ms_gram"] * 1e-3) / 1e12
+                                          / FP64_VALU_PEAK_TOPS, 4)
+    out["split"]["gram_int8_tops"] = round(i8_ops / (res["split"]["ms_gram"] * 1e-3) / 1e12, 1)
+    out["split"]["gram_int8_frac"] = round(i8_ops / (res["split"]["ms_gram"] * 1e-3) / 1e12
+                                           / INT8_PEAK_TOPS, 4)
+    del res, dA
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_leg(args, torch, gs, g, log_fn):
@@ -217,69 +380,10 @@ def main():
     A = g.make_a(spec)
     log(f"generated A {m}x{n} fp64 in {time.time() - t0:.1f}s")
     dA = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev).t()
-    lda = m
-    import ctypes
-
     stream = torch.cuda.current_stream()
-    sp = ctypes.c_void_p(int(stream.cuda_stream))
-
-    def timed(fn, k, w_):
-        for _ in range(w_):
-            fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(k):
-            fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / k  # ms
 
     def measure(gram_mode):
-        """Time gsvd_thin and its three phases (same kernels, same launch shapes)."""
-        o = gs.opts(gs.GSVD_F64, gram_mode, gs.GSVD_EIG_CHOL_JACOBI1)
-        ob = ctypes.byref(o)
-        S = torch.empty(n, dtype=torch.float64, device=dev)
-        V = gs.colmajor_empty(n, n, torch.float64, dev)
-        U = gs.colmajor_empty(m, n, torch.float64, dev)
-        info = torch.zeros(1, dtype=torch.int32, device=dev)
-        work = gs.workspace(gs.gsvd_thin_workspace_size(m, n, ob), dev)
-
-        def step():
-            rc = gs.gsvd_thin(m, n, dA.data_ptr(), lda, S.data_ptr(), V.data_ptr(), n,
-                              U.data_ptr(), m, work.data_ptr(), work.numel(), info.data_ptr(),
-                              ob, sp)
-            if rc != 0:
-                raise RuntimeError(f"gsvd_thin: {rc} {gs.gsvd_status_string(rc)}")
-
-        Mhi = gs.colmajor_empty(n, n, torch.float64, dev)
-        Mlo = gs.colmajor_empty(n, n, torch.float64, dev)
-        Wm = gs.colmajor_empty(n, n, torch.float64, dev)
-        gwork = gs.workspace(gs.gsvd_gram_workspace_size(m, n, ob), dev)
-        S2, V2, info2, U2 = torch.empty_like(S), torch.empty_like(V), torch.zeros_like(info), \
-            torch.empty_like(U)
-
-        def ph_gram():
-            assert gs.gsvd_gram(m, n, dA.data_ptr(), lda, Mhi.data_ptr(), Mlo.data_ptr(), n,
-                                gwork.data_ptr(), gwork.numel(), ob, sp) == 0
-
-        def ph_eig():
-            assert gs.gsvd_eig(n, Mhi.data_ptr(), Mlo.data_ptr(), n, S2.data_ptr(), V2.data_ptr(),
-                               n, Wm.data_ptr(), n, info2.data_ptr(), None, 0, ob, sp) == 0
-
-        def ph_u():
-            assert gs.gsvd_u_recover(m, n, dA.data_ptr(), lda, Wm.data_ptr(), n, U2.data_ptr(), m,
-                                     ob, sp) == 0
-
-        ms_step = timed(step, args.steps, args.warmup)
-        ms_gram = timed(ph_gram, args.steps, 2)
-        ms_eig = timed(ph_eig, args.steps, 2)
-        ms_u = timed(ph_u, args.steps, 2)
-        log(f"{'split' if gram_mode == gs.GSVD_GRAM_SPLIT else 'plain'}: step {ms_step:.4f} ms, "
-            f"gram {ms_gram:.4f} eig {ms_eig:.4f} u {ms_u:.4f}")
-        return dict(ms_step=ms_step, ms_gram=ms_gram, ms_eig=ms_eig, ms_u=ms_u, S=S, V=V, U=U,
-                    info=info)
+        return measure_thin(torch, gs, dA, gram_mode, args.steps, args.warmup, stream, log)
 
     def check(r, oracle):
         from oracle import ref
@@ -361,6 +465,9 @@ def main():
 
     if not args.no_batched:
         result["batched"] = batched_leg(args, torch, gs, g, log)
+
+    if not args.no_large:
+        result["large"] = large_leg(args, torch, gs, g, log)
 
     if not args.no_check:
         from oracle import ref
