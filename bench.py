@@ -18,6 +18,8 @@ records whether the paper's tolerances were met.
 
     batched      = 512 FP64 problems of uneven shape through gsvd_thin_batched
                    (eager and graph-replayed) vs 512 gsvd_thin calls
+    fp32         = FP32 m = 4e6, n = 128, kappa(B) = 1e2: plain vs split at every slice
+                   count, sigma error against the oracle per slice count
     large        = FP64 m = 2e6, n = 512, kappa(B) = 1e3: plain vs split thin SVD with
                    stage times and oracle-checked accuracy
 """
@@ -58,6 +60,10 @@ def parse():
                     help="skip the large leg (FP64 m = 2e6, n = 512, plain vs split)")
     ap.add_argument("--large-m", type=int, default=2_000_000)
     ap.add_argument("--large-steps", type=int, default=3)
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32 leg (m = 4e6, n = 128, sigma error per slice count)")
+    ap.add_argument("--f32-m", type=int, default=4_000_000)
+    ap.add_argument("--f32-steps", type=int, default=5)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB buffer 3 times (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -118,19 +124,22 @@ def timed_on(torch, stream, fn, k, w_):
     return e0.elapsed_time(e1) / k
 
 
-def measure_thin(torch, gs, dA, gram_mode, steps, warmup, stream, log_fn):
-    """Time gsvd_thin (FP64, Algorithm 2) on the column-major device matrix dA, and its three
-    stages through gsvd_gram, gsvd_eig and gsvd_u_recover (same kernels, same shapes)."""
+def measure_thin(torch, gs, dA, gram_mode, steps, warmup, stream, log_fn, n_slices=0):
+    """Time gsvd_thin on the column-major device matrix dA (working precision = its dtype,
+    the default eigensolver: Algorithm 2 for FP64, the two-sided Jacobi for FP32), and its
+    three stages through gsvd_gram, gsvd_eig and gsvd_u_recover (same kernels, same shapes)."""
     import ctypes
     m, n = int(dA.shape[0]), int(dA.shape[1])
     lda = int(dA.stride(1))
     dev = dA.device
+    dt = dA.dtype
+    w = gs.GSVD_F64 if dt == torch.float64 else gs.GSVD_F32
     sp = ctypes.c_void_p(int(stream.cuda_stream))
-    o = gs.opts(gs.GSVD_F64, gram_mode, gs.GSVD_EIG_CHOL_JACOBI1)
+    o = gs.opts(w, gram_mode, n_slices=n_slices)
     ob = ctypes.byref(o)
-    S = torch.empty(n, dtype=torch.float64, device=dev)
-    V = gs.colmajor_empty(n, n, torch.float64, dev)
-    U = gs.colmajor_empty(m, n, torch.float64, dev)
+    S = torch.empty(n, dtype=dt, device=dev)
+    V = gs.colmajor_empty(n, n, dt, dev)
+    U = gs.colmajor_empty(m, n, dt, dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     work = gs.workspace(gs.gsvd_thin_workspace_size(m, n, ob), dev)
 
@@ -142,7 +151,7 @@ def measure_thin(torch, gs, dA, gram_mode, steps, warmup, stream, log_fn):
 
     Mhi = gs.colmajor_empty(n, n, torch.float64, dev)
     Mlo = gs.colmajor_empty(n, n, torch.float64, dev)
-    Wm = gs.colmajor_empty(n, n, torch.float64, dev)
+    Wm = gs.colmajor_empty(n, n, dt, dev)
     gwork = gs.workspace(gs.gsvd_gram_workspace_size(m, n, ob), dev)
     ewn = gs.gsvd_eig_workspace_size(n, ob)
     ework = gs.workspace(ewn, dev) if ewn else None
@@ -167,11 +176,69 @@ def measure_thin(torch, gs, dA, gram_mode, steps, warmup, stream, log_fn):
     ms_gram = timed_on(torch, stream, ph_gram, steps, 1)
     ms_eig = timed_on(torch, stream, ph_eig, steps, 1)
     ms_u = timed_on(torch, stream, ph_u, steps, 1)
-    log_fn(f"{'split' if gram_mode == gs.GSVD_GRAM_SPLIT else 'plain'} m={m} n={n}: step "
+    log_fn(f"{'split' if gram_mode == gs.GSVD_GRAM_SPLIT else 'plain'} m={m} n={n} {dt}"
+           f"{' S=' + str(n_slices) if n_slices else ''}: step "
            f"{ms_step:.4f} ms, gram {ms_gram:.4f} eig {ms_eig:.4f} u {ms_u:.4f}")
     del U2, gwork, ework, work
     return dict(ms_step=ms_step, ms_gram=ms_gram, ms_eig=ms_eig, ms_u=ms_u, S=S, V=V, U=U,
                 info=info)
+
+
+def fp32_leg(args, torch, gs, g, log_fn):
+    """The FP32 workload: A = B D stored in FP32, m = 4e6, n = 128, kappa(B) = 1e2, kappa(D) = 1e6
+    (log-spaced).  FP64-accumulated plain Gram against the split Gram at every slice count 1..8,
+    each with the two-sided Jacobi on M_h (the FP32 default) and U on the FP32 matrix cores.
+
+    The oracle computes the SVD of the stored FP32 matrix (dd Gram, dd Jacobi) on the host, in a
+    thread while the GPU legs run; sigma's error is reported per slice count."""
+    import threading
+
+    from oracle import ref
+    spec = g.spec_tall_f32(m=args.f32_m)
+    spec.w1 = "gauss"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    dA, _ = g.make_a_device(spec, dev)
+    torch.cuda.synchronize()
+    m, n = spec.m, spec.n
+    A_host = np.asfortranarray(dA.t().contiguous().cpu().numpy().T)
+    log_fn(f"fp32: generated A {m}x{n} on the GPU in {time.time() - t0:.1f}s")
+    holder = {}
+    th = threading.Thread(target=lambda: holder.update(o=ref.svd(A_host)))
+    th.start()
+    stream = torch.cuda.current_stream()
+    runs = [("plain", gs.GSVD_GRAM_PLAIN, 0)] + [(f"split-S{S}", gs.GSVD_GRAM_SPLIT, S)
+                                                for S in range(1, 9)]
+    res = {}
+    for name, gram, S in runs:
+        res[name] = measure_thin(torch, gs, dA, gram, args.f32_steps, 1, stream, log_fn, S)
+    th.join()
+    oracle = holder["o"]
+    u = 2.0 ** -24
+    tol = 50 * n * u * oracle.kappa_b
+    flops = m * n * (n + 1) + 2 * m * n * n
+    out = {"workload": f"FP32 A=BD m={m} n={n} kappa(B)=1e2 kappa(D)=1e6 (log-spaced); FP64-"
+                       "accumulated plain Gram vs split int8-slice Gram per slice count, two-sided "
+                       "Jacobi on M_h in FP64, FP32 MFMA U",
+           "m": m, "n": n, "kappa_b_oracle": oracle.kappa_b, "sigma_tol_50nu_kappaB": tol,
+           "orth_tol_50nu": 50 * n * u,
+           "default_slices": gs.gram_config(m, n, gs.GSVD_F32, gs.GSVD_GRAM_SPLIT)["n_slices"]}
+    for name, r in res.items():
+        Sn = r["S"].cpu().numpy().astype(np.float64)
+        Mh, Ml = gs.gram(r["U"])
+        torch.cuda.synchronize()
+        orth = float(np.linalg.norm((Mh.cpu().numpy() - np.eye(n)) + Ml.cpu().numpy()))
+        err = float(ref.sigma_rel_err(Sn, oracle).max())
+        out[name] = {"ms_per_step": round(r["ms_step"], 4), "ms_gram": round(r["ms_gram"], 4),
+                     "value_gflops": round(flops / (r["ms_step"] * 1e-3) / 1e9, 1),
+                     "info": int(r["info"].item()), "sigma_max_rel_err": err, "u_orth": orth,
+                     "meets_tol": bool(int(r["info"].item()) == 0 and err <= tol
+                                       and orth <= 50 * n * u)}
+        log_fn(f"fp32 {name}: {out[name]}")
+    del res, dA
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
 def large_leg(args, torch, gs, g, log_fn):
@@ -465,6 +532,9 @@ def main():
 
     if not args.no_batched:
         result["batched"] = batched_leg(args, torch, gs, g, log)
+
+    if not args.no_fp32:
+        result["fp32"] = fp32_leg(args, torch, gs, g, log)
 
     if not args.no_large:
         result["large"] = large_leg(args, torch, gs, g, log)

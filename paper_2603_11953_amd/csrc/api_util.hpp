@@ -97,12 +97,18 @@ inline SplitPlan split_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool ba
     return split_plan(m, n, slices_of(o, n), slab_rows_of(o, m, n, batched));
 }
 
+// the plain Gram of FP32 A on the FP64 matrix cores (single problems, n <= 128)
+inline bool f32_mfma(const gsvd_opts *o, int64_t n, bool batched) {
+    return !batched && o->working == GSVD_F32 && !use_split(o) && n <= GSVD_KMAX_N;
+}
+
 // workspace bytes for the partial sums of whichever Gram form o selects
 inline size_t gram_part_bytes(int64_t m, int64_t n, const gsvd_opts *o, bool batched) {
     if (wide_n(n))
         return use_split(o) ? split_wide_plan(m, n, slices_of(o, n), o->slab_rows).part_bytes
                             : gram_wide_plan(m, n, o->slab_rows).part_bytes;
     if (use_split(o)) return split_plan_of(o, m, n, batched).part_bytes;
+    if (f32_mfma(o, n, batched)) return gram_f32mfma_plan(m, n, o->slab_rows).part_bytes;
     return gram_plan_of(o, m, n, batched).part_bytes;
 }
 

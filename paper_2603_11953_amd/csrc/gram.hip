@@ -109,6 +109,7 @@ __device__ __forceinline__ void gram_partial_body(const T *__restrict__ A, int64
         if (active) {
             const double *pi = cur + BS * bi;
             const double *pj = cur + BS * bj;
+#pragma unroll 2
             for (int k = g; k < kc; k += ks) {
                 const double2 a01 = *reinterpret_cast<const double2 *>(pi + k * LDL);
                 const double2 a23 = *reinterpret_cast<const double2 *>(pi + k * LDL + 2);

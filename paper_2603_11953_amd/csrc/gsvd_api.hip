@@ -30,6 +30,10 @@ hipError_t gram_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A, int
         SplitPlan p = split_plan_of(o, m, n, false);
         return split_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
     }
+    if (f32_mfma(o, n, false)) {
+        F32MfmaPlan p = gram_f32mfma_plan(m, n, o->slab_rows);
+        return gram_f32mfma_launch(m, n, (const float *)A, lda, Mhi, Mlo, ldm, part, p, st);
+    }
     GramPlan p = gram_plan_of(o, m, n, false);
     return gram_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
 }
@@ -107,6 +111,10 @@ int gsvd_gram_config(int64_t m, int64_t n, const gsvd_opts *o, int64_t *slab_row
         S = p.S;
     } else if (wide_n(n)) {
         const WidePlan p = gram_wide_plan(m, n, o->slab_rows);
+        rows = p.rows_per_split;
+        slabs = p.nsplit;
+    } else if (f32_mfma(o, n, false)) {
+        const F32MfmaPlan p = gram_f32mfma_plan(m, n, o->slab_rows);
         rows = p.rows_per_split;
         slabs = p.nsplit;
     } else if (use_split(o)) {

@@ -51,6 +51,19 @@ hipError_t gram_batched_launch(int working, const BatchMat *tab, const int *orde
                                int count, int max_nsplit, const GramPlan &p, hipStream_t st);
 hipError_t gram_reduce_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st);
 
+// Plain Gram of FP32 A on the FP64 matrix cores (gram_f32mfma.hip, n <= 128).
+struct F32MfmaPlan {
+    int nb;                  // ceil(n / 16)
+    int64_t rows_per_split;  // rows of A per slab (a multiple of 32)
+    int64_t nsplit;
+    size_t part_bytes;
+};
+// slab_rows > 0 fixes the slab height (rounded up to 32); 0 picks about 1024 slabs.
+F32MfmaPlan gram_f32mfma_plan(int64_t m, int64_t n, int64_t slab_rows = 0);
+hipError_t gram_f32mfma_launch(int64_t m, int64_t n, const float *A, int64_t lda, double *Mhi,
+                               double *Mlo, int64_t ldm, void *part, const F32MfmaPlan &p,
+                               hipStream_t st);
+
 // Launch geometry of the wide plain Gram (gram_wide.hip, n > 128): 64-column
 // panels, one workgroup per (panel pair, slab).
 struct WidePlan {
