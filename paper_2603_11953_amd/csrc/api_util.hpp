@@ -120,9 +120,11 @@ inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
     return __builtin_sqrt((double)n) * unit_roundoff(o->working);
 }
 
+inline int sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 30; }
+
 inline size_t eig_work_bytes(const gsvd_opts *o, int64_t n) {
     if (wide_eig(o, n)) return eig_wide_work_bytes(n);
-    return eig_mode_of(o) == GSVD_EIG_JACOBI2 ? j2_work_bytes(n) : 0;
+    return eig_mode_of(o) == GSVD_EIG_JACOBI2 ? j2_work_bytes(n, sweeps_of(o)) : 0;
 }
 
 inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, const double *Mlo,
@@ -138,7 +140,6 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
     return eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps, st);
 }
 
-inline int sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 30; }
 
 inline hipError_t urecover_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A,
                                int64_t lda, const void *W, int64_t ldw, void *U, int64_t ldu,

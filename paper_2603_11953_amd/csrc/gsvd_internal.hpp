@@ -152,8 +152,9 @@ hipError_t eig_wide_launch(int64_t n, const double *Mhi, const double *Mlo, int6
                            int max_sweeps, void *work, hipStream_t st);
 
 // Two-sided Jacobi eigensolver for FP32 working (eig_jacobi2.hip).  V needs
-// j2_work_bytes(n) of device scratch (0 while it fits LDS, n <= 96).
-size_t j2_work_bytes(int64_t n);
+// j2_work_bytes(n, max_sweeps) of device scratch (0 while it fits LDS, n <= 96; beyond,
+// the rotations are logged and V is formed from the log afterwards).
+size_t j2_work_bytes(int64_t n, int max_sweeps);
 hipError_t eig_jacobi2_launch(int working, int64_t n, const double *Mhi, int64_t ldm, void *S,
                               void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
                               int max_sweeps, void *work, hipStream_t st);
