@@ -170,21 +170,21 @@ __device__ __forceinline__ void eig_jacobi2_body(int n, const double *__restrict
             // the row update, as separate passes would do them); a rotated diagonal
             // block takes its closed form (m_pp - t m_pq, 0, 0, m_qq + t m_pq).
             // A pair whose q is the padding index n has one row / column only.
-            for (int it = tid; it < npair * npair; it += nthr) {
-                const int P = it % npair, R = it / npair;
-                const bool aP = sm.act[P] != 0, aR = sm.act[R] != 0;
-                if (!aP && !aR) continue;
-                const int p0 = sm.pp[P], q0 = sm.qq[P];
+            // item it = P + npair R; when npair divides the lane count a lane keeps
+            // one P for the whole pass (its pair read once), and R is the same
+            // across a wavefront (broadcast reads)
+            auto block = [&](int P, bool aP, int p0, int q0, double cP, double sP, int R) {
+                const bool aR = sm.act[R] != 0;
+                if (!aP && !aR) return;
                 if (P == R) {
                     Ms[p0 + p0 * LD] = sm.app[P];
                     Ms[q0 + q0 * LD] = sm.aqq[P];
                     Ms[p0 + q0 * LD] = 0.0;
                     Ms[q0 + p0 * LD] = 0.0;
-                    continue;
+                    return;
                 }
                 const int p1 = sm.pp[R], q1 = sm.qq[R];
                 const bool v0 = q0 < n, v1 = q1 < n;
-                const double cP = aP ? sm.c[P] : 1.0, sP = aP ? sm.s[P] : 0.0;
                 const double cR = aR ? sm.c[R] : 1.0, sR = aR ? sm.s[R] : 0.0;
                 const double x00 = Ms[p0 + p1 * LD];
                 const double x01 = v1 ? Ms[p0 + q1 * LD] : 0.0;
@@ -196,6 +196,30 @@ __device__ __forceinline__ void eig_jacobi2_body(int n, const double *__restrict
                 if (v1) Ms[p0 + q1 * LD] = cP * y01 - sP * y11;
                 if (v0) Ms[q0 + p1 * LD] = sP * y00 + cP * y10;
                 if (v0 && v1) Ms[q0 + q1 * LD] = sP * y01 + cP * y11;
+            };
+            auto pair_of = [&](int P, bool &aP, int &p0, int &q0, double &cP, double &sP) {
+                aP = sm.act[P] != 0;
+                p0 = sm.pp[P];
+                q0 = sm.qq[P];
+                cP = aP ? sm.c[P] : 1.0;
+                sP = aP ? sm.s[P] : 0.0;
+            };
+            if (nthr % npair == 0) {
+                const int P = tid % npair;
+                bool aP;
+                int p0, q0;
+                double cP, sP;
+                pair_of(P, aP, p0, q0, cP, sP);
+                for (int R = tid / npair; R < npair; R += nthr / npair) block(P, aP, p0, q0, cP, sP, R);
+            } else {
+                for (int it = tid; it < npair * npair; it += nthr) {
+                    const int P = it % npair;
+                    bool aP;
+                    int p0, q0;
+                    double cP, sP;
+                    pair_of(P, aP, p0, q0, cP, sP);
+                    block(P, aP, p0, q0, cP, sP, it / npair);
+                }
             }
             // V <- V J (columns p, q of every rotated pair)
             if (!LOGV) {
