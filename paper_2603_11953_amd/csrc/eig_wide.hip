@@ -31,7 +31,7 @@
 //      refined by Newton steps, as in the one-workgroup kernel.  The
 //      rotations of a step accumulate in a 32 x 32 product Q, and the same 32
 //      columns of V, staged through LDS, are multiplied by Q once at the end of
-//      the step (one row per lane).  One launch per
+//      the step, on the FP64 matrix cores.  One launch per
 //      step; after each tournament round a one-lane kernel marks convergence
 //      when no rotation passed the test |x_p^T x_q| > tol ||x_p|| ||x_q||, and
 //      later launches return at once.
@@ -55,6 +55,9 @@ constexpr int JB = 16;       // Jacobi block width (columns)
 constexpr int JC = 2 * JB;   // columns held by one workgroup
 constexpr int JT = 64 * JB;  // Jacobi workgroup size: one wavefront per column pair of a round
 constexpr int UT = 1024;     // update-kernel workgroup (32 x 32 tile)
+constexpr int QLD = JC + 2;  // column stride of Q in LDS: conflict-free matrix-core operand reads
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MAXWG = 64;    // Jacobi workgroups per step: ceil(512 / 16) / 2 = 16 at most
 
@@ -330,7 +333,7 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
     extern __shared__ __attribute__((aligned(16))) double jsm[];
     constexpr int LDL = 64 * RPL;  // rows of a column in LDS (n rounded up to 64)
     double *Xl = jsm;              // JC columns of X
-    double *Qs = jsm + JC * LDL;   // JC x JC rotation product, column-major
+    double *Qs = jsm + JC * LDL;   // JC x JC rotation product, column-major, stride QLD
     if (wg_read(&ctl->bad) || wg_read(&ctl->done)) return;
     int P, Qb;
     rr_pair(step, blockIdx.x, nblk, P, Qb);
@@ -354,7 +357,7 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
         for (int k = 0; k < NLD; ++k) Xl[tid + k * JT] = v[k];
     };
     stage(X);
-    for (int q = tid; q < JC * JC; q += JT) Qs[q] = (q % JC == q / JC) ? 1.0 : 0.0;
+    for (int q = tid; q < JC * QLD; q += JT) Qs[q] = (q % QLD == q / QLD) ? 1.0 : 0.0;
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6;
@@ -391,9 +394,9 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
             x1[i] = sn * a0 + c * a1;
         }
         if (lane < JC) {
-            const double u = Qs[lane + p * JC], w = Qs[lane + q * JC];
-            Qs[lane + p * JC] = c * u - sn * w;
-            Qs[lane + q * JC] = sn * u + c * w;
+            const double u = Qs[lane + p * QLD], w = Qs[lane + q * QLD];
+            Qs[lane + p * QLD] = c * u - sn * w;
+            Qs[lane + q * QLD] = sn * u + c * w;
         }
         return true;
     };
@@ -457,24 +460,27 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
     __syncthreads();
     stage(Vw);
     __syncthreads();
-    static_assert(JT >= GSVD_WIDE_MAX_N, "one row of V per lane");
-    if (tid < n) {
-        const int r = tid;
-#pragma unroll 1
-        for (int c0 = 0; c0 < JC; c0 += 16) {  // 16 output columns at a time
-            double out[16];
+    // V_new = V Q on the FP64 matrix cores: (LDL x 32) by (32 x 32) in 16 x 16 tiles,
+    // LDL / 16 x 2 of them dealt to the wavefronts, 8 steps of 16x16x4 each.
+    // Operands (16x16x4): lane l supplies V(r0 + l % 16, k0 + l / 16) and
+    // Q(k0 + l / 16, c0 + l % 16); result register r is V_new(r0 + 4 r + l / 16, c0 + l % 16).
+    {
+        constexpr int NTI = LDL / 16 * (JC / 16);
+        const int li = lane & 15, lk = lane >> 4;
+        for (int ti = wave; ti < NTI; ti += JT / 64) {
+            const int r0 = 16 * (ti >> 1), c0 = 16 * (ti & 1);
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < 16; ++c) out[c] = 0.0;
-#pragma unroll 4
-            for (int t = 0; t < JC; ++t) {
-                const double vt = Xl[r + t * LDL];
-#pragma unroll
-                for (int c = 0; c < 16; ++c) out[c] = __builtin_fma(vt, Qs[t + (c0 + c) * JC], out[c]);
+            for (int k0 = 0; k0 < JC; k0 += 4) {
+                const double a = Xl[(r0 + li) + (k0 + lk) * LDL];
+                const double b = Qs[(k0 + lk) + (c0 + li) * QLD];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
+            const int g = gcol(c0 + li);
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const int g = gcol(c0 + c);
-                if (g < n) Vw[r + (size_t)g * n] = out[c];
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + 4 * r + lk;
+                if (row < n && g < n) Vw[row + (size_t)g * n] = acc[r];
             }
         }
     }
@@ -585,7 +591,7 @@ weig_out_kernel(int n, const Ctl *ctl, const double *__restrict__ Vw,
 template <int RPL>
 hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double tol2,
                         int max_sweeps, hipStream_t st) {
-    const size_t lds = ((size_t)JC * 64 * RPL + JC * JC) * sizeof(double);
+    const size_t lds = ((size_t)JC * 64 * RPL + JC * QLD) * sizeof(double);
     auto k = weig_step_kernel<RPL>;
     hipError_t err = hipFuncSetAttribute((const void *)k,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
