@@ -85,11 +85,13 @@ struct EigShared {
 
 // ---- cross-lane helpers on doubles (DPP within a row of 16 lanes)
 
+// (every source lane of the permutations below lies in the same row, so no
+// lane reads the bound-control zero)
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
     const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -160,62 +162,85 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
         return;
     }
 
-    // ---- 2. H = D~^-1 M D~^-1 (exact) as a full n x n square in LDS; Cholesky
-    //      (only the upper triangle is read and written)
+    // ---- 2. H = D~^-1 M D~^-1 (exact) in the upper triangle of an n x n square
+    //      in LDS, leading dimension n + 1 (a row's entries fall in different
+    //      banks); Cholesky
     dd_t *Hd = reinterpret_cast<dd_t *>(lds);  // DDGRAM
     double *Hs = lds;                            // !DDGRAM
+    const int lh = n + 1;
     for (int q = tid; q < n * n; q += nthr) {
         const int i = q % n, j = q / n;
         if (i > j) continue;
         const int sc = -(sexp[i] + sexp[j]);
         const double hi = ldexp(Mhi[i + (int64_t)j * ldm], sc);
         if (DDGRAM) {
-            Hd[q] = dd_t{hi, ldexp(Mlo[i + (int64_t)j * ldm], sc)};
+            Hd[i + j * lh] = dd_t{hi, ldexp(Mlo[i + (int64_t)j * ldm], sc)};
         } else {
-            Hs[q] = hi;
+            Hs[i + j * lh] = hi;
         }
     }
     __syncthreads();
 
-    const int tx = tid & 31, ty = tid >> 5, nty = nthr >> 5;
+    // Right-looking, one barrier per column k: every lane forms the reciprocal
+    // of the pivot h_kk and updates its entries of the trailing triangle as
+    // h_ij -= h_ki (h_kj / h_kk) (= r_ki r_kj), the entries dealt out by a
+    // linear index so no lane holds more than its share; meanwhile the last
+    // lanes write row k of R, r_kj = h_kj / sqrt(h_kk), into the unused strict
+    // lower triangle (slot (j, k)) and r_kk into rowk[k], places no lane reads
+    // during the step.
     for (int k = 0; k < n; ++k) {
-        const dd_t hkk = DDGRAM ? Hd[k + k * n] : dd_t{Hs[k + k * n], 0.0};
+        const dd_t hkk = DDGRAM ? Hd[k + k * lh] : dd_t{Hs[k + k * lh], 0.0};
         if (!(hkk.hi > 0.0)) {  // uniform across the workgroup
             if (tid == 0) *info = 1;
             return;
         }
+        const int t = n - 1 - k;
+        const int nent = t * (t + 1) / 2;
         if (DDGRAM) {
-            // 1/sqrt(h) in dd: the FP64 estimate y refined once in dd,
-            // y + y (1 - h y^2) / 2; then sqrt(h) = h / sqrt(h)
-            const double y = rsq_nr(hkk.hi);
-            const dd_t hy2 = dd_mul_d(dd_mul_d(hkk, y), y);
-            const dd_t inv = dd_add(dd_t{y, 0.0}, dd_mul_d(dd_sub(dd_t{1.0, 0.0}, hy2), 0.5 * y));
-            const dd_t rkk = dd_mul(hkk, inv);
-            for (int j = k + 1 + tid; j < n; j += nthr) {
-                const dd_t v = dd_mul(Hd[k + j * n], inv);
-                Hd[k + j * n] = v;
-                rowk[j] = v;
+            // 1 / h in dd: the FP64 estimate r corrected once, r + r (1 - h r)
+            const double r0 = rcp_nr(hkk.hi);
+            const dd_t hr = dd_mul_d(hkk, r0);
+            const double e = (1.0 - hr.hi) - hr.lo;
+            const dd_t rinv = quick_two_sum(r0, r0 * e);
+            for (int q = tid; q < nent; q += nthr) {
+                int b = (int)((__builtin_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+                while (b * (b + 1) / 2 > q) --b;
+                while ((b + 1) * (b + 2) / 2 <= q) ++b;
+                const int i = k + 1 + (q - b * (b + 1) / 2), j = k + 1 + b;
+                const dd_t rkj = dd_mul(Hd[k + j * lh], rinv);
+                Hd[i + j * lh] = dd_sub_fast(Hd[i + j * lh], dd_mul(Hd[k + i * lh], rkj));
             }
-            if (tid == 0) Hd[k + k * n] = rkk;
         } else {
-            const double rkk = __builtin_sqrt(hkk.hi);
-            for (int j = k + 1 + tid; j < n; j += nthr) {
-                const double v = Hs[k + j * n] / rkk;
-                Hs[k + j * n] = v;
-                rowk[j] = dd_t{v, 0.0};
+            const double rinv = 1.0 / hkk.hi;
+            for (int q = tid; q < nent; q += nthr) {
+                int b = (int)((__builtin_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+                while (b * (b + 1) / 2 > q) --b;
+                while ((b + 1) * (b + 2) / 2 <= q) ++b;
+                const int i = k + 1 + (q - b * (b + 1) / 2), j = k + 1 + b;
+                Hs[i + j * lh] = __builtin_fma(-Hs[k + i * lh], Hs[k + j * lh] * rinv, Hs[i + j * lh]);
             }
-            if (tid == 0) Hs[k + k * n] = rkk;
         }
-        __syncthreads();
-        // trailing update of the upper triangle: H(i, j) -= R(k, i) R(k, j), k < i <= j
-        for (int j = k + 1 + ty; j < n; j += nty) {
-            const dd_t rkj = rowk[j];
-            for (int i = k + 1 + tx; i <= j; i += 32) {
-                const dd_t rki = rowk[i];
-                if (DDGRAM) {
-                    Hd[i + j * n] = dd_sub_fast(Hd[i + j * n], dd_mul(rki, rkj));
+        const int wr = tid - (nthr - 1 - t);  // lanes nthr - 1 - t .. nthr - 1
+        if (wr >= 0) {
+            if (DDGRAM) {
+                // 1 / sqrt(h) in dd: the FP64 estimate y refined once in dd,
+                // y + y (1 - h y^2) / 2
+                const double y = rsq_nr(hkk.hi);
+                const dd_t hy2 = dd_mul_d(dd_mul_d(hkk, y), y);
+                const dd_t inv = dd_add(dd_t{y, 0.0}, dd_mul_d(dd_sub(dd_t{1.0, 0.0}, hy2), 0.5 * y));
+                if (wr == 0) {
+                    rowk[k] = dd_mul(hkk, inv);
                 } else {
-                    Hs[i + j * n] = __builtin_fma(-rki.hi, rkj.hi, Hs[i + j * n]);
+                    const int j = k + wr;
+                    Hd[j + k * lh] = dd_mul(Hd[k + j * lh], inv);
+                }
+            } else {
+                const double rkk = __builtin_sqrt(hkk.hi);
+                if (wr == 0) {
+                    rowk[k] = dd_t{rkk, 0.0};
+                } else {
+                    const int j = k + wr;
+                    Hs[j + k * lh] = Hs[k + j * lh] / rkk;
                 }
             }
         }
@@ -235,7 +260,9 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
         if (q < n * n) {
             const int i = q % n, j = q / n;
             if (i <= j) {
-                const double h = DDGRAM ? Hd[q].hi : Hs[q];
+                // r_ij: the diagonal in rowk, the rest in the lower triangle
+                const double h = i == j ? rowk[i].hi
+                                        : (DDGRAM ? Hd[j + i * lh].hi : Hs[j + i * lh]);
                 rv[c] = ldexp((double)(TW)h, sexp[j] - emax);  // round to working, rescale
             }
         }
@@ -334,27 +361,16 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                     be = group_sum(be);
                     ga = group_sum(ga);
                     if (ga * ga > tol2 * (al * be)) {
-                        const double zeta = (be - al) * rcp_nr(2.0 * ga);
-                        const double az = __builtin_fabs(zeta);
-                        double tn;
-                        if (az > 1e150) {
-                            tn = 0.5 * rcp_nr(zeta);
-                        } else {
-                            const double x = __builtin_fma(zeta, zeta, 1.0);
-                            const double root = x * rsq_nr(x);
-                            tn = rcp_nr(az + root);
-                            if (zeta < 0) tn = -tn;
-                        }
-                        const double c = rsq_nr(__builtin_fma(tn, tn, 1.0));
-                        const double sn = c * tn;
+                        double c, sn;
+                        jacobi_cs(al, be, ga, c, sn);
 #pragma unroll
                         for (int i = 0; i < RPL; ++i) {
                             const double a0 = (double)x0[i], a1 = (double)x1[i];
                             const double u = (double)w0[i], w = (double)w1[i];
-                            x0[i] = (TS)(c * a0 - sn * a1);
-                            x1[i] = (TS)(sn * a0 + c * a1);
-                            w0[i] = (TS)(c * u - sn * w);
-                            w1[i] = (TS)(sn * u + c * w);
+                            x0[i] = (TS)__builtin_fma(c, a0, -(sn * a1));
+                            x1[i] = (TS)__builtin_fma(c, a1, sn * a0);
+                            w0[i] = (TS)__builtin_fma(c, u, -(sn * w));
+                            w1[i] = (TS)__builtin_fma(c, w, sn * u);
                         }
 #pragma unroll
                         for (int b = 0; b < RP2; ++b) {
@@ -494,7 +510,7 @@ eig_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ ord
 }
 
 size_t eig_lds_bytes(int working, int64_t n) {
-    const size_t chol = (size_t)(n * n) * (working == 1 ? sizeof(dd_t) : sizeof(double));
+    const size_t chol = (size_t)(n * (n + 1)) * (working == 1 ? sizeof(dd_t) : sizeof(double));
     const size_t jac = working == 1 ? 2 * (size_t)(n * jac_ld<double>((int)n)) * sizeof(double)
                                     : 2 * (size_t)(n * jac_ld<float>((int)n)) * sizeof(float);
     return chol > jac ? chol : jac;

@@ -375,28 +375,18 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
         be = wave_sum(be);
         ga = wave_sum(ga);
         if (!(ga * ga > tol2 * (al * be))) return false;  // uniform: the sums agree bitwise
-        const double zeta = (be - al) * rcp_nr(2.0 * ga);
-        const double az = __builtin_fabs(zeta);
-        double tn;
-        if (az > 1e150) {
-            tn = 0.5 * rcp_nr(zeta);
-        } else {
-            const double x = __builtin_fma(zeta, zeta, 1.0);
-            tn = rcp_nr(az + x * rsq_nr(x));
-            if (zeta < 0) tn = -tn;
-        }
-        const double c = rsq_nr(__builtin_fma(tn, tn, 1.0));
-        const double sn = c * tn;
+        double c, sn;
+        jacobi_cs(al, be, ga, c, sn);
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const double a0 = x0[i], a1 = x1[i];
-            x0[i] = c * a0 - sn * a1;
-            x1[i] = sn * a0 + c * a1;
+            x0[i] = __builtin_fma(c, a0, -(sn * a1));
+            x1[i] = __builtin_fma(c, a1, sn * a0);
         }
         if (lane < JC) {
             const double u = Qs[lane + p * QLD], w = Qs[lane + q * QLD];
-            Qs[lane + p * QLD] = c * u - sn * w;
-            Qs[lane + q * QLD] = sn * u + c * w;
+            Qs[lane + p * QLD] = __builtin_fma(c, u, -(sn * w));
+            Qs[lane + q * QLD] = __builtin_fma(c, w, sn * u);
         }
         return true;
     };
