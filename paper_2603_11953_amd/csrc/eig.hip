@@ -79,9 +79,12 @@ struct Vec2<float> {
 
 struct EigShared {
     int flag_rot;
+    int flag_big;  // a rotation of the sweep had |sin| >= 2^-22
     int flag_bad;  // GSVD info code, 0 = fine
     int emax;
 };
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // ---- cross-lane helpers on doubles (DPP within a row of 16 lanes)
 
@@ -114,6 +117,7 @@ struct EigSmem {
     int srank[GSVD_KMAX_N];
     double ssign[GSVD_KMAX_N];
     dd_t rowk[GSVD_KMAX_N];
+    dd_t rpiv[GSVD_KMAX_N + 1];  // reciprocal pivots of the Cholesky
 };
 
 // Algorithm 2 for one n x n Gram (one workgroup; n <= GRP * RPL, RPL even).
@@ -135,6 +139,7 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
 
     if (tid == 0) {
         sh.flag_rot = 0;
+        sh.flag_big = 0;
         sh.flag_bad = 0;
         sh.emax = -100000;
     }
@@ -181,13 +186,35 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
     }
     __syncthreads();
 
-    // Right-looking, one barrier per column k: every lane forms the reciprocal
-    // of the pivot h_kk and updates its entries of the trailing triangle as
-    // h_ij -= h_ki (h_kj / h_kk) (= r_ki r_kj), the entries dealt out by a
-    // linear index so no lane holds more than its share; meanwhile the last
-    // lanes write row k of R, r_kj = h_kj / sqrt(h_kk), into the unused strict
-    // lower triangle (slot (j, k)) and r_kk into rowk[k], places no lane reads
-    // during the step.
+    // Right-looking, one barrier per column k, in the square-root-free form:
+    // h_ij -= h_ki (h_kj / h_kk) (= r_ki r_kj) over the trailing triangle
+    // k < i <= j < n.  Its entries are numbered q = b (b + 1) / 2 + a for
+    // (i, j) = (k + 1 + a, k + 1 + b), so the triangle of step k is q < t (t + 1) / 2
+    // (t = n - 1 - k) and lane tid owns q = tid + e * nthr at every step: its
+    // offsets (a, b) are found once.  Entry q = 0 is the next pivot; its owner
+    // (lane 0) also forms that pivot's reciprocal for the next step.  Row k of
+    // the square is final once step k starts, so R's rows, r_kj = h_kj / sqrt(h_kk),
+    // are formed afterwards, all at once.
+    constexpr int MAXE = eig_maxreg(RPL) / 2;  // n (n - 1) / 2 <= MAXE nthr, as n^2 <= 2 MAXE nthr
+    int ab[MAXE];
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) {
+        const int q = tid + e * nthr;
+        int b = (int)((__builtin_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+        while (b * (b + 1) / 2 > q) --b;
+        while ((b + 1) * (b + 2) / 2 <= q) ++b;
+        ab[e] = (q - b * (b + 1) / 2) | (b << 8);
+    }
+    // 1 / h in dd: the FP64 estimate r corrected once, r + r (1 - h r)
+    auto dd_rcp = [](dd_t h) -> dd_t {
+        const double r0 = rcp_nr(h.hi);
+        const dd_t hr = dd_mul_d(h, r0);
+        const double e = (1.0 - hr.hi) - hr.lo;
+        return quick_two_sum(r0, r0 * e);
+    };
+    dd_t *rpiv = sm.rpiv;
+    if (DDGRAM && tid == 0) rpiv[0] = dd_rcp(Hd[0]);
+    __syncthreads();
     for (int k = 0; k < n; ++k) {
         const dd_t hkk = DDGRAM ? Hd[k + k * lh] : dd_t{Hs[k + k * lh], 0.0};
         if (!(hkk.hi > 0.0)) {  // uniform across the workgroup
@@ -197,55 +224,53 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
         const int t = n - 1 - k;
         const int nent = t * (t + 1) / 2;
         if (DDGRAM) {
-            // 1 / h in dd: the FP64 estimate r corrected once, r + r (1 - h r)
-            const double r0 = rcp_nr(hkk.hi);
-            const dd_t hr = dd_mul_d(hkk, r0);
-            const double e = (1.0 - hr.hi) - hr.lo;
-            const dd_t rinv = quick_two_sum(r0, r0 * e);
-            for (int q = tid; q < nent; q += nthr) {
-                int b = (int)((__builtin_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
-                while (b * (b + 1) / 2 > q) --b;
-                while ((b + 1) * (b + 2) / 2 <= q) ++b;
-                const int i = k + 1 + (q - b * (b + 1) / 2), j = k + 1 + b;
-                const dd_t rkj = dd_mul(Hd[k + j * lh], rinv);
-                Hd[i + j * lh] = dd_sub_fast(Hd[i + j * lh], dd_mul(Hd[k + i * lh], rkj));
+            const dd_t rinv = rpiv[k];
+#pragma unroll
+            for (int e = 0; e < MAXE; e += 2) {
+                const int q = tid + e * nthr;
+                if (q < nent) {
+                    const bool two = q + nthr < nent;
+                    const int ia = k + 1 + (ab[e] & 255), ja = k + 1 + (ab[e] >> 8);
+                    const int ib = k + 1 + (ab[e + 1] & 255), jb = k + 1 + (ab[e + 1] >> 8);
+                    const dd_t kia = Hd[k + ia * lh], kja = Hd[k + ja * lh], hija = Hd[ia + ja * lh];
+                    dd_t kib{0.0, 0.0}, kjb{0.0, 0.0}, hijb{0.0, 0.0};
+                    if (two) {
+                        kib = Hd[k + ib * lh];
+                        kjb = Hd[k + jb * lh];
+                        hijb = Hd[ib + jb * lh];
+                    }
+                    const dd_t va = dd_sub_fast(hija, dd_mul(kia, dd_mul(kja, rinv)));
+                    Hd[ia + ja * lh] = va;
+                    if (e == 0 && q == 0) rpiv[k + 1] = dd_rcp(va);  // the next pivot
+                    if (two) Hd[ib + jb * lh] = dd_sub_fast(hijb, dd_mul(kib, dd_mul(kjb, rinv)));
+                }
             }
         } else {
             const double rinv = 1.0 / hkk.hi;
-            for (int q = tid; q < nent; q += nthr) {
-                int b = (int)((__builtin_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
-                while (b * (b + 1) / 2 > q) --b;
-                while ((b + 1) * (b + 2) / 2 <= q) ++b;
-                const int i = k + 1 + (q - b * (b + 1) / 2), j = k + 1 + b;
-                Hs[i + j * lh] = __builtin_fma(-Hs[k + i * lh], Hs[k + j * lh] * rinv, Hs[i + j * lh]);
-            }
-        }
-        const int wr = tid - (nthr - 1 - t);  // lanes nthr - 1 - t .. nthr - 1
-        if (wr >= 0) {
-            if (DDGRAM) {
-                // 1 / sqrt(h) in dd: the FP64 estimate y refined once in dd,
-                // y + y (1 - h y^2) / 2
-                const double y = rsq_nr(hkk.hi);
-                const dd_t hy2 = dd_mul_d(dd_mul_d(hkk, y), y);
-                const dd_t inv = dd_add(dd_t{y, 0.0}, dd_mul_d(dd_sub(dd_t{1.0, 0.0}, hy2), 0.5 * y));
-                if (wr == 0) {
-                    rowk[k] = dd_mul(hkk, inv);
-                } else {
-                    const int j = k + wr;
-                    Hd[j + k * lh] = dd_mul(Hd[k + j * lh], inv);
-                }
-            } else {
-                const double rkk = __builtin_sqrt(hkk.hi);
-                if (wr == 0) {
-                    rowk[k] = dd_t{rkk, 0.0};
-                } else {
-                    const int j = k + wr;
-                    Hs[j + k * lh] = Hs[k + j * lh] / rkk;
+#pragma unroll
+            for (int e = 0; e < MAXE; ++e) {
+                const int q = tid + e * nthr;
+                if (q < nent) {
+                    const int i = k + 1 + (ab[e] & 255), j = k + 1 + (ab[e] >> 8);
+                    Hs[i + j * lh] = __builtin_fma(-Hs[k + i * lh], Hs[k + j * lh] * rinv, Hs[i + j * lh]);
                 }
             }
         }
         __syncthreads();
     }
+    // 1 / sqrt(h_kk) per row k (in dd, the FP64 estimate y refined once,
+    // y + y (1 - h y^2) / 2), kept in rowk; then r_kj = h_kj rowk[k]
+    for (int k = tid; k < n; k += nthr) {
+        if (DDGRAM) {
+            const dd_t hkk = Hd[k + k * lh];
+            const double y = rsq_nr(hkk.hi);
+            const dd_t hy2 = dd_mul_d(dd_mul_d(hkk, y), y);
+            rowk[k] = dd_add(dd_t{y, 0.0}, dd_mul_d(dd_sub(dd_t{1.0, 0.0}, hy2), 0.5 * y));
+        } else {
+            rowk[k] = dd_t{1.0 / __builtin_sqrt(Hs[k + k * lh]), 0.0};
+        }
+    }
+    __syncthreads();
 
     // ---- 3. R = working(R_H) D~ 2^-emax as an n x n column-major TS matrix Y in
     //      LDS, V = I next to it.  The Cholesky square overlaps both, so every
@@ -260,9 +285,8 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
         if (q < n * n) {
             const int i = q % n, j = q / n;
             if (i <= j) {
-                // r_ij: the diagonal in rowk, the rest in the lower triangle
-                const double h = i == j ? rowk[i].hi
-                                        : (DDGRAM ? Hd[j + i * lh].hi : Hs[j + i * lh]);
+                const double h = DDGRAM ? dd_mul(Hd[i + j * lh], rowk[i]).hi
+                                        : Hs[i + j * lh] * rowk[i].hi;  // r_ij
                 rv[c] = ldexp((double)(TW)h, sexp[j] - emax);  // round to working, rescale
             }
         }
@@ -331,6 +355,8 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                     w0[2 * b] = v.x;
                     w0[2 * b + 1] = v.y;
                 }
+                // wait for the resident here, once, not at the top of every step
+
             }
             for (int t = 0; t < h; ++t) {
                 int tj = li + t;
@@ -360,6 +386,10 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                     al = group_sum(al);
                     be = group_sum(be);
                     ga = group_sum(ga);
+                    // keep the traveler's V loads ahead of the test (left to
+                    // itself the compiler sinks them into the rotation, after
+                    // the parameters, and then waits for them)
+
                     if (ga * ga > tol2 * (al * be)) {
                         double c, sn;
                         jacobi_cs(al, be, ga, c, sn);
@@ -383,7 +413,12 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                             *reinterpret_cast<tv2 *>(yq + r) = y;
                             *reinterpret_cast<tv2 *>(vq + r) = v;
                         }
-                        if (gl == 0) sh.flag_rot = 1;
+                        // (plain stores: a register carrying the sweep's largest
+                        // |sin| through the steps costs register copies per rotation)
+                        if (gl == 0) {
+                            sh.flag_rot = 1;
+                            if (__builtin_fabs(sn) >= 0x1p-22) sh.flag_big = 1;
+                        }
                     }
                 }
                 __syncthreads();  // the travelers move on
@@ -404,10 +439,60 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
             }
             __syncthreads();
         }
-        const bool any = sh.flag_rot != 0;
+        const bool any = sh.flag_rot != 0, big = sh.flag_big != 0;
         __syncthreads();
-        if (!any) converged = true;
-        if (tid == 0) sh.flag_rot = 0;
+        if (tid == 0) {
+            sh.flag_rot = 0;
+            sh.flag_big = 0;
+        }
+        if (!any) {
+            converged = true;
+        } else if (!big) {
+            // The rotations of this sweep were all tiny, so the next sweep most
+            // likely rotates nothing: test every pair at once instead, with the
+            // same criterion on the Gram matrix Y^T Y (squared column norms by
+            // groups as in the sweep, the products on the FP64 matrix cores).
+            for (int p = grp; p < n; p += ngrp) {
+                double ss = 0.0;
+                for (int r = gl; r < n; r += GRP) {
+                    const double x = (double)Y[r + p * ld];
+                    ss = __builtin_fma(x, x, ss);
+                }
+                ss = group_sum(ss);
+                if (gl == 0) ssig[p] = ss;
+            }
+            __syncthreads();
+            const int lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+            const int li = lane & 15, lk = lane >> 4;
+            const int nb = (n + 15) / 16;
+            bool bad = false;
+            for (int ti = wv; ti < nb * nb; ti += nwv) {  // uniform per wavefront
+                const int bi = ti / nb, bj = ti % nb;
+                if (bi > bj) continue;
+                const int pa = 16 * bi + li < n ? 16 * bi + li : n - 1;
+                const int pb = 16 * bj + li < n ? 16 * bj + li : n - 1;
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+                for (int k0 = 0; k0 < n; k0 += 4) {  // rows n .. ld - 1 are zero
+                    const double a = (double)Y[(k0 + lk) + pa * ld];
+                    const double b = (double)Y[(k0 + lk) + pb * ld];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
+                const int q = 16 * bj + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int pp = 16 * bi + 4 * r + lk;
+                    if (pp < q && q < n) {
+                        const double g = acc[r];
+                        bad = bad || (g * g > tol2 * (ssig[pp] * ssig[q]));
+                    }
+                }
+            }
+            if (bad) sh.flag_rot = 1;
+            __syncthreads();
+            converged = sh.flag_rot == 0;
+            __syncthreads();
+            if (tid == 0) sh.flag_rot = 0;
+        }
         __syncthreads();
     }
     if (!converged) {
