@@ -6,7 +6,9 @@ paper_2603_11953_amd/build.py``).
 
 Slab height (rows of A per Gram workgroup).  For every working precision, Gram
 form (plain / split), call kind (one problem / batched), n bucket and m bucket,
-the Gram stage is timed through the C-ABI over a ladder of slab heights on
+the Gram stage is timed through the C-ABI over a ladder of slab heights (fixed
+powers of two, and for single problems the heights giving 128, 256, 384 and 512
+slabs) on
 seeded Gaussian inputs (each height over at least 10 ms of work, best of three
 passes that alternate over the ladder), and the fastest height is kept.
 
@@ -104,7 +106,10 @@ def tune_single(gs, quick):
                     Mhi = torch.empty(n, n, device=dev, dtype=torch.float64)
                     Mlo = torch.empty_like(Mhi)
                     fns, works = {}, []
-                    for slab in SINGLE_LADDER:
+                    # besides the fixed ladder, heights that give 128 j slabs, so
+                    # that the workgroups fill whole rounds of the 256 CUs
+                    ladder = sorted(set(SINGLE_LADDER) | {-(-m // (128 * j)) for j in (1, 2, 3, 4)})
+                    for slab in ladder:
                         if slab and slab > m:
                             continue
                         o = gs.opts(working, gram, slab_rows=slab)

@@ -90,7 +90,7 @@ inline int64_t slab_rows_of(const gsvd_opts *o, int64_t m, int64_t n, bool batch
 }
 
 inline GramPlan gram_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool batched) {
-    return gram_plan(m, n, slab_rows_of(o, m, n, batched));
+    return gram_plan(m, n, slab_rows_of(o, m, n, batched), !batched);
 }
 
 inline SplitPlan split_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool batched) {

@@ -28,7 +28,7 @@
 namespace gsvd {
 
 constexpr int BS = 4;       // register block edge
-constexpr int MAXPER = 4;   // staged chunk elements per lane
+constexpr int MAXPER = 6;   // staged chunk elements per lane
 
 __device__ __forceinline__ void decode_block(int b, int nb, int &bi, int &bj) {
     int i = 0, rem = b;
@@ -43,11 +43,13 @@ __device__ __forceinline__ void decode_block(int b, int nb, int &bi, int &bj) {
 constexpr int GRAM_MAX_THREADS = 768;  // three waves per SIMD: up to 168 VGPRs per lane
 
 // The partial Gram of slab `split` of one matrix (one workgroup).
+// Blocks b0 .. b0 + nblkg - 1 (those below nblk) of slab `split`.
 template <typename T, bool DD>
 __device__ __forceinline__ void gram_partial_body(const T *__restrict__ A, int64_t lda, int64_t m,
-                                                  int n, int nb, int nblk, int ks, int kc,
-                                                  int64_t rows_per_split, int64_t split,
-                                                  double *__restrict__ part, double *lds) {
+                                                  int n, int nb, int nblk, int b0, int nblkg,
+                                                  int ks, int kc, int64_t rows_per_split,
+                                                  int64_t split, double *__restrict__ part,
+                                                  double *lds) {
     const int NC = BS * nb;     // staged columns (n rounded up to a multiple of 4)
     const int LDL = NC + 2;     // row stride in LDS (16-byte aligned rows)
     double *buf0 = lds;
@@ -55,9 +57,10 @@ __device__ __forceinline__ void gram_partial_body(const T *__restrict__ A, int64
 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    const int g = tid / nblk;          // k-group
-    const int b = tid - g * nblk;      // block
-    const bool active = g < ks;
+    const int g = tid / nblkg;         // k-group
+    const int bl = tid - g * nblkg;    // block within the group
+    const int b = b0 + bl;             // block
+    const bool active = g < ks && b < nblk;
     int bi = 0, bj = 0;
     if (active) decode_block(b, nb, bi, bj);
 
@@ -151,16 +154,16 @@ __device__ __forceinline__ void gram_partial_body(const T *__restrict__ A, int64
     }
 
     // add the k-groups into k-group 0, one group at a time (fixed order)
-    double *red = lds;  // nblk x 16 dd, reuses the chunk buffers
+    double *red = lds;  // nblkg x 16 dd, reuses the chunk buffers
     for (int r = 1; r < ks; ++r) {
         if (active && g == r) {
-            double4 *dst = reinterpret_cast<double4 *>(red + (size_t)b * 32);
+            double4 *dst = reinterpret_cast<double4 *>(red + (size_t)bl * 32);
 #pragma unroll
             for (int q = 0; q < BS * BS; q += 2) dst[q / 2] = make_double4(hi[q], lo[q], hi[q + 1], lo[q + 1]);
         }
         __syncthreads();
         if (active && g == 0) {
-            const double4 *src = reinterpret_cast<const double4 *>(red + (size_t)b * 32);
+            const double4 *src = reinterpret_cast<const double4 *>(red + (size_t)bl * 32);
 #pragma unroll
             for (int q = 0; q < BS * BS; q += 2) {
                 const double4 o = src[q / 2];
@@ -187,12 +190,21 @@ __device__ __forceinline__ void gram_partial_body(const T *__restrict__ A, int64
     }
 }
 
+// One workgroup per (slab, block group).  Workgroup ids are dealt to the XCDs
+// round robin (id mod 8), so the ng groups of a slab take ids 8 apart: they
+// run on one XCD and the second reader of a row chunk finds it in that XCD's L2.
 template <typename T, bool DD>
 __global__ void __launch_bounds__(GRAM_MAX_THREADS)
 gram_partial_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int nb, int nblk,
-                    int ks, int kc, int64_t rows_per_split, double *__restrict__ part) {
+                    int ng, int nblkg, int ks, int kc, int64_t rows_per_split, int64_t nsplit,
+                    double *__restrict__ part) {
     extern __shared__ double lds[];
-    gram_partial_body<T, DD>(A, lda, m, n, nb, nblk, ks, kc, rows_per_split, blockIdx.y, part, lds);
+    const int64_t id = blockIdx.x;
+    const int64_t split = id / (8 * ng) * 8 + id % 8;
+    const int grp = (int)(id / 8 % ng);
+    if (split >= nsplit) return;  // uniform: the whole workgroup
+    gram_partial_body<T, DD>(A, lda, m, n, nb, nblk, grp * nblkg, nblkg, ks, kc, rows_per_split,
+                             split, part, lds);
 }
 
 // Batched: blockIdx.z picks the problem order[first + z], blockIdx.y its slab.
@@ -203,8 +215,8 @@ gram_partial_batched_kernel(const BatchMat *__restrict__ tab, const int *__restr
     extern __shared__ double lds[];
     const BatchMat &d = tab[order[first + blockIdx.z]];
     if ((int)blockIdx.y >= d.nsplit) return;
-    gram_partial_body<T, DD>(reinterpret_cast<const T *>(d.A), d.lda, d.m, d.n, nb, nblk, ks, kc,
-                             d.rows_per_split, blockIdx.y, d.part, lds);
+    gram_partial_body<T, DD>(reinterpret_cast<const T *>(d.A), d.lda, d.m, d.n, nb, nblk, 0, nblk,
+                             ks, kc, d.rows_per_split, blockIdx.y, d.part, lds);
 }
 
 // One wavefront per M entry: lane l adds splits l, l + 64, ... in order, then a
@@ -255,29 +267,41 @@ gram_reduce_batched_kernel(const BatchMat *__restrict__ tab) {
     gram_reduce_body(d.part, d.nsplit, nb, nb * (nb + 1) / 2, d.n, d.Mhi, d.Mlo, d.n);
 }
 
-GramPlan gram_plan(int64_t m, int64_t n, int64_t slab_rows) {
+GramPlan gram_plan(int64_t m, int64_t n, int64_t slab_rows, bool groups) {
     GramPlan p{};
     p.nb = (int)((n + BS - 1) / BS);
     p.nblk = p.nb * (p.nb + 1) / 2;
-    // k-groups: the count whose lanes fill whole wavefronts best, at most 16
-    int best_ks = 1;
-    double best_fill = 0.0;
-    for (int ks = 1; ks <= 16 && ks * p.nblk <= GRAM_MAX_THREADS; ++ks) {
-        const int lanes = ks * p.nblk;
-        const double fill = (double)lanes / (double)(((lanes + 63) / 64) * 64);
-        if (fill >= best_fill - 1e-9) {
-            best_fill = fill;
-            best_ks = ks;
+    // Lanes = ks k-groups x the blocks of a group.  Batched problems keep one
+    // group and maximise the filled fraction of the wavefronts.  With `groups`
+    // the blocks may be cut into up to 4 groups, one workgroup each (the rows are
+    // then read once per group, the later reads mostly from L2), and the score is
+    // the useful fraction of a CU's wavefront slots: the double-double kernel's
+    // registers allow three wavefronts per SIMD, twelve per CU, and fewer than
+    // three per SIMD do not hide the latency of its dependent additions.
+    p.ng = 1;
+    p.nblkg = p.nblk;
+    p.ks = 1;
+    double best = -1.0;
+    for (int ng = 1; ng <= (groups ? 4 : 1); ++ng) {
+        const int nblkg = (p.nblk + ng - 1) / ng;
+        if (ng > 1 && nblkg * (ng - 1) >= p.nblk) break;  // an empty group
+        for (int ks = 1; ks <= (groups ? 24 : 16) && ks * nblkg <= GRAM_MAX_THREADS; ++ks) {
+            const int lanes = ks * nblkg;
+            const int waves = (lanes + 63) / 64;
+            const double score = groups ? (double)lanes / (64.0 * 12 * ((waves + 11) / 12)) - 0.01 * (ng - 1)
+                                        : (double)lanes / (64.0 * waves);
+            if (score >= best - 1e-9) {
+                best = score;
+                p.ng = ng;
+                p.nblkg = nblkg;
+                p.ks = ks;
+            }
         }
     }
-    p.ks = best_ks;
-    p.threads = ((p.ks * p.nblk + 63) / 64) * 64;
-    // rows per k-group per chunk: up to 8, as many as the lanes can stage with
-    // <= MAXPER values each (kk = 1 always fits: 4 nb <= MAXPER nb (nb + 1) / 2)
+    p.threads = ((p.ks * p.nblkg + 63) / 64) * 64;
     int kk = 8;
     while (kk > 1 && p.ks * kk * BS * p.nb > MAXPER * p.threads) --kk;
     p.kc = p.ks * kk;
-    // slabs: about two workgroups per compute unit, every slab a multiple of kc rows
     int64_t target = 512;
     int64_t rps = slab_rows > 0 ? slab_rows : (m + target - 1) / target;
     rps = ((rps + p.kc - 1) / p.kc) * p.kc;
@@ -286,7 +310,7 @@ GramPlan gram_plan(int64_t m, int64_t n, int64_t slab_rows) {
     p.nsplit = (m + rps - 1) / rps;
     if (p.nsplit < 1) p.nsplit = 1;
     const size_t chunk = (size_t)2 * p.kc * (BS * p.nb + 2) * sizeof(double);
-    const size_t red = (size_t)p.nblk * 32 * sizeof(double);
+    const size_t red = (size_t)p.nblkg * 32 * sizeof(double);
     p.lds_bytes = chunk > red ? chunk : red;
     p.part_bytes = (size_t)p.nsplit * p.nblk * 32 * sizeof(double);
     return p;
@@ -294,14 +318,15 @@ GramPlan gram_plan(int64_t m, int64_t n, int64_t slab_rows) {
 
 static bool plan_ok(const GramPlan &p) {
     return !(p.threads > GRAM_MAX_THREADS || (p.kc * BS * p.nb + p.threads - 1) / p.threads > MAXPER ||
-             p.ks * p.nblk > p.threads || p.lds_bytes > 160 * 1024);
+             p.ks * p.nblkg > p.threads || p.ng < 1 || p.nblkg * p.ng < p.nblk ||
+             p.lds_bytes > 160 * 1024);
 }
 
 hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                        double *Mhi, double *Mlo, int64_t ldm, void *part, const GramPlan &p,
                        hipStream_t st) {
     if (!plan_ok(p)) return hipErrorInvalidValue;
-    dim3 grid(1, (unsigned)p.nsplit);
+    const dim3 grid((unsigned)(8 * p.ng * ((p.nsplit + 7) / 8)));
     hipError_t err;
     if (working == 1) {
         auto k = gram_partial_kernel<double, true>;
@@ -309,14 +334,16 @@ hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t
                                   (int)p.lds_bytes);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(k, grid, dim3(p.threads), p.lds_bytes, st, (const double *)A, lda, m,
-                           (int)n, p.nb, p.nblk, p.ks, p.kc, p.rows_per_split, (double *)part);
+                           (int)n, p.nb, p.nblk, p.ng, p.nblkg, p.ks, p.kc, p.rows_per_split,
+                           p.nsplit, (double *)part);
     } else {
         auto k = gram_partial_kernel<float, false>;
         err = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)p.lds_bytes);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(k, grid, dim3(p.threads), p.lds_bytes, st, (const float *)A, lda, m,
-                           (int)n, p.nb, p.nblk, p.ks, p.kc, p.rows_per_split, (double *)part);
+                           (int)n, p.nb, p.nblk, p.ng, p.nblkg, p.ks, p.kc, p.rows_per_split,
+                           p.nsplit, (double *)part);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;

@@ -29,6 +29,8 @@ struct BatchMat {
 struct GramPlan {
     int nb;                  // ceil(n / 4): 4x4 blocks per side
     int nblk;                // blocks in the upper triangle
+    int ng;                  // block groups (workgroups per slab)
+    int nblkg;               // blocks per group (the last may have fewer)
     int ks;                  // k-groups per workgroup
     int kc;                  // rows per LDS chunk (a multiple of ks)
     int threads;             // lanes per workgroup
@@ -39,8 +41,9 @@ struct GramPlan {
 };
 
 // slab_rows > 0 fixes the slab height (rounded up to a whole number of chunks);
-// 0 picks about 512 slabs.
-GramPlan gram_plan(int64_t m, int64_t n, int64_t slab_rows = 0);
+// 0 picks about 512 slabs.  groups: the blocks may be split over several
+// workgroups per slab (single problems; the batched kernel takes ng = 1).
+GramPlan gram_plan(int64_t m, int64_t n, int64_t slab_rows = 0, bool groups = false);
 hipError_t gram_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                        double *Mhi, double *Mlo, int64_t ldm, void *part, const GramPlan &p,
                        hipStream_t st);
