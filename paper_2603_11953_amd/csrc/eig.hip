@@ -3,8 +3,9 @@
 //   1. Column scaling: d_j = sqrt(m_jj) = ||a_j|| (the D of A = B D), rounded to
 //      a power of two 2^e_j so that H = D~^-1 M_h D~^-1 is formed exactly.
 //   2. Cholesky H = R_H^T R_H at the Gram precision (double-double for FP64
-//      working, where M_h carries a low plane; FP64 otherwise), right-looking,
-//      on the full square held in LDS.  (Alg. 2 step 1.)
+//      working, where M_h carries a low plane; FP64 otherwise), right-looking
+//      in the square-root-free form on the upper triangle held in LDS, rows of
+//      R_H scaled at the end.  (Alg. 2 step 1.)
 //   3. R = working(R_H) D~  (Alg. 2 step 2; the power-of-two scaling is exact).
 //      R is further scaled by one global power of two so its largest column
 //      norm is about 1 (no overflow in the squared norms below; undone at the end).
@@ -21,8 +22,9 @@
 //      of the pair's two columns of R in registers for the step; the three
 //      inner products are reduced across the group with DPP moves arranged so
 //      all 8 lanes obtain bitwise identical sums, and the rotation parameters
-//      come from the hardware reciprocal / reciprocal square root refined by
-//      Newton steps.
+//      come from two reciprocal square roots (hardware estimate refined by
+//      Newton steps).  After a sweep whose rotations were all tiny, every pair
+//      is tested at once on Y^T Y instead of by a further sweep.
 //   5. sigma_p = ||r_p||; ordering sigma_1 >= ... >= sigma_n; each V column
 //      signed so its entry of largest magnitude is positive (lowest index on
 //      ties); Sigma and V cast to the working precision (Alg. 1 steps 4-5);
