@@ -357,8 +357,6 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                     w0[2 * b] = v.x;
                     w0[2 * b + 1] = v.y;
                 }
-                // wait for the resident here, once, not at the top of every step
-
             }
             for (int t = 0; t < h; ++t) {
                 int tj = li + t;
@@ -388,10 +386,6 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                     al = group_sum(al);
                     be = group_sum(be);
                     ga = group_sum(ga);
-                    // keep the traveler's V loads ahead of the test (left to
-                    // itself the compiler sinks them into the rotation, after
-                    // the parameters, and then waits for them)
-
                     if (ga * ga > tol2 * (al * be)) {
                         double c, sn;
                         jacobi_cs(al, be, ga, c, sn);
