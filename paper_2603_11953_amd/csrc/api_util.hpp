@@ -89,8 +89,42 @@ inline int64_t slab_rows_of(const gsvd_opts *o, int64_t m, int64_t n, bool batch
                           batched);
 }
 
+// compute units of the current device (256 on MI355X; also the fallback)
+inline int64_t device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        const bool ok = hipGetDevice(&dev) == hipSuccess &&
+                        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) ==
+                            hipSuccess &&
+                        v > 0;
+        cus = ok ? v : 256;
+    }
+    return cus;
+}
+
 inline GramPlan gram_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool batched) {
-    return gram_plan(m, n, slab_rows_of(o, m, n, batched), !batched);
+    GramPlan p = gram_plan(m, n, slab_rows_of(o, m, n, batched), !batched);
+    if (!batched && o->slab_rows == 0) {
+        // The tuned height was measured at one m of its bucket.  A single problem's
+        // workgroups run one per CU at a time, so a slab count that leaves the last
+        // round nearly empty costs almost a whole round: for other m the slab count
+        // is set so the workgroups fill whole rounds.  A caller's height is kept.
+        const int64_t cus = device_cus();
+        const int64_t wgs = (int64_t)p.ng * p.nsplit;
+        const int64_t rounds = (wgs + cus - 1) / cus;
+        const int64_t target = rounds * cus / p.ng;  // slabs
+        if (wgs % cus != 0 && target >= 1) {
+            const GramPlan q = gram_plan(m, n, (m + target - 1) / target, true);
+            if ((int64_t)q.ng * q.nsplit <= rounds * cus) p = q;
+        }
+    }
+    return p;
+}
+
+// the plain Gram of FP32 A on the matrix cores, at the tuned slab height
+inline F32MfmaPlan f32mfma_plan_of(const gsvd_opts *o, int64_t m, int64_t n) {
+    return gram_f32mfma_plan(m, n, slab_rows_of(o, m, n, false));
 }
 
 inline SplitPlan split_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool batched) {
@@ -108,7 +142,7 @@ inline size_t gram_part_bytes(int64_t m, int64_t n, const gsvd_opts *o, bool bat
         return use_split(o) ? split_wide_plan(m, n, slices_of(o, n), o->slab_rows).part_bytes
                             : gram_wide_plan(m, n, o->slab_rows).part_bytes;
     if (use_split(o)) return split_plan_of(o, m, n, batched).part_bytes;
-    if (f32_mfma(o, n, batched)) return gram_f32mfma_plan(m, n, o->slab_rows).part_bytes;
+    if (f32_mfma(o, n, batched)) return f32mfma_plan_of(o, m, n).part_bytes;
     return gram_plan_of(o, m, n, batched).part_bytes;
 }
 

@@ -31,7 +31,7 @@ hipError_t gram_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A, int
         return split_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
     }
     if (f32_mfma(o, n, false)) {
-        F32MfmaPlan p = gram_f32mfma_plan(m, n, o->slab_rows);
+        F32MfmaPlan p = f32mfma_plan_of(o, m, n);
         return gram_f32mfma_launch(m, n, (const float *)A, lda, Mhi, Mlo, ldm, part, p, st);
     }
     GramPlan p = gram_plan_of(o, m, n, false);
@@ -114,7 +114,7 @@ int gsvd_gram_config(int64_t m, int64_t n, const gsvd_opts *o, int64_t *slab_row
         rows = p.rows_per_split;
         slabs = p.nsplit;
     } else if (f32_mfma(o, n, false)) {
-        const F32MfmaPlan p = gram_f32mfma_plan(m, n, o->slab_rows);
+        const F32MfmaPlan p = f32mfma_plan_of(o, m, n);
         rows = p.rows_per_split;
         slabs = p.nsplit;
     } else if (use_split(o)) {
