@@ -430,7 +430,7 @@ def batched_leg(args, torch, gs, g, log_fn):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: use --gpus 1 "
+        print(json.dumps({"error": "the library runs on one GPU: use --gpus 1 "
                                    "(the row-split multi-GPU design is described, not built)"}))
         sys.exit(2)
     if args.copy_probe:
