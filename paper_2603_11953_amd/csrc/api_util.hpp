@@ -91,15 +91,14 @@ inline int64_t slab_rows_of(const gsvd_opts *o, int64_t m, int64_t n, bool batch
 
 // compute units of the current device (256 on MI355X; also the fallback)
 inline int64_t device_cus() {
-    static int cus = 0;
-    if (cus == 0) {
+    static const int cus = [] {  // initialised once, thread-safe
         int dev = 0, v = 0;
         const bool ok = hipGetDevice(&dev) == hipSuccess &&
                         hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) ==
                             hipSuccess &&
                         v > 0;
-        cus = ok ? v : 256;
-    }
+        return ok ? v : 256;
+    }();
     return cus;
 }
 
