@@ -56,14 +56,24 @@ enum {
 
 /* eigensolver of Alg. 1 step 3 */
 enum {
-    GSVD_EIG_AUTO = 0,       /* JACOBI2 for FP32 working, CHOL_JACOBI1 for FP64 working */
-    GSVD_EIG_JACOBI2 = 1,    /* two-sided Jacobi on M_h at u_h (Sec. 2.1, Remark 1): FP32
-                                working only (M_h and the rotations in FP64); default
-                                threshold n * 2^-53; V needs gsvd_eig_workspace_size
-                                bytes of scratch when n > 96 */
+    GSVD_EIG_AUTO = 0,       /* JACOBI2 */
+    GSVD_EIG_JACOBI2 = 1,    /* two-sided Jacobi on M_h at u_h (Sec. 2.1, Remark 1).
+                                FP32 working, n <= 128: M_h and the rotations in FP64,
+                                round-robin sweeps in one workgroup; default threshold
+                                n * 2^-53; V needs gsvd_eig_workspace_size bytes of
+                                scratch when n > 96.
+                                FP64 working (any n), and FP32 working with n > 128: the
+                                Jacobi sweeps run in double-double on the Gram matrix
+                                preconditioned by Algorithm 2's eigenvectors X, i.e. on
+                                X^T M_h X, whose rotations are all small; a sweep applies
+                                its rotations together to first order in the angles
+                                (X <- X (I + F), Ogita-Aishima form, which also restores
+                                X^T X = I), until the largest angle is <= 2^-30.  The
+                                threshold option applies to the Algorithm 2 stage. */
     GSVD_EIG_CHOL_JACOBI1 = 2 /* Algorithm 2: Cholesky of M_h at u_h, R cast to u,
                                  one-sided Jacobi SVD of R (Thm. 2, Lemma 1); default
-                                 threshold sqrt(n) * u */
+                                 threshold sqrt(n) * u.  FP32 working with n > 128: the
+                                 SVD of R runs in FP64 and its results are rounded */
 };
 
 /* flags */
@@ -79,12 +89,29 @@ enum {
 #define GSVD_INFO_NOT_SPD 1       /* M_h not positive definite at u_h: A not of full rank */
 #define GSVD_INFO_NO_CONVERGE 2   /* Jacobi did not converge within max_sweeps */
 #define GSVD_INFO_NONFINITE 3     /* A (hence M_h) holds a NaN or Inf */
+/* Warning bits, or-ed into an info that is otherwise 0; the outputs are
+   complete.  (info & 0xff) != 0 means failure. */
+#define GSVD_INFO_WARN_ASSUMPTION 256 /* eq. (thm:assump), eps_1 <= 1/2, cannot be
+                                     verified: with kappa(B) bounded by
+                                     sqrt(n) ||D W||_F (D = diag(sqrt(m_jj)),
+                                     W = V Sigma^-1) and unit constants,
+                                     eps_1 = 2 (n^2 eps_M + n u_h) kappa^2
+                                           + 4 n sqrt(n) (1 + n) u kappa > 1/2,
+                                     where eps_M is u_h for the plain Gram and
+                                     2^(7 - 8 n_slices) for the split Gram; the
+                                     error bounds of Theorem 1 then do not apply */
+#define GSVD_INFO_WARN_REFINE 512 /* the double-double Jacobi stage of JACOBI2 (FP64
+                                     working, or n > 128) left pairs of eigenvalues that
+                                     agree to within their coupling unrotated, or its
+                                     last sweep had an angle above 2^-30 */
 
 #define GSVD_MAX_N 512            /* largest n of the single-problem calls; n > 128 runs
                                      the wide kernels (64-column panel pairs, blocked
                                      Cholesky, block Jacobi) */
-#define GSVD_MAX_N_EIG_F32 128    /* FP32 working: largest n of the eigensolver stage
-                                     (larger n returns GSVD_ERR_UNSUPPORTED) */
+#define GSVD_MAX_N_EIG_F32 512    /* FP32 working: largest n of the eigensolver stage
+                                     (n > 128: Algorithm 2 over many workgroups with the
+                                     SVD of R in FP64, plus the double-double Jacobi
+                                     stage for JACOBI2) */
 #define GSVD_MAX_N_BATCHED_F64 96 /* largest n of a batched problem, FP64 working */
 #define GSVD_MAX_N_BATCHED_F32 128 /* largest n of a batched problem, FP32 working */
 #define GSVD_MAX_SLICES 12        /* largest n_slices of the split Gram, FP64 A */

@@ -93,3 +93,24 @@ def rel_err_mp(hi: float, lo: float, ref, dps: int = 60) -> float:
     with mpmath.workdps(dps):
         v = mpmath.mpf(hi) + mpmath.mpf(lo)
         return float(abs(v - ref) / ref)
+
+
+def mp_eigvecs(A: np.ndarray, dps: int = 60, G=None):
+    """(sigma, V) of the stored A from the exact Gram and mpmath's eigsy at `dps` digits:
+    sigma descending (mpf), V as an n x n numpy array of mpf whose columns are the unit
+    eigenvectors in that order, each with the sign mpmath returned (no sign rule)."""
+    G = exact_gram(A) if G is None else G
+    n = len(G)
+    with mpmath.workdps(dps):
+        M = mpmath.matrix(n, n)
+        for i in range(n):
+            for j in range(n):
+                M[i, j] = mpmath.mpf(G[i][j].numerator) / G[i][j].denominator
+        E, Q = mpmath.eigsy(M)
+        order = sorted(range(n), key=lambda i: -E[i])
+        sig = [mpmath.sqrt(E[i]) for i in order]
+        V = np.empty((n, n), dtype=object)
+        for c, i in enumerate(order):
+            for r in range(n):
+                V[r, c] = Q[r, i]
+    return sig, V

@@ -12,6 +12,7 @@ missing the import raises, naming the build command.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -178,6 +179,14 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(int(s.cuda_stream))
 
 
+def _on(stream):
+    """Allocate on the stream the library will run on: torch's caching allocator
+    then hands the blocks (workspace, outputs, info) to later work only in that
+    stream's order, after the library's kernels."""
+    torch = _torch()
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 def workspace(nbytes: int, device):
     torch = _torch()
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
@@ -194,16 +203,17 @@ def thin(A, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, want_u: boo
     lda = _ld(A)
     o = opts(w, gram, eig, want_u=want_u, jacobi_tol=jacobi_tol, max_sweeps=max_sweeps,
              n_slices=n_slices, slab_rows=slab_rows)
-    S = torch.empty(n, dtype=A.dtype, device=A.device)
-    V = colmajor_empty(n, n, A.dtype, A.device)
-    U = colmajor_empty(m, n, A.dtype, A.device) if want_u else None
-    info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    need = lib.gsvd_thin_workspace_size(m, n, ctypes.byref(o))
-    if work is None:
-        work = workspace(need, A.device)
-    rc = lib.gsvd_thin(m, n, A.data_ptr(), lda, S.data_ptr(), V.data_ptr(), n,
-                       U.data_ptr() if want_u else None, m, work.data_ptr(), work.numel(),
-                       info.data_ptr(), ctypes.byref(o), _stream(stream))
+    with _on(stream):
+        S = torch.empty(n, dtype=A.dtype, device=A.device)
+        V = colmajor_empty(n, n, A.dtype, A.device)
+        U = colmajor_empty(m, n, A.dtype, A.device) if want_u else None
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+        need = lib.gsvd_thin_workspace_size(m, n, ctypes.byref(o))
+        if work is None:
+            work = workspace(need, A.device)
+        rc = lib.gsvd_thin(m, n, A.data_ptr(), lda, S.data_ptr(), V.data_ptr(), n,
+                           U.data_ptr() if want_u else None, m, work.data_ptr(), work.numel(),
+                           info.data_ptr(), ctypes.byref(o), _stream(stream))
     _check(rc, "gsvd_thin")
     return S, V, U, info
 
@@ -215,13 +225,14 @@ def gram(A, *, work=None, stream=None):
     m, n = int(A.shape[0]), int(A.shape[1])
     lda = _ld(A)
     o = opts(w, GSVD_GRAM_PLAIN)
-    Mhi = colmajor_empty(n, n, torch.float64, A.device)
-    Mlo = colmajor_empty(n, n, torch.float64, A.device)
-    need = lib.gsvd_gram_workspace_size(m, n, ctypes.byref(o))
-    if work is None:
-        work = workspace(need, A.device)
-    rc = lib.gsvd_gram(m, n, A.data_ptr(), lda, Mhi.data_ptr(), Mlo.data_ptr(), n,
-                       work.data_ptr(), work.numel(), ctypes.byref(o), _stream(stream))
+    with _on(stream):
+        Mhi = colmajor_empty(n, n, torch.float64, A.device)
+        Mlo = colmajor_empty(n, n, torch.float64, A.device)
+        need = lib.gsvd_gram_workspace_size(m, n, ctypes.byref(o))
+        if work is None:
+            work = workspace(need, A.device)
+        rc = lib.gsvd_gram(m, n, A.data_ptr(), lda, Mhi.data_ptr(), Mlo.data_ptr(), n,
+                           work.data_ptr(), work.numel(), ctypes.byref(o), _stream(stream))
     _check(rc, "gsvd_gram")
     return Mhi, Mlo
 
@@ -233,16 +244,18 @@ def eig(Mhi, Mlo, working: int, *, eig: int = GSVD_EIG_AUTO, jacobi_tol: float =
     n = int(Mhi.shape[0])
     dt = torch.float64 if working == GSVD_F64 else torch.float32
     o = opts(working, GSVD_GRAM_PLAIN, eig, jacobi_tol=jacobi_tol, max_sweeps=max_sweeps)
-    S = torch.empty(n, dtype=dt, device=Mhi.device)
-    V = colmajor_empty(n, n, dt, Mhi.device)
-    W = colmajor_empty(n, n, dt, Mhi.device)
-    info = torch.full((1,), -1, dtype=torch.int32, device=Mhi.device)
-    need = lib.gsvd_eig_workspace_size(n, ctypes.byref(o))
-    work = workspace(need, Mhi.device) if need > 0 else None
-    rc = lib.gsvd_eig(n, Mhi.data_ptr(), Mlo.data_ptr() if Mlo is not None else None, _ld(Mhi),
-                      S.data_ptr(), V.data_ptr(), n, W.data_ptr(), n, info.data_ptr(),
-                      work.data_ptr() if work is not None else None,
-                      work.numel() if work is not None else 0, ctypes.byref(o), _stream(stream))
+    with _on(stream):
+        S = torch.empty(n, dtype=dt, device=Mhi.device)
+        V = colmajor_empty(n, n, dt, Mhi.device)
+        W = colmajor_empty(n, n, dt, Mhi.device)
+        info = torch.full((1,), -1, dtype=torch.int32, device=Mhi.device)
+        need = lib.gsvd_eig_workspace_size(n, ctypes.byref(o))
+        work = workspace(need, Mhi.device) if need > 0 else None
+        rc = lib.gsvd_eig(n, Mhi.data_ptr(), Mlo.data_ptr() if Mlo is not None else None,
+                          _ld(Mhi), S.data_ptr(), V.data_ptr(), n, W.data_ptr(), n,
+                          info.data_ptr(), work.data_ptr() if work is not None else None,
+                          work.numel() if work is not None else 0, ctypes.byref(o),
+                          _stream(stream))
     _check(rc, "gsvd_eig")
     return S, V, W, info
 
@@ -252,9 +265,10 @@ def u_recover(A, W, *, stream=None):
     w = _working_of(A)
     m, n = int(A.shape[0]), int(A.shape[1])
     o = opts(w)
-    U = colmajor_empty(m, n, A.dtype, A.device)
-    rc = lib.gsvd_u_recover(m, n, A.data_ptr(), _ld(A), W.data_ptr(), _ld(W), U.data_ptr(), m,
-                            ctypes.byref(o), _stream(stream))
+    with _on(stream):
+        U = colmajor_empty(m, n, A.dtype, A.device)
+        rc = lib.gsvd_u_recover(m, n, A.data_ptr(), _ld(A), W.data_ptr(), _ld(W), U.data_ptr(),
+                                m, ctypes.byref(o), _stream(stream))
     _check(rc, "gsvd_u_recover")
     return U
 
@@ -302,6 +316,13 @@ class Batch:
         self.work = workspace(need, dev)
 
     def run(self, stream=None) -> None:
+        """Enqueue the call on ``stream`` (default: torch's current stream).  The buffers
+        were allocated on the stream current at construction; on another stream they are
+        recorded as used there, so the caching allocator keeps them until that work ends."""
+        if stream is not None:
+            for t in [self.work, self.info, self.dA, self.dS, self.dV, *self.S, *self.V,
+                      *(self.U or []), *([self.dU] if self.dU is not None else [])]:
+                t.record_stream(stream)
         rc = lib.gsvd_thin_batched(
             self.count, self.hM, self.hN, self.dA.data_ptr(), self.hLda, self.dS.data_ptr(),
             self.dV.data_ptr(), self.hLdv, self.dU.data_ptr() if self.dU is not None else None,

@@ -39,11 +39,9 @@ inline int max_slices(int working) {
     return working == GSVD_F64 ? GSVD_MAX_SLICES : GSVD_MAX_SLICES_F32;
 }
 
-// The eigensolver in force: AUTO is the two-sided Jacobi for FP32 working
-// (M_h in FP64) and Algorithm 2 for FP64 working (M_h in double-double).
+// The eigensolver in force: AUTO is the two-sided Jacobi on M_h at u_h.
 inline int eig_mode_of(const gsvd_opts *o) {
-    if (o->eig != GSVD_EIG_AUTO) return o->eig;
-    return o->working == GSVD_F32 ? GSVD_EIG_JACOBI2 : GSVD_EIG_CHOL_JACOBI1;
+    return o->eig == GSVD_EIG_AUTO ? GSVD_EIG_JACOBI2 : o->eig;
 }
 
 inline bool use_split(const gsvd_opts *o) { return o->gram == GSVD_GRAM_SPLIT; }
@@ -51,16 +49,24 @@ inline bool use_split(const gsvd_opts *o) { return o->gram == GSVD_GRAM_SPLIT; }
 inline int check_supported(const gsvd_opts *o) {
     if (o->gram == GSVD_GRAM_SPLIT && o->n_slices > max_slices(o->working))
         return GSVD_ERR_UNSUPPORTED;
-    // the two-sided Jacobi runs in FP64: it is the u_h solver of FP32 working only
-    if (eig_mode_of(o) == GSVD_EIG_JACOBI2 && o->working != GSVD_F32) return GSVD_ERR_UNSUPPORTED;
     return 0;
 }
 
 // n > 128: the wide Gram and U kernels (64-column panels)
 inline bool wide_n(int64_t n) { return n > GSVD_KMAX_N; }
-// FP64 working beyond the one-workgroup eigensolver: the multi-launch Algorithm 2
+// FP32 working beyond the one-workgroup eigensolvers: Algorithm 2 over many
+// workgroups with the SVD of R in FP64, results rounded to FP32
+inline bool f32_wide_eig(const gsvd_opts *o, int64_t n) {
+    return o->working == GSVD_F32 && n > GSVD_KMAX_N;
+}
+// beyond the one-workgroup eigensolver: the multi-launch Algorithm 2
 inline bool wide_eig(const gsvd_opts *o, int64_t n) {
-    return o->working == GSVD_F64 && n > GSVD_KMAX_N_F64;
+    return (o->working == GSVD_F64 && n > GSVD_KMAX_N_F64) || f32_wide_eig(o, n);
+}
+// the double-double Jacobi stage after Algorithm 2 (JACOBI2 for FP64 working,
+// and for FP32 working beyond the one-workgroup two-sided Jacobi)
+inline bool eig_refined(const gsvd_opts *o, int64_t n) {
+    return eig_mode_of(o) == GSVD_EIG_JACOBI2 && (o->working == GSVD_F64 || n > GSVD_KMAX_N);
 }
 
 inline int check_eig_supported(const gsvd_opts *o, int64_t n) {
@@ -145,34 +151,112 @@ inline size_t gram_part_bytes(int64_t m, int64_t n, const gsvd_opts *o, bool bat
     return gram_plan_of(o, m, n, batched).part_bytes;
 }
 
-// default rotation threshold: n u_h for the two-sided Jacobi on M_h (FP64),
-// sqrt(n) u_w for the one-sided Jacobi on R in Algorithm 2
+// rotation threshold of Algorithm 2's one-sided Jacobi: sqrt(n) u_w unless given
+inline double alg2_tol_of(const gsvd_opts *o, int64_t n) {
+    if (o->jacobi_tol > 0) return o->jacobi_tol;
+    return __builtin_sqrt((double)n) * unit_roundoff(o->working);
+}
+
+// default rotation threshold: n u_h for the one-workgroup two-sided Jacobi on
+// M_h (FP32 working, FP64), else Algorithm 2's
 inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
     if (o->jacobi_tol > 0) return o->jacobi_tol;
-    if (eig_mode_of(o) == GSVD_EIG_JACOBI2) return (double)n * 0x1p-53;
-    return __builtin_sqrt((double)n) * unit_roundoff(o->working);
+    if (eig_mode_of(o) == GSVD_EIG_JACOBI2 && o->working == GSVD_F32 && !wide_n(n))
+        return (double)n * 0x1p-53;
+    return alg2_tol_of(o, n);
 }
 
 inline int sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 30; }
 
-inline size_t eig_work_bytes(const gsvd_opts *o, int64_t n) {
-    if (wide_eig(o, n)) return eig_wide_work_bytes(n);
-    return eig_mode_of(o) == GSVD_EIG_JACOBI2 ? j2_work_bytes(n, sweeps_of(o)) : 0;
+// eps_M of eq. (ATA) for the assumption check, in the scaled sense
+// |dM_ij| <= eps sqrt(M_ii M_jj): u_h for the plain Gram; for the split Gram the
+// tuning table's measured error of its slice count
+inline double gram_eps_of(const gsvd_opts *o, int64_t n) {
+    const double u_h = o->working == GSVD_F64 ? 0x1p-104 : 0x1p-53;
+    if (!use_split(o)) return u_h;
+    const double e = tune_eps(o->working, n, slices_of(o, n));
+    return e > u_h ? e : u_h;
 }
 
+// Eigensolver scratch.  FP32 working with n > 128: S, V, W of the FP64
+// Algorithm 2, a zero low plane (when the caller passes none), then the
+// Algorithm 2 / double-double stage scratch (used one after the other).
+struct EigLayout {
+    size_t s64, v64, w64, zlo, scratch, total;
+};
+
+inline EigLayout eig_layout(const gsvd_opts *o, int64_t n) {
+    EigLayout L{};
+    size_t scratch = 0;
+    if (wide_eig(o, n)) scratch = eig_wide_work_bytes(n);
+    if (eig_refined(o, n)) scratch = scratch > refine_work_bytes(n) ? scratch : refine_work_bytes(n);
+    if (o->working == GSVD_F32 && !wide_n(n) && eig_mode_of(o) == GSVD_EIG_JACOBI2)
+        scratch = j2_work_bytes(n, sweeps_of(o));
+    size_t off = 0;
+    if (f32_wide_eig(o, n)) {
+        const size_t nn = (size_t)n * (size_t)n;
+        L.s64 = off;
+        off = align_up(off + (size_t)n * sizeof(double));
+        L.v64 = off;
+        off = align_up(off + nn * sizeof(double));
+        L.w64 = off;
+        off = align_up(off + nn * sizeof(double));
+        L.zlo = off;
+        off = align_up(off + nn * sizeof(double));
+    }
+    L.scratch = off;
+    L.total = scratch ? align_up(off + scratch) : off;
+    return L;
+}
+
+inline size_t eig_work_bytes(const gsvd_opts *o, int64_t n) { return eig_layout(o, n).total; }
+
+// The eigensolver stage (Alg. 1 steps 3-5), then the assumption check.
 inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, const double *Mlo,
                           int64_t ldm, void *S, void *V, int64_t ldv, void *W, int64_t ldw,
-                          int *info, void *work, hipStream_t st) {
-    const double tol = jacobi_tol_of(o, n);
-    const int sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
-    if (wide_eig(o, n))
-        return eig_wide_launch(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps, work, st);
-    if (eig_mode_of(o) == GSVD_EIG_JACOBI2)
-        return eig_jacobi2_launch(o->working, n, Mhi, ldm, S, V, ldv, W, ldw, info, tol, sweeps,
-                                  work, st);
-    return eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps, st);
+                          int *info, void *work, double eps_m, hipStream_t st) {
+    const int sweeps = sweeps_of(o);
+    char *base = (char *)work;
+    const EigLayout L = eig_layout(o, n);
+    hipError_t err;
+    if (f32_wide_eig(o, n)) {
+        double *s64 = (double *)(base + L.s64);
+        double *v64 = (double *)(base + L.v64);
+        double *w64 = (double *)(base + L.w64);
+        const double *lo = Mlo;
+        if (lo == nullptr) {
+            double *z = (double *)(base + L.zlo);
+            if ((err = fill_zero_launch(z, (size_t)n * (size_t)n, st)) != hipSuccess) return err;
+            lo = z;
+        }
+        void *scr = base + L.scratch;
+        err = eig_wide_launch(n, Mhi, lo, ldm, s64, v64, n, w64, n, info, alg2_tol_of(o, n),
+                              sweeps, scr, st);
+        if (err == hipSuccess)
+            err = eig_refined(o, n)
+                      ? refine_launch(GSVD_F32, n, Mhi, lo, ldm, v64, n, S, V, ldv, W, ldw, info,
+                                      scr, st)
+                      : cast_eig_f32_launch(n, s64, v64, S, V, ldv, W, ldw, info, st);
+    } else if (o->working == GSVD_F64) {
+        const double tol = alg2_tol_of(o, n);
+        err = wide_eig(o, n)
+                  ? eig_wide_launch(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps, work,
+                                    st)
+                  : eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps,
+                               st);
+        if (err == hipSuccess && eig_refined(o, n))
+            err = refine_launch(GSVD_F64, n, Mhi, Mlo, ldm, (const double *)V, ldv, S, V, ldv, W,
+                                ldw, info, work, st);
+    } else if (eig_mode_of(o) == GSVD_EIG_JACOBI2) {
+        err = eig_jacobi2_launch(o->working, n, Mhi, ldm, S, V, ldv, W, ldw, info,
+                                 jacobi_tol_of(o, n), sweeps, work, st);
+    } else {
+        err = eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info,
+                         jacobi_tol_of(o, n), sweeps, st);
+    }
+    if (err != hipSuccess) return err;
+    return assump_launch(o->working, n, Mhi, ldm, W, ldw, info, eps_m, st);
 }
-
 
 inline hipError_t urecover_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A,
                                int64_t lda, const void *W, int64_t ldw, void *U, int64_t ldu,

@@ -16,6 +16,9 @@
 //   one Gram launch per class   grid (tile groups, slabs, problems of the class)
 //   one reduction launch         grid (entries, problems)
 //   one eigensolver launch       one workgroup per problem, largest n first
+//   FP64 working, JACOBI2: the double-double Jacobi stage, a fixed sequence of
+//                                launches each covering every problem
+//   one assumption-check launch  one workgroup per problem
 //   one U launch per class       grid (tile groups, 1, problems of the class)
 #include <hip/hip_runtime.h>
 
@@ -31,14 +34,14 @@
 namespace gsvd {
 namespace {
 
-// What the host knows of one problem (kernel-argument payload, 64 bytes).
+// What the host knows of one problem (kernel-argument payload, 72 bytes).
 struct MatArg {
     int64_t m, lda, ldu, rows_per_split;
-    int64_t part_off, mat_off;  // byte offsets in the workspace
+    int64_t part_off, mat_off, rw_off;  // byte offsets in the workspace (rw_off < 0: none)
     int32_t n, ldv, nsplit, pos;
 };
 
-constexpr int kChunk = 56;  // problems per set-up launch (3584 bytes of arguments)
+constexpr int kChunk = 48;  // problems per set-up launch (3456 bytes of arguments)
 
 struct SetupArgs {
     int first, count;
@@ -62,6 +65,7 @@ batch_setup_kernel(SetupArgs args, char *base, const void *const *dA, void *cons
         d.Mlo = d.Mhi + nn;
         d.W = reinterpret_cast<void *>(d.Mlo + nn);
         d.part = reinterpret_cast<double *>(base + x.part_off);
+        d.rw = x.rw_off >= 0 ? reinterpret_cast<double *>(base + x.rw_off) : nullptr;
         d.info = dInfo + i;
         d.m = x.m;
         d.lda = x.lda;
@@ -101,6 +105,7 @@ int plan_batch(int batch, const int64_t *hM, const int64_t *hN, const int64_t *h
                const int64_t *hLdv, const int64_t *hLdu, bool want_u, const gsvd_opts *o,
                BatchPlan &P) {
     const bool split = use_split(o);
+    const bool refine = o->working == GSVD_F64 && eig_mode_of(o) == GSVD_EIG_JACOBI2;
     P.order.resize(batch);
     for (int i = 0; i < batch; ++i) P.order[i] = i;
     std::stable_sort(P.order.begin(), P.order.end(),
@@ -147,6 +152,11 @@ int plan_batch(int batch, const int64_t *hM, const int64_t *hN, const int64_t *h
         off = align_up(off + 2 * nn * sizeof(double) + nn * ws);
         x.part_off = off;
         off = align_up(off + part);
+        x.rw_off = -1;
+        if (refine) {
+            x.rw_off = (int64_t)off;
+            off = align_up(off + refine_work_bytes(n));
+        }
         // Gram classes: consecutive problems with the same launch shape
         const bool same = !P.gram.empty() &&
                           (split ? (P.gram.back().sp.nb == sp.nb && P.gram.back().sp.S == sp.S &&
@@ -239,11 +249,20 @@ int gsvd_thin_batched(int batch, const int64_t *hM, const int64_t *hN, const voi
     err = use_split(o) ? split_reduce_batched_launch(tab, batch, P.max_n, st)
                        : gram_reduce_batched_launch(tab, batch, P.max_n, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
-    err = eig_mode_of(o) == GSVD_EIG_JACOBI2
-              ? eig_jacobi2_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol,
-                                           sweeps_of(o), st)
-              : eig_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol,
-                                   sweeps_of(o), st);
+    if (o->working == GSVD_F64) {
+        err = eig_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol,
+                                 sweeps_of(o), st);
+        if (err == hipSuccess && eig_mode_of(o) == GSVD_EIG_JACOBI2)
+            err = refine_batched_launch(tab, batch, P.max_n, st);
+    } else {
+        err = eig_mode_of(o) == GSVD_EIG_JACOBI2
+                  ? eig_jacobi2_batched_launch(o->working, tab, order, batch, P.max_n,
+                                               o->jacobi_tol, sweeps_of(o), st)
+                  : eig_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol,
+                                       sweeps_of(o), st);
+    }
+    if (err == hipSuccess)
+        err = assump_batched_launch(o->working, tab, batch, gram_eps_of(o, P.max_n), st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (want_u) {
         for (const UClass &c : P.u) {

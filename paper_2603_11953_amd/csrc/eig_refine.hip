@@ -1,0 +1,598 @@
+// Two-sided Jacobi on M_h at the Gram precision (Sec. 2.1, Remark 1),
+// preconditioned by Algorithm 2.
+//
+// Remark 1 bounds the orthogonality of U by O(u) + O(u_h) kappa^2(B) when the
+// eigensolver of Alg. 1 step 3 is the two-sided Jacobi method run at u_h; with
+// Algorithm 2 (the remark after Lemma 1) the bound is O(u) kappa(B).  The
+// difference comes from the eigenvector matrix: Algorithm 2 rounds R to the
+// working precision, so its V diagonalises M_h only to O(u kappa(B)) in the
+// scaled sense |x_i^T M_h x_j| <= eps sqrt(lambda_i lambda_j).
+//
+// This stage runs the u_h Jacobi method on the Gram matrix expressed in the
+// basis X that Algorithm 2 returned:
+//
+//   S = X^T M_h X,  G = X^T X               (double-double, exact products)
+//   lambda_i = s_ii / g_ii                  (Rayleigh quotients)
+//   f_ij = (s_ij - lambda_j g_ij) / (lambda_j - lambda_i),  i != j
+//   f_ii = (1 - g_ii) / 2
+//   X <- X (I + F)                          (double-double)
+//
+// S is diagonal up to the O(u kappa(B)) coupling left by Algorithm 2, so every
+// Jacobi rotation of a sweep on S is tiny.  The antisymmetric part of F holds
+// the first-order angles of those rotations (tan 2 theta = 2 s_ij /
+// (s_jj - s_ii) gives theta = s_ij / (lambda_j - lambda_i) + O(theta^3)), and
+// rotations by angles of order theta commute up to O(theta^2): the whole sweep
+// is applied at once, with an error of second order in the angles.  The
+// symmetric part of F, -(G - I)/2, re-orthogonalises X to first order.  This
+// update is the eigenvector refinement of Ogita and Aishima (2018, "Iterative
+// refinement for symmetric eigenvalue decomposition"), which converges
+// quadratically: one sweep when the largest angle is below 2^-30 (the
+// neglected terms are then below 2^-60 relative), a few otherwise.
+//
+// Stopping rule: the sweep whose largest angle is <= 2^-30 is the last.  At most
+// RK sweeps are queued on the stream; those after convergence return at once.
+// A pair whose angle would exceed 2^-8 (eigenvalues that agree to within the
+// coupling: a cluster) is not rotated (f_ij = -g_ij / 2 only re-orthogonalises);
+// such pairs, or a last sweep above the threshold, set GSVD_INFO_WARN_REFINE.
+//
+// Every sum is a double-double dot product over exact FP64 products (TwoProduct
+// with the low parts folded in), so S and G carry u_h relative to
+// |X|^T |M_h| |X| and |X|^T |X|: in the scaled sense that is O(u_h kappa^2(B)),
+// the term Remark 1 keeps.
+//
+// Outputs as every eigensolver of the library writes them: sigma_i =
+// sqrt(lambda_i) (double-double square root) rounded to the working precision,
+// sigma descending, each V column signed so its entry of largest magnitude is
+// positive, V rounded to the working precision, W = fl(V Sigma^-1).
+#include <hip/hip_runtime.h>
+
+#include "dd_device.hpp"
+#include "gsvd.h"
+#include "gsvd_internal.hpp"
+
+namespace gsvd {
+namespace {
+
+constexpr int RK = 4;                  // sweeps queued
+constexpr double TAU_STOP = 0x1p-30;   // last sweep: every angle at most this
+constexpr double TAU_CLUSTER = 0x1p-8; // larger angles: a cluster pair, not rotated
+constexpr int TB = 32;                 // output tile edge of the products
+constexpr int KC = 16;                 // k-chunk staged through LDS
+constexpr int FT = 1024;               // lanes of the per-problem kernels
+
+struct RefCtrl {
+    int stop_iter;  // sweeps 0 .. stop_iter run; -1: nothing (the preconditioner failed)
+    int warn;       // bit 0: last sweep above TAU_STOP; bit 1: cluster pairs left
+    int pad[14];
+};
+
+// Per-problem scratch, in doubles after the 64-byte control block: X twice
+// (ping-pong, hi and lo planes), T = M X, S, G (hi and lo), F, lambda (hi, lo).
+struct RefBufs {
+    RefCtrl *ctrl;
+    double *xh[2], *xl[2], *th, *tl, *sh, *sl, *gh, *gl, *f, *lh, *ll;
+};
+
+__host__ __device__ inline size_t ref_bytes_of(int n) {
+    const size_t nn = (size_t)n * (size_t)n;
+    const size_t b = sizeof(RefCtrl) + (11 * nn + 2 * (size_t)n) * sizeof(double);
+    return (b + 255) / 256 * 256;
+}
+
+__device__ __forceinline__ RefBufs ref_bufs(double *rw, int n) {
+    const size_t nn = (size_t)n * (size_t)n;
+    RefBufs B;
+    B.ctrl = reinterpret_cast<RefCtrl *>(rw);
+    double *d = rw + sizeof(RefCtrl) / sizeof(double);
+    B.xh[0] = d;
+    B.xl[0] = d + nn;
+    B.xh[1] = d + 2 * nn;
+    B.xl[1] = d + 3 * nn;
+    B.th = d + 4 * nn;
+    B.tl = d + 5 * nn;
+    B.sh = d + 6 * nn;
+    B.sl = d + 7 * nn;
+    B.gh = d + 8 * nn;
+    B.gl = d + 9 * nn;
+    B.f = d + 10 * nn;
+    B.lh = d + 11 * nn;
+    B.ll = B.lh + n;
+    return B;
+}
+
+// One problem as the kernels see it.
+struct RefProb {
+    const double *Mhi, *Mlo;  // Mlo may be null (an FP64 Gram: low parts zero)
+    int64_t ldm;
+    const double *X0;         // the preconditioner (Algorithm 2's V), FP64
+    int64_t ldx0;
+    void *S, *V, *W;          // outputs, working precision
+    int64_t ldv, ldw;
+    int *info;
+    double *rw;               // ref_bytes_of(n) bytes of scratch
+    int n;
+};
+
+struct OneRef {
+    RefProb p;
+    __device__ RefProb get(int) const { return p; }
+};
+
+// Batched, FP64 working: the problem's record in the batch table.
+struct TabRef {
+    const BatchMat *tab;
+    __device__ RefProb get(int b) const {
+        const BatchMat &t = tab[b];
+        RefProb p;
+        p.Mhi = t.Mhi;
+        p.Mlo = t.Mlo;
+        p.ldm = t.n;
+        p.X0 = reinterpret_cast<const double *>(t.V);
+        p.ldx0 = t.ldv;
+        p.S = t.S;
+        p.V = t.V;
+        p.W = t.W;
+        p.ldv = t.ldv;
+        p.ldw = t.n;
+        p.info = t.info;
+        p.rw = t.rw;
+        p.n = t.n;
+        return p;
+    }
+};
+
+// acc (h + l) += a * b for double-double a, b: the product of the high parts
+// exactly (TwoProduct), the cross terms folded into its error, TwoSum into h.
+__device__ __forceinline__ void mac_dd(double &h, double &l, double ah, double al, double bh,
+                                       double bl) {
+    const double p = ah * bh;
+    double e = __builtin_fma(ah, bh, -p);
+    e = __builtin_fma(ah, bl, e);
+    e = __builtin_fma(al, bh, e);
+    const double s = h + p;
+    const double bv = s - h;
+    const double err = (h - (s - bv)) + (p - bv);
+    h = s;
+    l += err + e;
+}
+
+template <class P>
+__global__ void __launch_bounds__(256) ref_init_kernel(P probs) {
+    const RefProb p = probs.get(blockIdx.y);
+    const int n = p.n;
+    const int nn = n * n;
+    RefBufs B = ref_bufs(p.rw, n);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        B.ctrl->stop_iter = (*p.info != 0) ? -1 : RK - 1;
+        B.ctrl->warn = 0;
+    }
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nn) return;
+    const int r = idx % n, c = idx / n;
+    B.xh[0][idx] = p.X0[r + (int64_t)c * p.ldx0];
+    B.xl[0][idx] = 0.0;
+}
+
+// MODE 0: T = M X.  MODE 1: [S | G] = X^T [T | X].  MODE 2: X' = X + X F.
+// One workgroup per 32 x 32 output tile; each lane owns a 2 x 2 block (rows
+// tx, tx + 16 and columns ty, ty + 16 of the tile).
+template <int MODE, class P>
+__global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter) {
+    const RefProb p = probs.get(blockIdx.z);
+    const int n = p.n;
+    const int ncol = MODE == 1 ? 2 * n : n;
+    const int i0 = blockIdx.x * TB, j0 = blockIdx.y * TB;
+    if (i0 >= n || j0 >= ncol) return;
+    RefBufs B = ref_bufs(p.rw, n);
+    if (iter > B.ctrl->stop_iter) return;
+    const int cur = iter & 1;
+    const double *__restrict__ Xh = B.xh[cur];
+    const double *__restrict__ Xl = B.xl[cur];
+
+    __shared__ double Ah[TB][KC + 1], Al[TB][KC + 1], Bh[KC][TB + 1], Bl[KC][TB + 1];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    double ch[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, cl[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+
+    for (int k0 = 0; k0 < n; k0 += KC) {
+        for (int e = tid; e < TB * KC; e += 256) {
+            int i, k;
+            if (MODE == 1) {  // A = X^T: contiguous along k
+                k = e % KC;
+                i = e / KC;
+            } else {          // A = M or X: contiguous along i
+                i = e % TB;
+                k = e / TB;
+            }
+            const int gi = i0 + i, gk = k0 + k;
+            double ah = 0.0, al = 0.0;
+            if (gi < n && gk < n) {
+                if (MODE == 0) {
+                    const int64_t o = gi + (int64_t)gk * p.ldm;
+                    ah = p.Mhi[o];
+                    al = p.Mlo ? p.Mlo[o] : 0.0;
+                } else if (MODE == 1) {
+                    ah = Xh[gk + gi * n];
+                    al = Xl[gk + gi * n];
+                } else {
+                    ah = Xh[gi + gk * n];
+                    al = Xl[gi + gk * n];
+                }
+            }
+            Ah[i][k] = ah;
+            Al[i][k] = al;
+        }
+        for (int e = tid; e < TB * KC; e += 256) {
+            const int k = e % KC, j = e / KC;
+            const int gk = k0 + k, gj = j0 + j;
+            double bh = 0.0, bl = 0.0;
+            if (gk < n && gj < ncol) {
+                if (MODE == 0) {
+                    bh = Xh[gk + gj * n];
+                    bl = Xl[gk + gj * n];
+                } else if (MODE == 1) {
+                    if (gj < n) {
+                        bh = B.th[gk + gj * n];
+                        bl = B.tl[gk + gj * n];
+                    } else {
+                        bh = Xh[gk + (gj - n) * n];
+                        bl = Xl[gk + (gj - n) * n];
+                    }
+                } else {
+                    bh = B.f[gk + gj * n];
+                }
+            }
+            Bh[k][j] = bh;
+            Bl[k][j] = bl;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < KC; ++k) {
+            const double a0h = Ah[tx][k], a0l = Al[tx][k];
+            const double a1h = Ah[tx + 16][k], a1l = Al[tx + 16][k];
+            const double b0h = Bh[k][ty], b0l = Bl[k][ty];
+            const double b1h = Bh[k][ty + 16], b1l = Bl[k][ty + 16];
+            mac_dd(ch[0][0], cl[0][0], a0h, a0l, b0h, b0l);
+            mac_dd(ch[1][0], cl[1][0], a1h, a1l, b0h, b0l);
+            mac_dd(ch[0][1], cl[0][1], a0h, a0l, b1h, b1l);
+            mac_dd(ch[1][1], cl[1][1], a1h, a1l, b1h, b1l);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * b;
+            if (gi >= n || gj >= ncol) continue;
+            dd_t c = two_sum(ch[a][b], cl[a][b]);
+            if (MODE == 0) {
+                B.th[gi + gj * n] = c.hi;
+                B.tl[gi + gj * n] = c.lo;
+            } else if (MODE == 1) {
+                if (gj < n) {
+                    B.sh[gi + gj * n] = c.hi;
+                    B.sl[gi + gj * n] = c.lo;
+                } else {
+                    B.gh[gi + (gj - n) * n] = c.hi;
+                    B.gl[gi + (gj - n) * n] = c.lo;
+                }
+            } else {
+                const int o = gi + gj * n;
+                c = dd_add(dd_t{Xh[o], Xl[o]}, c);
+                B.xh[cur ^ 1][o] = c.hi;
+                B.xl[cur ^ 1][o] = c.lo;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+// Rayleigh quotients, the update F, and the stopping decision (one workgroup
+// per problem).
+template <class P>
+__global__ void __launch_bounds__(FT) ref_angles_kernel(P probs, int iter) {
+    const RefProb p = probs.get(blockIdx.x);
+    const int n = p.n;
+    RefBufs B = ref_bufs(p.rw, n);
+    if (iter > B.ctrl->stop_iter) return;
+    __shared__ double lam_h[GSVD_WIDE_MAX_N], lam_l[GSVD_WIDE_MAX_N];
+    __shared__ double red[FT / 64];
+    __shared__ int redc[FT / 64];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += FT) {
+        const int o = i + i * n;
+        const dd_t lam = dd_div(dd_t{B.sh[o], B.sl[o]}, dd_t{B.gh[o], B.gl[o]});
+        lam_h[i] = lam.hi;
+        lam_l[i] = lam.lo;
+        B.lh[i] = lam.hi;
+        B.ll[i] = lam.lo;
+    }
+    __syncthreads();
+    double mx = 0.0;
+    int clus = 0;
+    for (int idx = tid; idx < n * n; idx += FT) {
+        const int i = idx % n, j = idx / n;
+        double f;
+        if (i == j) {
+            const dd_t r = dd_sub(dd_t{1.0, 0.0}, dd_t{B.gh[idx], B.gl[idx]});
+            f = 0.5 * r.hi;
+        } else {
+            const double s = B.sh[idx] + B.sl[idx];
+            const double g = B.gh[idx] + B.gl[idx];
+            const double num = __builtin_fma(-lam_h[j], g, s);
+            const dd_t den = dd_sub(dd_t{lam_h[j], lam_l[j]}, dd_t{lam_h[i], lam_l[i]});
+            f = num / den.hi;
+            if (!(__builtin_fabs(f) <= TAU_CLUSTER)) {
+                clus = 1;
+                f = -0.5 * g;
+            } else {
+                mx = fmax(mx, __builtin_fabs(f));
+            }
+        }
+        B.f[idx] = f;
+    }
+    mx = wave_max(mx);
+    const unsigned long long any = __ballot(clus != 0);
+    if ((tid & 63) == 0) {
+        red[tid >> 6] = mx;
+        redc[tid >> 6] = any != 0ull;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double m = 0.0;
+        int c = 0;
+        for (int w = 0; w < FT / 64; ++w) {
+            m = fmax(m, red[w]);
+            c |= redc[w];
+        }
+        if (m <= TAU_STOP || iter == RK - 1) {
+            B.ctrl->stop_iter = iter;
+            B.ctrl->warn = (m <= TAU_STOP ? 0 : 1) | (c ? 2 : 0);
+        }
+    }
+}
+
+// sigma, ordering, signs, cast, W (one workgroup per problem).
+template <typename TW, class P>
+__global__ void __launch_bounds__(FT) ref_final_kernel(P probs) {
+    const RefProb p = probs.get(blockIdx.x);
+    const int n = p.n;
+    RefBufs B = ref_bufs(p.rw, n);
+    const int stop = B.ctrl->stop_iter;
+    if (stop < 0) return;
+    const double *__restrict__ Xh = B.xh[(stop + 1) & 1];
+    __shared__ double sig[GSVD_WIDE_MAX_N], sgn[GSVD_WIDE_MAX_N];
+    __shared__ int rank[GSVD_WIDE_MAX_N];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int c = wv; c < n; c += FT / 64) {
+        double best = -1.0;
+        int barg = 0;
+        for (int r = lane; r < n; r += 64) {
+            const double av = __builtin_fabs(Xh[r + c * n]);
+            if (av > best) {
+                best = av;
+                barg = r;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oa = __shfl_xor(barg, off, 64);
+            if (ob > best || (ob == best && oa < barg)) {
+                best = ob;
+                barg = oa;
+            }
+        }
+        if (lane == 0) {
+            sgn[c] = Xh[barg + c * n] < 0.0 ? -1.0 : 1.0;
+            sig[c] = dd_sqrt(dd_t{B.lh[c], B.ll[c]}).hi;
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < n; c += FT) {
+        const double sc = sig[c];
+        int rk = 0;
+        for (int q = 0; q < n; ++q) {
+            const double sq = sig[q];
+            rk += (sq > sc) || (sq == sc && q < c);
+        }
+        rank[c] = rk;
+    }
+    __syncthreads();
+    TW *S = reinterpret_cast<TW *>(p.S);
+    TW *V = reinterpret_cast<TW *>(p.V);
+    TW *W = reinterpret_cast<TW *>(p.W);
+    for (int idx = tid; idx < n * n; idx += FT) {
+        const int r = idx % n, c = idx / n;
+        const int pos = rank[c];
+        const TW sw = (TW)sig[c];
+        const TW vw = (TW)(sgn[c] * Xh[idx]);
+        V[r + (int64_t)pos * p.ldv] = vw;
+        W[r + (int64_t)pos * p.ldw] = vw / sw;
+        if (r == 0) S[pos] = sw;
+    }
+    if (tid == 0 && B.ctrl->warn != 0) *p.info = GSVD_INFO_WARN_REFINE;
+}
+
+// ---- the assumption check of Theorem 1 (every eigensolver) ----------------
+
+struct AssumpProb {
+    const double *Mhi;
+    int64_t ldm;
+    const void *W;
+    int64_t ldw;
+    int *info;
+    int n;
+};
+
+struct OneAssump {
+    AssumpProb p;
+    __device__ AssumpProb get(int) const { return p; }
+};
+
+struct TabAssump {
+    const BatchMat *tab;
+    __device__ AssumpProb get(int b) const {
+        const BatchMat &t = tab[b];
+        return AssumpProb{t.Mhi, t.n, t.W, t.n, t.info, t.n};
+    }
+};
+
+// kappa(B) <= ||B||_F ||B^+||_F = sqrt(n) ||D W||_F (B = A D^-1 has unit columns;
+// A = U Sigma V^T gives B^+ = D V Sigma^-1 U^T, so ||B^+||_F = ||D V Sigma^-1||_F,
+// with D = diag(sqrt(m_jj))).  With that kappa, eq. (thm:assump) with unit
+// constants: eps_1 = 2 (n^2 eps_m + n u_h) kappa^2 + 4 n sqrt(n) (1 + n) u kappa;
+// eps_1 > 1/2 sets GSVD_INFO_WARN_ASSUMPTION (the bounds of Theorem 1 are then
+// not guaranteed).
+template <typename TW, class P>
+__global__ void __launch_bounds__(256)
+assump_kernel(P probs, double eps_m, double u_h, double u_w) {
+    const AssumpProb p = probs.get(blockIdx.x);
+    const int n = p.n;
+    const TW *W = reinterpret_cast<const TW *>(p.W);
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+        const int r = idx % n, c = idx / n;
+        const double w = (double)W[r + (int64_t)c * p.ldw];
+        s = __builtin_fma(p.Mhi[r + (int64_t)r * p.ldm] * w, w, s);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int info = *p.info;
+    if ((info & 0xff) != 0) return;
+    const double dn = (double)n;
+    const double kap = __builtin_sqrt(dn * (((red[0] + red[1]) + red[2]) + red[3]));
+    const double eps1 = 2.0 * (dn * dn * eps_m + dn * u_h) * kap * kap +
+                        4.0 * dn * __builtin_sqrt(dn) * (1.0 + dn) * u_w * kap;
+    if (!(eps1 <= 0.5)) *p.info = info | GSVD_INFO_WARN_ASSUMPTION;
+}
+
+// FP64 eigensolver outputs cast to FP32 working precision (Alg. 1 steps 4-5):
+// S and V rounded, W = fl(V Sigma^-1) formed from the rounded values.
+__global__ void __launch_bounds__(256)
+cast_eig_kernel(int n, const double *__restrict__ S64, const double *__restrict__ V64,
+                float *__restrict__ S, float *__restrict__ V, int64_t ldv,
+                float *__restrict__ W, int64_t ldw, const int *__restrict__ info) {
+    if ((*info & 0xff) != 0) return;
+    const int c = blockIdx.x;
+    const float sw = (float)S64[c];
+    for (int r = threadIdx.x; r < n; r += 256) {
+        const float vw = (float)V64[r + (int64_t)c * n];
+        V[r + (int64_t)c * ldv] = vw;
+        W[r + (int64_t)c * ldw] = vw / sw;
+    }
+    if (threadIdx.x == 0) S[c] = sw;
+}
+
+__global__ void __launch_bounds__(256) fill_zero_kernel(double *__restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        p[i] = 0.0;
+}
+
+template <class P>
+hipError_t refine_queue(P probs, int count, int max_n, bool f32, hipStream_t st) {
+    const int nt = (max_n + TB - 1) / TB;
+    const unsigned nn_blocks = (unsigned)(((size_t)max_n * max_n + 255) / 256);
+    hipLaunchKernelGGL(ref_init_kernel<P>, dim3(nn_blocks, (unsigned)count), dim3(256), 0, st,
+                       probs);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    for (int it = 0; it < RK; ++it) {
+        hipLaunchKernelGGL((ref_gemm_kernel<0, P>), dim3(nt, nt, count), dim3(256), 0, st, probs,
+                           it);
+        hipLaunchKernelGGL((ref_gemm_kernel<1, P>), dim3(nt, 2 * nt, count), dim3(256), 0, st,
+                           probs, it);
+        hipLaunchKernelGGL(ref_angles_kernel<P>, dim3((unsigned)count), dim3(FT), 0, st, probs, it);
+        hipLaunchKernelGGL((ref_gemm_kernel<2, P>), dim3(nt, nt, count), dim3(256), 0, st, probs,
+                           it);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
+    if (f32)
+        hipLaunchKernelGGL((ref_final_kernel<float, P>), dim3((unsigned)count), dim3(FT), 0, st,
+                           probs);
+    else
+        hipLaunchKernelGGL((ref_final_kernel<double, P>), dim3((unsigned)count), dim3(FT), 0, st,
+                           probs);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t refine_work_bytes(int64_t n) {
+    return (n < 1 || n > GSVD_WIDE_MAX_N) ? 0 : ref_bytes_of((int)n);
+}
+
+hipError_t refine_launch(int working, int64_t n, const double *Mhi, const double *Mlo,
+                         int64_t ldm, const double *X0, int64_t ldx0, void *S, void *V,
+                         int64_t ldv, void *W, int64_t ldw, int *info, void *work,
+                         hipStream_t st) {
+    if (n < 1 || n > GSVD_WIDE_MAX_N || work == nullptr || X0 == nullptr || ldx0 < n ||
+        ldm < n || ldv < n || ldw < n)
+        return hipErrorInvalidValue;
+    OneRef pr;
+    pr.p = RefProb{Mhi, Mlo, ldm, X0, ldx0, S, V, W, ldv, ldw, info, (double *)work, (int)n};
+    return refine_queue(pr, 1, (int)n, working == GSVD_F32, st);
+}
+
+hipError_t refine_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st) {
+    if (batch < 1 || max_n < 1 || max_n > GSVD_WIDE_MAX_N) return hipErrorInvalidValue;
+    return refine_queue(TabRef{tab}, batch, max_n, false, st);
+}
+
+hipError_t assump_launch(int working, int64_t n, const double *Mhi, int64_t ldm, const void *W,
+                         int64_t ldw, int *info, double eps_m, hipStream_t st) {
+    if (n < 1 || ldm < n || ldw < n) return hipErrorInvalidValue;
+    OneAssump a;
+    a.p = AssumpProb{Mhi, ldm, W, ldw, info, (int)n};
+    const double u_h = working == GSVD_F64 ? 0x1p-104 : 0x1p-53;
+    const double u_w = working == GSVD_F64 ? 0x1p-53 : 0x1p-24;
+    if (working == GSVD_F64)
+        hipLaunchKernelGGL((assump_kernel<double, OneAssump>), dim3(1), dim3(256), 0, st, a,
+                           eps_m, u_h, u_w);
+    else
+        hipLaunchKernelGGL((assump_kernel<float, OneAssump>), dim3(1), dim3(256), 0, st, a, eps_m,
+                           u_h, u_w);
+    return hipGetLastError();
+}
+
+hipError_t assump_batched_launch(int working, const BatchMat *tab, int batch, double eps_m,
+                                 hipStream_t st) {
+    if (batch < 1) return hipErrorInvalidValue;
+    const double u_h = working == GSVD_F64 ? 0x1p-104 : 0x1p-53;
+    const double u_w = working == GSVD_F64 ? 0x1p-53 : 0x1p-24;
+    if (working == GSVD_F64)
+        hipLaunchKernelGGL((assump_kernel<double, TabAssump>), dim3((unsigned)batch), dim3(256), 0,
+                           st, TabAssump{tab}, eps_m, u_h, u_w);
+    else
+        hipLaunchKernelGGL((assump_kernel<float, TabAssump>), dim3((unsigned)batch), dim3(256), 0,
+                           st, TabAssump{tab}, eps_m, u_h, u_w);
+    return hipGetLastError();
+}
+
+hipError_t fill_zero_launch(double *p, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const size_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256),
+                       0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t cast_eig_f32_launch(int64_t n, const double *S64, const double *V64, void *S, void *V,
+                               int64_t ldv, void *W, int64_t ldw, const int *info,
+                               hipStream_t st) {
+    if (n < 1 || ldv < n || ldw < n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cast_eig_kernel, dim3((unsigned)n), dim3(256), 0, st, (int)n, S64, V64,
+                       (float *)S, (float *)V, ldv, (float *)W, ldw, info);
+    return hipGetLastError();
+}
+
+}  // namespace gsvd

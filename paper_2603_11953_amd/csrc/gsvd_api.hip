@@ -83,6 +83,9 @@ const char *gsvd_status_string(int code) {
         case GSVD_INFO_NOT_SPD: return "info 1: Gram matrix not positive definite (A not of full column rank at the Gram precision)";
         case GSVD_INFO_NO_CONVERGE: return "info 2: Jacobi iteration did not converge within max_sweeps";
         case GSVD_INFO_NONFINITE: return "info 3: input holds NaN or Inf";
+        case GSVD_INFO_WARN_ASSUMPTION: return "info 256 (warning): the assumption eps_1 <= 1/2 of Theorem 1 could not be verified";
+        case GSVD_INFO_WARN_REFINE: return "info 512 (warning): the double-double Jacobi stage left near-multiple eigenvalue pairs unrotated or did not reach its threshold";
+        case GSVD_INFO_WARN_ASSUMPTION | GSVD_INFO_WARN_REFINE: return "info 768 (warnings 256 and 512)";
         case GSVD_ERR_HIP: return "HIP launch or runtime error";
         case GSVD_ERR_UNSUPPORTED: return "option combination not implemented";
         default: break;
@@ -174,7 +177,8 @@ int gsvd_eig(int64_t n, const double *dMhi, const double *dMlo, int64_t ldm, voi
     if (need > 0 && (work == nullptr || !aligned(work, kAlign))) return -11;
     if (work_bytes < need) return -12;
     if (int e = check_eig_supported(o, n)) return e;
-    hipError_t err = eig_any(o, n, dMhi, dMlo, ldm, dS, dV, ldv, dW, ldw, dInfo, work,
+    const double u_h = o->working == GSVD_F64 ? 0x1p-104 : 0x1p-53;
+    hipError_t err = eig_any(o, n, dMhi, dMlo, ldm, dS, dV, ldv, dW, ldw, dInfo, work, u_h,
                              (hipStream_t)stream);
     return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
 }
@@ -227,7 +231,8 @@ int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void 
     void *W = base + L.w;
     hipError_t err = gram_any(o, m, n, dA, lda, Mhi, Mlo, n, base + L.part, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
-    err = eig_any(o, n, Mhi, Mlo, n, dS, dV, ldv, W, n, dInfo, base + L.eigw, st);
+    err = eig_any(o, n, Mhi, Mlo, n, dS, dV, ldv, W, n, dInfo, base + L.eigw, gram_eps_of(o, n),
+                  st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (want_u) {
         err = urecover_any(o, m, n, dA, lda, W, n, dU, ldu, st);

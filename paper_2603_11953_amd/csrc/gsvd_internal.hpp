@@ -20,6 +20,7 @@ struct BatchMat {
     void *W;                 // fl(V Sigma^-1), n x n, ld = n, working precision
     double *Mhi, *Mlo;       // Gram planes, n x n, ld = n
     double *part;            // Gram partial sums of the slabs
+    double *rw;              // scratch of the double-double Jacobi stage (FP64 working)
     int *info;
     int64_t m, lda, ldu, rows_per_split;
     int n, ldv, nsplit, pad;
@@ -165,6 +166,31 @@ hipError_t eig_jacobi2_launch(int working, int64_t n, const double *Mhi, int64_t
 // partial-sum area, which always holds at least n^2 doubles.
 hipError_t eig_jacobi2_batched_launch(int working, const BatchMat *tab, const int *order, int batch,
                                       int max_n, double tol, int max_sweeps, hipStream_t st);
+
+// Double-double two-sided Jacobi stage on the Gram matrix preconditioned by
+// Algorithm 2's eigenvectors (eig_refine.hip).  X0 (FP64, ld ldx0) is
+// Algorithm 2's V; the outputs S, V, W (working precision) may be the buffers X0
+// was read from.  Skipped when *info is non-zero on entry.
+size_t refine_work_bytes(int64_t n);
+hipError_t refine_launch(int working, int64_t n, const double *Mhi, const double *Mlo,
+                         int64_t ldm, const double *X0, int64_t ldx0, void *S, void *V,
+                         int64_t ldv, void *W, int64_t ldw, int *info, void *work,
+                         hipStream_t st);
+// Batched, FP64 working: each problem's X0 is its V, its scratch BatchMat::rw.
+hipError_t refine_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st);
+// The assumption check of Theorem 1 (GSVD_INFO_WARN_ASSUMPTION) after any
+// eigensolver: reads diag(M_h), W and info.
+hipError_t assump_launch(int working, int64_t n, const double *Mhi, int64_t ldm, const void *W,
+                         int64_t ldw, int *info, double eps_m, hipStream_t st);
+hipError_t assump_batched_launch(int working, const BatchMat *tab, int batch, double eps_m,
+                                 hipStream_t st);
+// zeros into n doubles (a kernel, so a captured graph holds no memset node)
+hipError_t fill_zero_launch(double *p, size_t n, hipStream_t st);
+// FP32 working with an FP64 eigensolver: S, V rounded, W = fl(V Sigma^-1)
+// (V64 has leading dimension n).
+hipError_t cast_eig_f32_launch(int64_t n, const double *S64, const double *V64, void *S, void *V,
+                               int64_t ldv, void *W, int64_t ldw, const int *info,
+                               hipStream_t st);
 
 // U = A W (urecover.hip).
 hipError_t urecover_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,

@@ -20,4 +20,11 @@ int tune_slices(int working, int64_t n) {
     return working == GSVD_F64 ? 10 : 6;
 }
 
+double tune_eps(int working, int64_t n, int S) {
+    if (S >= 1 && S <= 12)
+        for (const TuneEps &r : kTuneEps)
+            if (r.working == working && n <= r.n_max && r.eps[S - 1] > 0.0) return r.eps[S - 1];
+    return __builtin_ldexp(1.0, 12 - 8 * S);
+}
+
 }  // namespace gsvd

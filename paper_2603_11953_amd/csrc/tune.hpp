@@ -21,8 +21,19 @@ struct TuneSlices {
     int slices;        // split Gram slice count
 };
 
+struct TuneEps {
+    int working;
+    int n_max;
+    double eps[12];    // measured Gram error of the split form with S = 1 .. 12 slices,
+                       // max |dM_ij| / sqrt(M_ii M_jj) (0: not measured)
+};
+
 // 0 when no row matches: the plan then uses its own default slab count
 int64_t tune_slab_rows(int working, int gram, int64_t n, int64_t m, bool batched);
 int tune_slices(int working, int64_t n);
+// the split Gram's error for S slices (scaled as above): the table's measurement,
+// else the a-priori 2^(12 - 8 S) (a digit pair's dropped remainder, 2^(-8 S) of
+// the slab's column scale 2^E <= 64 max|a|, summed over a slab)
+double tune_eps(int working, int64_t n, int S);
 
 }  // namespace gsvd

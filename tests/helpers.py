@@ -52,8 +52,18 @@ def orth_tol_alg2(n: int, u: float, kb: float) -> float:
     return 50.0 * n * u * max(1.0, kb)
 
 
-def check_thin(A, S, V, Uo, o: ref.OracleSVD, rows=None, label=""):
-    """The paper's three measures for a GPU result (S, V, U as numpy arrays)."""
+def info_ok(info) -> bool:
+    """No failure code: the low byte is 0 (bits 256 and 512 are warnings)."""
+    return (int(info) & 0xFF) == 0
+
+
+def check_thin(A, S, V, Uo, o: ref.OracleSVD, rows=None, label="", alg2=False):
+    """The paper's three measures for a GPU result (S, V, U as numpy arrays).
+
+    ||U^T U - I||_F is held to the kappa(B)-free 50 n u -- the bound of the two-sided
+    Jacobi on M_h at u_h (Remark 1), the library default -- and reported against
+    50 n u kappa(B) beside it.  ``alg2``: the result came from Algorithm 2 alone, whose
+    bound (the remark after Lemma 1) carries kappa(B)."""
     n = A.shape[1]
     u = u_of(A)
     err = ref.sigma_rel_err(S.astype(np.float64), o)
@@ -66,7 +76,9 @@ def check_thin(A, S, V, Uo, o: ref.OracleSVD, rows=None, label=""):
     if Uo is not None:
         report["u_orth"] = ref.orth(Uo)
         report["u_orth_meets_50nu"] = report["u_orth"] <= orth_tol(n, u)
-        assert report["u_orth"] <= orth_tol_alg2(n, u, o.kappa_b), (label, report)
+        report["u_orth_tol_50nu_kappab"] = orth_tol_alg2(n, u, o.kappa_b)
+        bound = orth_tol_alg2(n, u, o.kappa_b) if alg2 else orth_tol(n, u)
+        assert report["u_orth"] <= bound, (label, report)
         report["resid"] = ref.resid(A, Uo, S, V, rows=rows)
         assert report["resid"] <= orth_tol(n, u), (label, report)
     return report

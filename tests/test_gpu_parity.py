@@ -9,7 +9,7 @@ import pytest
 
 from gen import matrices as g
 from oracle import ref
-from tests.helpers import U_DD, check_thin, say, sigma_tol, to_dev, to_np, u_of
+from tests.helpers import U_DD, check_thin, info_ok, say, sigma_tol, to_dev, to_np, u_of
 
 pytestmark = pytest.mark.gpu
 
@@ -79,7 +79,14 @@ EIG_CASES = [(1, "f64", "alg2"), (2, "f64", "alg2"), (7, "f64", "alg2"), (20, "f
              (128, "f32", "alg2"),
              (1, "f32", "jacobi2"), (2, "f32", "jacobi2"), (7, "f32", "jacobi2"),
              (20, "f32", "jacobi2"), (64, "f32", "jacobi2"), (96, "f32", "jacobi2"),
-             (97, "f32", "jacobi2"), (128, "f32", "jacobi2")]
+             (97, "f32", "jacobi2"), (128, "f32", "jacobi2"),
+             # FP64 working: the double-double Jacobi stage on Algorithm 2's basis
+             (1, "f64", "jacobi2"), (2, "f64", "jacobi2"), (7, "f64", "jacobi2"),
+             (20, "f64", "jacobi2"), (64, "f64", "jacobi2"), (65, "f64", "jacobi2"),
+             (96, "f64", "jacobi2"), (97, "f64", "jacobi2"), (160, "f64", "jacobi2"),
+             # FP32 working beyond one workgroup: Algorithm 2 over many workgroups
+             (129, "f32", "alg2"), (200, "f32", "alg2"), (129, "f32", "jacobi2"),
+             (200, "f32", "jacobi2")]
 
 
 @pytest.mark.parametrize("n,dt,mode", EIG_CASES)
@@ -109,6 +116,11 @@ def test_eig_parity(n, dt, mode):
     assert np.linalg.norm(V64.T @ V64 - np.eye(n)) <= 50 * n * u
     # eigenvectors: same sign rule, so compare directly (sigma of mode 3 well separated)
     assert np.abs(V64 - o.V_hi).max() <= 1e3 * n * u * o.kappa_b
+    if mode == "jacobi2":
+        # Remark 1: with the eigensolver at u_h, sigma is O(u) and V is the rounding
+        # of the u_h eigenvectors, whatever kappa(B)
+        assert err.max() <= 8 * u, err.max()
+        assert np.abs(V64 - o.V_hi).max() <= 50 * n * u, np.abs(V64 - o.V_hi).max()
     # sign rule: largest-magnitude entry of each column positive
     idx = np.argmax(np.abs(V64), axis=0)
     assert np.all(V64[idx, np.arange(n)] > 0)
@@ -167,8 +179,7 @@ def test_thin_end_to_end(spec):
     S, V, Uo, info = _thin(A)
     assert info == 0
     rep = check_thin(A, S, V, Uo, o, label=str(spec))
-    if o.kappa_b <= 100.5:  # Remark 2's kappa(B) term is then below the kappa(B)-free target
-        assert rep["u_orth_meets_50nu"], rep
+    assert rep["u_orth_meets_50nu"], rep
     rows = np.unique(np.r_[0, spec.m - 1, np.random.default_rng(0).integers(0, spec.m, 300)])
     Uh, Ul = ref.u_rows_dd(A, o.V_hi, o.V_lo, o.sigma_hi, o.sigma_lo, rows=rows)
     # each column of U has unit norm; its error is bounded like that of V (Thm. 1)
@@ -279,7 +290,9 @@ def test_two_sided_jacobi_is_O_u_while_alg2_tracks_kappa_b():
         for mode, em in (("jacobi2", gs.GSVD_EIG_JACOBI2), ("alg2", gs.GSVD_EIG_CHOL_JACOBI1)):
             say("accuracy mode", mode, seed)
             S, V, Uo, info = _thin(A, eig=em)
-            assert info == 0
+            # Theorem 1's assumption eps_1 <= 1/2 is not met by FP32 at kappa(B) = 1e4:
+            # the warning bit may be set, the results are complete
+            assert info_ok(info), info
             errs[mode].append(float(ref.sigma_rel_err(S.astype(np.float64), o).max()))
     u = 2.0 ** -24
     assert max(errs["jacobi2"]) <= 8 * u, errs            # O(u): the cast of sigma dominates

@@ -161,6 +161,53 @@ def test_n2_closed_form():
         assert brute.rel_err_mp(o.sigma_hi[i], o.sigma_lo[i], s[i]) <= 1e-29
 
 
+def _sign_rule(V):
+    """The output sign convention, stated plainly: flip each column so that its entry of
+    largest magnitude is positive; among entries of equal magnitude the lowest row index
+    counts.  (Written here, independently of the oracle's code.)"""
+    V = V.copy()
+    for c in range(V.shape[1]):
+        mags = [abs(x) for x in V[:, c]]
+        best = max(mags)
+        r = mags.index(best)  # first (lowest) index of the largest magnitude
+        if V[r, c] < 0:
+            V[:, c] = -V[:, c]
+    return V
+
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (3, 2), (5, 3), (8, 4)])
+def test_sign_rule_against_brute_force(n, seed):
+    """V of the oracle, compared entry by entry with NO sign alignment, against the
+    60-digit eigenvectors of the exact Gram with the sign convention applied in the test:
+    a wrong convention (smallest entry positive, first entry positive, highest index on
+    ties) or a column permutation fails."""
+    rng = np.random.default_rng(300 + seed)
+    A = np.asfortranarray(rng.standard_normal((40, n)) * np.logspace(0, -3, n)[None, :])
+    o = ref.svd(A)
+    sig, Vb = brute.mp_eigvecs(A)
+    with mpmath.workdps(60):  # (mpmath rounds even a negation to the working precision)
+        Vb = _sign_rule(Vb)
+        for c in range(n):
+            mags = sorted((abs(x) for x in Vb[:, c]), reverse=True)
+            assert mags[0] - mags[1] > mpmath.mpf(10) ** -6  # no near-tie: the rule decides
+            for r in range(n):
+                d = mpmath.mpf(o.V_hi[r, c]) + mpmath.mpf(o.V_lo[r, c]) - Vb[r, c]
+                assert abs(d) <= mpmath.mpf(10) ** -25, (r, c, float(d))
+
+
+def test_sign_rule_exact_ties_take_the_lowest_index():
+    """A = [[1, 0], [1, 1], [0, 1]]: A^T A = [[2, 1], [1, 2]], eigenvectors (1, 1)/sqrt(2)
+    (sigma = sqrt(3)) and (1, -1)/sqrt(2) (sigma = 1).  Both columns tie in magnitude
+    exactly, so the lowest row index carries the positive sign: V = [[c, c], [c, -c]]."""
+    A = np.asfortranarray(np.array([[1.0, 0.0], [1.0, 1.0], [0.0, 1.0]]))
+    o = ref.svd(A)
+    V = o.V_hi + o.V_lo
+    c = 2.0 ** -0.5
+    assert np.abs(V - np.array([[c, c], [c, -c]])).max() <= 1e-15
+    assert V[0, 0] > 0 and V[0, 1] > 0 and V[1, 1] < 0
+    assert abs(o.V_hi[0, 1]) == abs(o.V_hi[1, 1])  # the tie is exact in the oracle
+
+
 def test_orthogonal_columns():
     """kappa(B) = 1: sigma are the column norms, V a permutation."""
     scales = np.array([3.0, -1e-6, 0.25, 7e5, 1e-12, -2.5, 1.0, 9e-3])
