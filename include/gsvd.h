@@ -91,15 +91,14 @@ enum {
 #define GSVD_INFO_NONFINITE 3     /* A (hence M_h) holds a NaN or Inf */
 /* Warning bits, or-ed into an info that is otherwise 0; the outputs are
    complete.  (info & 0xff) != 0 means failure. */
-#define GSVD_INFO_WARN_ASSUMPTION 256 /* eq. (thm:assump), eps_1 <= 1/2, cannot be
-                                     verified: with kappa(B) bounded by
-                                     sqrt(n) ||D W||_F (D = diag(sqrt(m_jj)),
-                                     W = V Sigma^-1) and unit constants,
-                                     eps_1 = 2 (n^2 eps_M + n u_h) kappa^2
-                                           + 4 n sqrt(n) (1 + n) u kappa > 1/2,
-                                     where eps_M is u_h for the plain Gram and
-                                     2^(7 - 8 n_slices) for the split Gram; the
-                                     error bounds of Theorem 1 then do not apply */
+#define GSVD_INFO_WARN_ASSUMPTION 256 /* the accuracy assumptions of Theorem 1 cannot be
+                                     verified.  With kappa(B) bounded by sqrt(n) ||D W||_F
+                                     (D = diag(sqrt(m_jj)), W = V Sigma^-1), the bit is set
+                                     when 2 (n^2 eps_M + n u_h) kappa^2 > 1/2 (the u_h terms
+                                     of eq. (thm:assump); eps_M = u_h for the plain Gram,
+                                     the tuning table's measured error for the split Gram)
+                                     or, with Algorithm 2, when n u kappa > 1/2 (its
+                                     O(u) kappa(B) condition) */
 #define GSVD_INFO_WARN_REFINE 512 /* the double-double Jacobi stage of JACOBI2 (FP64
                                      working, or n > 128) left pairs of eigenvalues that
                                      agree to within their coupling unrotated, or its

@@ -255,7 +255,8 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
                          jacobi_tol_of(o, n), sweeps, st);
     }
     if (err != hipSuccess) return err;
-    return assump_launch(o->working, n, Mhi, ldm, W, ldw, info, eps_m, st);
+    return assump_launch(o->working, n, Mhi, ldm, W, ldw, info, eps_m,
+                         eig_mode_of(o) == GSVD_EIG_CHOL_JACOBI1, st);
 }
 
 inline hipError_t urecover_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A,

@@ -262,7 +262,8 @@ int gsvd_thin_batched(int batch, const int64_t *hM, const int64_t *hN, const voi
                                        sweeps_of(o), st);
     }
     if (err == hipSuccess)
-        err = assump_batched_launch(o->working, tab, batch, gram_eps_of(o, P.max_n), st);
+        err = assump_batched_launch(o->working, tab, batch, gram_eps_of(o, P.max_n),
+                                    eig_mode_of(o) == GSVD_EIG_CHOL_JACOBI1, P.max_n, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (want_u) {
         for (const UClass &c : P.u) {

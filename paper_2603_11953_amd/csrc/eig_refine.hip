@@ -445,13 +445,16 @@ struct TabAssump {
 
 // kappa(B) <= ||B||_F ||B^+||_F = sqrt(n) ||D W||_F (B = A D^-1 has unit columns;
 // A = U Sigma V^T gives B^+ = D V Sigma^-1 U^T, so ||B^+||_F = ||D V Sigma^-1||_F,
-// with D = diag(sqrt(m_jj))).  With that kappa, eq. (thm:assump) with unit
-// constants: eps_1 = 2 (n^2 eps_m + n u_h) kappa^2 + 4 n sqrt(n) (1 + n) u kappa;
-// eps_1 > 1/2 sets GSVD_INFO_WARN_ASSUMPTION (the bounds of Theorem 1 are then
+// with D = diag(sqrt(m_jj))).  With that kappa the conditions of Remark 1 (the
+// u_h Jacobi) and of the remark after Lemma 1 (Algorithm 2) are checked with the
+// constants of eq. (thm:assump) where it fixes them:
+//   2 (n^2 eps_m + n u_h) kappa^2 <= 1/2        (the Gram and eigensolver at u_h)
+//   c_w u kappa <= 1/2, c_w = n for Algorithm 2 (its O(u) kappa(B) term), else 0;
+// a failed condition sets GSVD_INFO_WARN_ASSUMPTION (Theorem 1's bounds are then
 // not guaranteed).
 template <typename TW, class P>
 __global__ void __launch_bounds__(256)
-assump_kernel(P probs, double eps_m, double u_h, double u_w) {
+assump_kernel(P probs, double eps_m, double u_h, double u_w, double c_w) {
     const AssumpProb p = probs.get(blockIdx.x);
     const int n = p.n;
     const TW *W = reinterpret_cast<const TW *>(p.W);
@@ -471,9 +474,9 @@ assump_kernel(P probs, double eps_m, double u_h, double u_w) {
     if ((info & 0xff) != 0) return;
     const double dn = (double)n;
     const double kap = __builtin_sqrt(dn * (((red[0] + red[1]) + red[2]) + red[3]));
-    const double eps1 = 2.0 * (dn * dn * eps_m + dn * u_h) * kap * kap +
-                        4.0 * dn * __builtin_sqrt(dn) * (1.0 + dn) * u_w * kap;
-    if (!(eps1 <= 0.5)) *p.info = info | GSVD_INFO_WARN_ASSUMPTION;
+    const bool hi_ok = 2.0 * (dn * dn * eps_m + dn * u_h) * kap * kap <= 0.5;
+    const bool w_ok = c_w * u_w * kap <= 0.5;
+    if (!(hi_ok && w_ok)) *p.info = info | GSVD_INFO_WARN_ASSUMPTION;
 }
 
 // FP64 eigensolver outputs cast to FP32 working precision (Alg. 1 steps 4-5):
@@ -549,32 +552,35 @@ hipError_t refine_batched_launch(const BatchMat *tab, int batch, int max_n, hipS
 }
 
 hipError_t assump_launch(int working, int64_t n, const double *Mhi, int64_t ldm, const void *W,
-                         int64_t ldw, int *info, double eps_m, hipStream_t st) {
+                         int64_t ldw, int *info, double eps_m, bool alg2, hipStream_t st) {
     if (n < 1 || ldm < n || ldw < n) return hipErrorInvalidValue;
     OneAssump a;
     a.p = AssumpProb{Mhi, ldm, W, ldw, info, (int)n};
     const double u_h = working == GSVD_F64 ? 0x1p-104 : 0x1p-53;
     const double u_w = working == GSVD_F64 ? 0x1p-53 : 0x1p-24;
+    const double c_w = alg2 ? (double)n : 0.0;
     if (working == GSVD_F64)
         hipLaunchKernelGGL((assump_kernel<double, OneAssump>), dim3(1), dim3(256), 0, st, a,
-                           eps_m, u_h, u_w);
+                           eps_m, u_h, u_w, c_w);
     else
         hipLaunchKernelGGL((assump_kernel<float, OneAssump>), dim3(1), dim3(256), 0, st, a, eps_m,
-                           u_h, u_w);
+                           u_h, u_w, c_w);
     return hipGetLastError();
 }
 
 hipError_t assump_batched_launch(int working, const BatchMat *tab, int batch, double eps_m,
-                                 hipStream_t st) {
+                                 bool alg2, int max_n, hipStream_t st) {
     if (batch < 1) return hipErrorInvalidValue;
     const double u_h = working == GSVD_F64 ? 0x1p-104 : 0x1p-53;
     const double u_w = working == GSVD_F64 ? 0x1p-53 : 0x1p-24;
+    // the Algorithm 2 condition with the largest n of the batch (conservative)
+    const double c_w = alg2 ? (double)max_n : 0.0;
     if (working == GSVD_F64)
         hipLaunchKernelGGL((assump_kernel<double, TabAssump>), dim3((unsigned)batch), dim3(256), 0,
-                           st, TabAssump{tab}, eps_m, u_h, u_w);
+                           st, TabAssump{tab}, eps_m, u_h, u_w, c_w);
     else
         hipLaunchKernelGGL((assump_kernel<float, TabAssump>), dim3((unsigned)batch), dim3(256), 0,
-                           st, TabAssump{tab}, eps_m, u_h, u_w);
+                           st, TabAssump{tab}, eps_m, u_h, u_w, c_w);
     return hipGetLastError();
 }
 

