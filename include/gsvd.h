@@ -41,7 +41,11 @@ enum { GSVD_F32 = 0, GSVD_F64 = 1 };
 
 /* how the Gram M_h = A^T A is formed */
 enum {
-    GSVD_GRAM_AUTO = 0,   /* library choice (currently PLAIN) */
+    GSVD_GRAM_AUTO = 0,   /* SPLIT when a slice count meets the accuracy target (see
+                             target_rel_err) and the tuning table's times put it ahead
+                             of PLAIN; otherwise PLAIN.  Without table rows: SPLIT for
+                             FP64 A, PLAIN for FP32 A; the batched call: SPLIT for FP64,
+                             PLAIN for FP32 */
     GSVD_GRAM_PLAIN = 1,  /* FP32 A: exact FP64 products, FP64 sums; FP64 A: double-double */
     GSVD_GRAM_SPLIT = 2   /* operand splitting: per slab of rows and column, a power-of-two
                              exponent E above the column's largest entry (raised, with two
@@ -92,13 +96,14 @@ enum {
 /* Warning bits, or-ed into an info that is otherwise 0; the outputs are
    complete.  (info & 0xff) != 0 means failure. */
 #define GSVD_INFO_WARN_ASSUMPTION 256 /* the accuracy assumptions of Theorem 1 cannot be
-                                     verified.  With kappa(B) bounded by sqrt(n) ||D W||_F
-                                     (D = diag(sqrt(m_jj)), W = V Sigma^-1), the bit is set
-                                     when 2 (n^2 eps_M + n u_h) kappa^2 > 1/2 (the u_h terms
-                                     of eq. (thm:assump); eps_M = u_h for the plain Gram,
-                                     the tuning table's measured error for the split Gram)
-                                     or, with Algorithm 2, when n u kappa > 1/2 (its
-                                     O(u) kappa(B) condition) */
+                                     verified.  kappa(B)^2 is bounded by g ||D W||_F^2 (g the
+                                     Gershgorin bound of D^-1 M_h D^-1, D = diag(sqrt(m_jj)),
+                                     W = V Sigma^-1); the bit is set when
+                                     2 (e + n u_h) kappa^2 > 1/2 (the u_h terms of
+                                     eq. (thm:assump); e = n^2 u_h for the plain Gram,
+                                     n eps_S for the split Gram with eps_S the tuning
+                                     table's measured error) or, with Algorithm 2, when
+                                     n u kappa > 1/2 (its O(u) kappa(B) condition) */
 #define GSVD_INFO_WARN_REFINE 512 /* the double-double Jacobi stage of JACOBI2 (FP64
                                      working, or n > 128) left pairs of eigenvalues that
                                      agree to within their coupling unrotated, or its
@@ -121,8 +126,11 @@ typedef struct {
     int gram;           /* GSVD_GRAM_* */
     int eig;            /* GSVD_EIG_* */
     int n_slices;       /* split Gram only: 1..GSVD_MAX_SLICES (FP64 A) or
-                           1..GSVD_MAX_SLICES_F32 (FP32 A); 0 = the tuning table's
-                           count (the smallest meeting the accuracy budget) */
+                           1..GSVD_MAX_SLICES_F32 (FP32 A); 0 = the smallest count whose
+                           measured Gram error eps(S) (tuning table) meets the target:
+                           n eps kappa_b^2 / 2 <= target_rel_err / 16, since a Gram error
+                           |dM_ij| <= eps sqrt(m_ii m_jj) moves each sigma by a relative
+                           n eps kappa(B)^2 / 2 at most; the largest count if none does */
     double jacobi_tol;  /* rotation threshold: a pair p, q is rotated when
                            |g_pq| > tol * sqrt(g_pp g_qq); 0 = the eigensolver's default */
     int max_sweeps;     /* 0 = 30 */
@@ -132,6 +140,11 @@ typedef struct {
                            back to about 512 (plain) / 1024 (split) slabs per matrix.
                            n > 128, split form: a cap on the rows per pass of the int8
                            digit planes (multiples of 8192; 0 = about 1 GiB of planes) */
+    double target_rel_err; /* requested bound on max_i |s_i - sigma_i| / sigma_i that the
+                           slice count and the AUTO Gram form are planned for; 0 = the
+                           tolerance 50 n u kappa_b.  Must be >= 0 */
+    double kappa_b;     /* the kappa(B) of A = B D (B with unit columns) the plan assumes;
+                           0 = 1e3 (FP64 working) or 1e2 (FP32 working).  Must be >= 0 */
 } gsvd_opts;
 
 /* Fill *o with the defaults for the given working precision (WANT_U set). */

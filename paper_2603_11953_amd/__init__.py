@@ -46,6 +46,8 @@ class GsvdOpts(ctypes.Structure):
         ("max_sweeps", ctypes.c_int),
         ("flags", ctypes.c_uint),
         ("slab_rows", ctypes.c_int64),
+        ("target_rel_err", ctypes.c_double),
+        ("kappa_b", ctypes.c_double),
     ]
 
 
@@ -119,7 +121,8 @@ def gsvd_status_string(code: int) -> str:
 def gram_config(m: int, n: int, working: int = GSVD_F64, gram: int = GSVD_GRAM_AUTO,
                 **kw) -> dict:
     """The Gram launch shape the library resolves for (m, n) and these options:
-    slab height, slab count and (split form) int8 slice count."""
+    slab height, slab count and (split form) int8 slice count; n_slices 0 means the
+    plain form (also what GSVD_GRAM_AUTO resolved to)."""
     o = opts(working, gram, **kw)
     rows, slabs, sl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
     rc = lib.gsvd_gram_config(m, n, ctypes.byref(o), ctypes.addressof(rows),
@@ -130,13 +133,15 @@ def gram_config(m: int, n: int, working: int = GSVD_F64, gram: int = GSVD_GRAM_A
 
 def opts(working: int, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, *,
          want_u: bool = True, jacobi_tol: float = 0.0, max_sweeps: int = 0,
-         n_slices: int = 0, slab_rows: int = 0) -> GsvdOpts:
+         n_slices: int = 0, slab_rows: int = 0, target_rel_err: float = 0.0,
+         kappa_b: float = 0.0) -> GsvdOpts:
     o = GsvdOpts()
     lib.gsvd_opts_default(ctypes.byref(o), int(working))
     o.gram, o.eig, o.n_slices = int(gram), int(eig), int(n_slices)
     o.jacobi_tol, o.max_sweeps = float(jacobi_tol), int(max_sweeps)
     o.flags = GSVD_WANT_U if want_u else 0
     o.slab_rows = int(slab_rows)
+    o.target_rel_err, o.kappa_b = float(target_rel_err), float(kappa_b)
     return o
 
 
@@ -194,7 +199,7 @@ def workspace(nbytes: int, device):
 
 def thin(A, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, want_u: bool = True,
          jacobi_tol: float = 0.0, max_sweeps: int = 0, n_slices: int = 0, slab_rows: int = 0,
-         work=None, stream=None):
+         target_rel_err: float = 0.0, kappa_b: float = 0.0, work=None, stream=None):
     """Thin SVD of a column-major CUDA tensor A (m x n).  Returns (S, V, U, info) tensors;
     info is a one-element int32 device tensor (check it after synchronising)."""
     torch = _torch()
@@ -202,7 +207,8 @@ def thin(A, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, want_u: boo
     m, n = int(A.shape[0]), int(A.shape[1])
     lda = _ld(A)
     o = opts(w, gram, eig, want_u=want_u, jacobi_tol=jacobi_tol, max_sweeps=max_sweeps,
-             n_slices=n_slices, slab_rows=slab_rows)
+             n_slices=n_slices, slab_rows=slab_rows, target_rel_err=target_rel_err,
+             kappa_b=kappa_b)
     with _on(stream):
         S = torch.empty(n, dtype=A.dtype, device=A.device)
         V = colmajor_empty(n, n, A.dtype, A.device)
@@ -280,7 +286,8 @@ class Batch:
 
     def __init__(self, As, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO,
                  want_u: bool = True, jacobi_tol: float = 0.0, max_sweeps: int = 0,
-                 n_slices: int = 0, slab_rows: int = 0):
+                 n_slices: int = 0, slab_rows: int = 0, target_rel_err: float = 0.0,
+                 kappa_b: float = 0.0):
         torch = _torch()
         if len(As) < 1:
             raise ValueError("empty batch")
@@ -291,7 +298,8 @@ class Batch:
         self.count = len(As)
         self.As = list(As)
         self.o = opts(w, gram, eig, want_u=want_u, jacobi_tol=jacobi_tol,
-                      max_sweeps=max_sweeps, n_slices=n_slices, slab_rows=slab_rows)
+                      max_sweeps=max_sweeps, n_slices=n_slices, slab_rows=slab_rows,
+                      target_rel_err=target_rel_err, kappa_b=kappa_b)
         i64 = ctypes.c_int64 * self.count
         self.hM = i64(*[int(a.shape[0]) for a in As])
         self.hN = i64(*[int(a.shape[1]) for a in As])

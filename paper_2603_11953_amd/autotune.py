@@ -1,7 +1,7 @@
 """Tune the library's launch shapes and slice counts on the GPU in use.
 
 Writes ``csrc/tune_table.inc`` (the rows behind ``tune_slab_rows`` and
-``tune_slices``); rebuild the library afterwards (``python
+``tune_eps``); rebuild the library afterwards (``python
 paper_2603_11953_amd/build.py``).
 
 Slab height (rows of A per Gram workgroup).  For every working precision, Gram
@@ -12,15 +12,16 @@ slabs) on
 seeded Gaussian inputs (each height over at least 10 ms of work, best of three
 passes that alternate over the ladder), and the fastest height is kept.
 
-Slice count of the split Gram.  A perturbation dM of the Gram with
-|dM_ij| <= eps sqrt(M_ii M_jj) moves the eigenvalues of the column-scaled Gram
-H = D^-1 M D^-1 by at most n eps, i.e. each sigma_i by a relative
-n eps kappa(B)^2 / 2 at most; the sigma tolerance 50 n u kappa(B) therefore asks
-for eps <= 100 u / kappa(B).  For each working precision and n bucket the split
-Gram of seeded A = B D test matrices (the paper's recipe, kappa(B) = kappa_ref,
-strongly graded D) is compared with the plain higher-precision Gram of the same
-matrices; the smallest S whose measured eps (worst over the seeds) stays a
-factor 16 below the budget 50 u / kappa_ref is kept.
+Error of the split Gram per slice count.  For each working precision and n
+bucket the split Gram of seeded A = B D test matrices (the paper's recipe,
+kappa(B) = kappa_ref, strongly graded D) is compared with the plain
+higher-precision Gram of the same matrices, for every slice count S; the worst
+scaled error eps(S) = max |dM_ij| / sqrt(M_ii M_jj) over the seeds goes into the
+table.  The library picks S per call from it: a perturbation with
+|dM_ij| <= eps sqrt(M_ii M_jj) moves each sigma_i by a relative
+n eps kappa(B)^2 / 2 at most, so a requested sigma accuracy (default
+50 n u kappa(B)) is met, with a factor 16 of margin, by the smallest S with
+eps(S) <= target / (8 n kappa(B)^2).
 
 Run on the GPU:  python -m paper_2603_11953_amd.autotune [--quick] [--write]
 """
@@ -42,6 +43,7 @@ N_BUCKETS = (16, 32, 64, 96, 128)
 M_BUCKETS = ((20_000, 50_000), (160_000, 500_000), (1_000_000, 2_000_000), (4_000_000, 2**62))
 SINGLE_LADDER = (0, 256, 512, 1024, 2048, 4096, 8192)
 BATCH_LADDER = (512, 1024, 2048, 4096, 8192, 16384)
+SLICE_N_BUCKETS = N_BUCKETS + (256, 512)  # the wide split form too
 KAPPA_REF = {1: 1e3, 0: 1e2}  # FP64 working: kappa(B) up to 1e3; FP32 working: 1e2
 
 
@@ -118,8 +120,11 @@ def tune_single(gs, quick):
                         fns[slab] = _gram_fn(gs, A, Mhi, Mlo, works[-1], o)
                     best = _best(fns, quick)
                     del fns, works
+                    S_used = (gs.gram_config(m, n, working, gram)["n_slices"]
+                              if gram == gs.GSVD_GRAM_SPLIT else 0)
                     rows.append(dict(working=working, gram=gram, batched=0, n_max=n, m_max=m_edge,
-                                     slab_rows=best[0], ms=round(best[1], 4), m_tuned=m))
+                                     slab_rows=best[0], ms=round(best[1], 4), m_tuned=m,
+                                     slices=S_used))
                     print(f"[tune] single w={working} gram={gram} n<={n} m={m}: slab {best[0]} "
                           f"({best[1]:.3f} ms)", flush=True)
                     del A
@@ -143,8 +148,10 @@ def tune_batched(gs, quick):
                            for slab in BATCH_LADDER}
                 best = _best({slab: b.run for slab, b in batches.items()}, quick)
                 del batches
+                S_used = (gs.gram_config(100_000, n, working, gram)["n_slices"]
+                          if gram == gs.GSVD_GRAM_SPLIT else 0)
                 rows.append(dict(working=working, gram=gram, batched=1, n_max=n, m_max=2**62,
-                                 slab_rows=best[0], ms=round(best[1], 4)))
+                                 slab_rows=best[0], ms=round(best[1], 4), slices=S_used))
                 print(f"[tune] batched w={working} gram={gram} n<={n}: slab {best[0]} "
                       f"({best[1]:.3f} ms for {count} problems)", flush=True)
                 del As
@@ -163,7 +170,7 @@ def tune_slices(gs, quick):
         kref = KAPPA_REF[working]
         budget = 50 * u / kref
         smax = 12 if working == 1 else 8
-        for n in N_BUCKETS:
+        for n in (N_BUCKETS[:3] if quick else SLICE_N_BUCKETS):
             worst = np.zeros(smax + 1)
             for seed in range(1 if quick else 3):
                 A = g.make_a(g.MatrixSpec(m=100_000, n=n, kappa_b=kref,
@@ -199,7 +206,17 @@ def tune_slices(gs, quick):
     return rows
 
 
-def render(slab_rows, slice_rows, meta):
+def render_slices(slice_rows):
+    names = {1: "GSVD_F64", 0: "GSVD_F32"}
+    out = ["static const TuneEps kTuneEps[] = {"]
+    for r in slice_rows:
+        eps = ", ".join(f"{e:.3g}" for e in (list(r["eps"]) + [0.0] * 12)[:12])
+        out.append(f"    {{{names[r['working']]}, {r['n_max']}, {{{eps}}}}},")
+    out.append("};")
+    return out
+
+
+def render(slab_rows, slice_rows, meta, slab_text=None):
     # the largest m bucket of each (precision, form, kind, n) also covers every taller matrix
     top = {}
     for r in slab_rows:
@@ -211,19 +228,28 @@ def render(slab_rows, slice_rows, meta):
     names = {1: "GSVD_F64", 0: "GSVD_F32"}
     grams = {1: "GSVD_GRAM_PLAIN", 2: "GSVD_GRAM_SPLIT"}
     out = ["// Generated by paper_2603_11953_amd/autotune.py -- do not edit by hand.",
-           f"// {meta}",
-           "static const TuneSlab kTuneSlab[] = {"]
-    for r in slab_rows:
-        m_max = "INT64_MAX" if r["m_max"] >= 2**62 else str(r["m_max"])
-        note = f"{r['ms']} ms at m = {r['m_tuned']}" if "m_tuned" in r else f"{r['ms']} ms"
-        out.append(f"    {{{names[r['working']]}, {grams[r['gram']]}, {r['batched']}, {r['n_max']}, "
-                   f"{m_max}, {r['slab_rows']}}},  // {note}")
-    out.append("};")
-    out.append("static const TuneSlices kTuneSlices[] = {")
-    for r in slice_rows:
-        out.append(f"    {{{names[r['working']]}, {r['n_max']}, {r['slices']}}},")
-    out.append("};")
+           f"// {meta}"]
+    if slab_text is not None:  # slab heights kept from the previous table
+        out.append(slab_text)
+    else:
+        out.append("static const TuneSlab kTuneSlab[] = {")
+        for r in slab_rows:
+            m_max = "INT64_MAX" if r["m_max"] >= 2**62 else str(r["m_max"])
+            note = f"{r['ms']} ms at m = {r['m_tuned']}" if "m_tuned" in r else f"{r['ms']} ms"
+            out.append(f"    {{{names[r['working']]}, {grams[r['gram']]}, {r['batched']}, "
+                       f"{r['n_max']}, {m_max}, {r['slab_rows']}, {r['ms']}, "
+                       f"{r.get('slices', 0)}}},  // {note}")
+        out.append("};")
+    out += render_slices(slice_rows)
     return "\n".join(out) + "\n"
+
+
+def _slab_block(path):
+    """The kTuneSlab block of an existing table, verbatim."""
+    txt = open(path).read()
+    a = txt.index("static const TuneSlab kTuneSlab[]")
+    b = txt.index("};", a) + 2
+    return txt[a:b]
 
 
 def main():
@@ -232,15 +258,20 @@ def main():
     ap.add_argument("--write", action="store_true", help="write the table (to --out)")
     ap.add_argument("--out", default=TABLE, help="table path (default: the library's csrc)")
     ap.add_argument("--json", default="", help="also dump the measurements to this file")
+    ap.add_argument("--slices-only", action="store_true",
+                    help="measure only the split Gram error per slice count; keep the slab "
+                         "heights of the current table")
     args = ap.parse_args()
     gs = _gs()
     t0 = time.time()
-    slab_rows = tune_single(gs, args.quick) + tune_batched(gs, args.quick)
+    slab_text = _slab_block(TABLE) if args.slices_only else None
+    slab_rows = [] if args.slices_only else tune_single(gs, args.quick) + tune_batched(gs, args.quick)
     slice_rows = tune_slices(gs, args.quick)
     import torch
-    meta = (f"{torch.cuda.get_device_name(0)}; {'quick' if args.quick else 'full'} run, "
+    meta = (f"{torch.cuda.get_device_name(0)}; {'quick' if args.quick else 'full'} run"
+            f"{' (slice counts; slab heights kept)' if args.slices_only else ''}, "
             f"{time.time() - t0:.0f} s")
-    text = render(slab_rows, slice_rows, meta)
+    text = render(slab_rows, slice_rows, meta, slab_text)
     print(text)
     if args.json:
         with open(args.json, "w") as f:

@@ -32,6 +32,7 @@ inline int check_opts(const gsvd_opts *o, int argpos) {
         return -argpos;
     if (o->max_sweeps < 0 || o->jacobi_tol < 0.0 || o->n_slices < 0 || o->slab_rows < 0)
         return -argpos;
+    if (!(o->target_rel_err >= 0.0) || !(o->kappa_b >= 0.0)) return -argpos;  // also NaN
     return 0;
 }
 
@@ -81,10 +82,38 @@ inline int check_gram_supported(const gsvd_opts *o, int64_t n) {
     return check_supported(o);
 }
 
-// slice count of the split Gram: the caller's, else the tuning table's
+// kappa(B) the accuracy plan assumes: the caller's, else 1e3 (FP64) / 1e2 (FP32)
+inline double plan_kappa(const gsvd_opts *o) {
+    return o->kappa_b > 0.0 ? o->kappa_b : (o->working == GSVD_F64 ? 1e3 : 1e2);
+}
+
+// requested bound on max_i |s_i - sigma_i| / sigma_i: the caller's, else the
+// tolerance 50 n u kappa(B) at the planned kappa(B)
+inline double plan_target(const gsvd_opts *o, int64_t n) {
+    if (o->target_rel_err > 0.0) return o->target_rel_err;
+    return 50.0 * (double)n * unit_roundoff(o->working) * plan_kappa(o);
+}
+
+// Smallest slice count whose Gram error meets the target.  A perturbation dM with
+// |dM_ij| <= eps sqrt(M_ii M_jj) moves the eigenvalues of H = D^-1 M D^-1 by at
+// most n eps, hence each sigma_i by a relative n eps kappa(B)^2 / 2 at most
+// (eq. (ATA) and the first-order step of Theorem 1's proof); with a factor 16
+// of margin the target asks for eps <= target / (8 n kappa^2).  eps(S) is the
+// tuning table's measurement.  0: no slice count meets the target.
+inline int slices_for_target(const gsvd_opts *o, int64_t n) {
+    const double k = plan_kappa(o);
+    const double budget = plan_target(o, n) / (8.0 * (double)n * k * k);
+    for (int S = 1; S <= max_slices(o->working); ++S)
+        if (tune_eps(o->working, n, S) <= budget) return S;
+    return 0;
+}
+
+// slice count of the split Gram: the caller's, else the one the target asks for
+// (the largest when none meets it)
 inline int slices_of(const gsvd_opts *o, int64_t n) {
     if (o->n_slices > 0) return o->n_slices;
-    return tune_slices(o->working, n);
+    const int S = slices_for_target(o, n);
+    return S > 0 ? S : max_slices(o->working);
 }
 
 // slab height of the Gram: the caller's, else the tuning table's (0 = the
@@ -125,6 +154,35 @@ inline GramPlan gram_plan_of(const gsvd_opts *o, int64_t m, int64_t n, bool batc
         }
     }
     return p;
+}
+
+// GSVD_GRAM_AUTO: the split form when a slice count meets the accuracy target and
+// the tuning table's times (scaled by the slice count: the split Gram's work grows
+// about linearly with S) put it ahead of the plain form.  Without table rows:
+// FP64 A split (the dd Gram runs on the vector units, the split form on the int8
+// matrix cores), FP32 A plain (one exact FP64 matrix-core pass).  The batched call
+// takes one form for all its problems: split for FP64, plain for FP32.
+inline bool auto_split(const gsvd_opts *o, int64_t m, int64_t n, bool batched) {
+    const int S = slices_for_target(o, n);
+    if (S == 0) return false;
+    const bool f64 = o->working == GSVD_F64;
+    if (batched || wide_n(n)) return f64;
+    double tp = 0.0, ts = 0.0;
+    int sp = 0, ss = 0;
+    if (!tune_gram_ms(o->working, GSVD_GRAM_PLAIN, n, m, false, &tp, &sp) ||
+        !tune_gram_ms(o->working, GSVD_GRAM_SPLIT, n, m, false, &ts, &ss) || ss < 1)
+        return f64;
+    return ts * (double)S / (double)ss < tp;
+}
+
+// The options with the Gram form and slice count resolved for this problem shape:
+// gram is PLAIN or SPLIT, and a split form carries its slice count.
+inline gsvd_opts resolve_opts(const gsvd_opts *o, int64_t m, int64_t n, bool batched) {
+    gsvd_opts r = *o;
+    if (r.gram == GSVD_GRAM_AUTO)
+        r.gram = auto_split(o, m, n, batched) ? GSVD_GRAM_SPLIT : GSVD_GRAM_PLAIN;
+    if (r.gram == GSVD_GRAM_SPLIT) r.n_slices = slices_of(o, n);
+    return r;
 }
 
 // the plain Gram of FP32 A on the matrix cores, at the tuned slab height
@@ -168,14 +226,16 @@ inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
 
 inline int sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 30; }
 
-// eps_M of eq. (ATA) for the assumption check, in the scaled sense
-// |dM_ij| <= eps sqrt(M_ii M_jj): u_h for the plain Gram; for the split Gram the
-// tuning table's measured error of its slice count
-inline double gram_eps_of(const gsvd_opts *o, int64_t n) {
+// Bound on ||D^-1 dM D^-1|| for the Gram's error dM, for the assumption check:
+// n^2 u_h for the plain Gram (the n^2 eps_M of eq. (thm:assump)); n eps for the
+// split Gram, eps the tuning table's measured error of its slice count in the
+// scaled sense |dM_ij| <= eps sqrt(M_ii M_jj)
+inline double gram_pert_of(const gsvd_opts *o, int64_t n) {
     const double u_h = o->working == GSVD_F64 ? 0x1p-104 : 0x1p-53;
-    if (!use_split(o)) return u_h;
+    const double dn = (double)n;
+    if (!use_split(o)) return dn * dn * u_h;
     const double e = tune_eps(o->working, n, slices_of(o, n));
-    return e > u_h ? e : u_h;
+    return dn * (e > u_h ? e : u_h);
 }
 
 // Eigensolver scratch.  FP32 working with n > 128: S, V, W of the FP64
@@ -214,7 +274,7 @@ inline size_t eig_work_bytes(const gsvd_opts *o, int64_t n) { return eig_layout(
 // The eigensolver stage (Alg. 1 steps 3-5), then the assumption check.
 inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, const double *Mlo,
                           int64_t ldm, void *S, void *V, int64_t ldv, void *W, int64_t ldw,
-                          int *info, void *work, double eps_m, hipStream_t st) {
+                          int *info, void *work, double e_gram, hipStream_t st) {
     const int sweeps = sweeps_of(o);
     char *base = (char *)work;
     const EigLayout L = eig_layout(o, n);
@@ -255,7 +315,7 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
                          jacobi_tol_of(o, n), sweeps, st);
     }
     if (err != hipSuccess) return err;
-    return assump_launch(o->working, n, Mhi, ldm, W, ldw, info, eps_m,
+    return assump_launch(o->working, n, Mhi, ldm, W, ldw, info, e_gram,
                          eig_mode_of(o) == GSVD_EIG_CHOL_JACOBI1, st);
 }
 

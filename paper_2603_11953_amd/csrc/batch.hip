@@ -182,6 +182,13 @@ int plan_batch(int batch, const int64_t *hM, const int64_t *hN, const int64_t *h
     return 0;
 }
 
+// One Gram form and slice count for the whole batch, resolved at its largest n.
+gsvd_opts resolve_batched(const gsvd_opts *o, int batch, const int64_t *hN) {
+    int64_t nmax = 1;
+    for (int i = 0; i < batch; ++i) nmax = std::max(nmax, hN[i]);
+    return resolve_opts(o, 0, nmax, true);
+}
+
 }  // namespace
 }  // namespace gsvd
 
@@ -193,6 +200,8 @@ size_t gsvd_thin_batched_workspace_size(int batch, const int64_t *hM, const int6
                                         const gsvd_opts *o) {
     if (batch < 1 || batch > 65535 || hM == nullptr || hN == nullptr || check_opts(o, 4) != 0)
         return 0;
+    const gsvd_opts r = resolve_batched(o, batch, hN);
+    o = &r;
     BatchPlan P;
     if (plan_batch(batch, hM, hN, nullptr, nullptr, nullptr, false, o, P) != 0) return 0;
     return P.total;
@@ -211,6 +220,8 @@ int gsvd_thin_batched(int batch, const int64_t *hM, const int64_t *hN, const voi
     if (dV == nullptr) return -7;
     if (hLdv == nullptr) return -8;
     if (int e = check_opts(o, 14)) return e;
+    const gsvd_opts r = resolve_batched(o, batch, hN);
+    o = &r;
     const bool want_u = (o->flags & GSVD_WANT_U) != 0;
     if (want_u && dU == nullptr) return -9;
     if (want_u && hLdu == nullptr) return -10;
@@ -262,7 +273,7 @@ int gsvd_thin_batched(int batch, const int64_t *hM, const int64_t *hN, const voi
                                        sweeps_of(o), st);
     }
     if (err == hipSuccess)
-        err = assump_batched_launch(o->working, tab, batch, gram_eps_of(o, P.max_n),
+        err = assump_batched_launch(o->working, tab, batch, gram_pert_of(o, P.max_n),
                                     eig_mode_of(o) == GSVD_EIG_CHOL_JACOBI1, P.max_n, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (want_u) {

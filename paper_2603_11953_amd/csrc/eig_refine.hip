@@ -30,7 +30,9 @@
 // neglected terms are then below 2^-60 relative), a few otherwise.
 //
 // Stopping rule: the sweep whose largest angle is <= 2^-30 is the last.  At most
-// RK sweeps are queued on the stream; those after convergence return at once.
+// rk sweeps are queued on the stream (2 after the FP64 Algorithm 2, whose angles
+// are about u kappa(B); 3 after an FP32-accurate one); those after convergence
+// return at once.
 // A pair whose angle would exceed 2^-8 (eigenvalues that agree to within the
 // coupling: a cluster) is not rotated (f_ij = -g_ij / 2 only re-orthogonalises);
 // such pairs, or a last sweep above the threshold, set GSVD_INFO_WARN_REFINE.
@@ -53,7 +55,6 @@
 namespace gsvd {
 namespace {
 
-constexpr int RK = 4;                  // sweeps queued
 constexpr double TAU_STOP = 0x1p-30;   // last sweep: every angle at most this
 constexpr double TAU_CLUSTER = 0x1p-8; // larger angles: a cluster pair, not rotated
 constexpr int TB = 32;                 // output tile edge of the products
@@ -157,13 +158,13 @@ __device__ __forceinline__ void mac_dd(double &h, double &l, double ah, double a
 }
 
 template <class P>
-__global__ void __launch_bounds__(256) ref_init_kernel(P probs) {
+__global__ void __launch_bounds__(256) ref_init_kernel(P probs, int rk) {
     const RefProb p = probs.get(blockIdx.y);
     const int n = p.n;
     const int nn = n * n;
     RefBufs B = ref_bufs(p.rw, n);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        B.ctrl->stop_iter = (*p.info != 0) ? -1 : RK - 1;
+        B.ctrl->stop_iter = (*p.info != 0) ? -1 : rk - 1;
         B.ctrl->warn = 0;
     }
     const int idx = blockIdx.x * 256 + threadIdx.x;
@@ -295,7 +296,7 @@ __device__ __forceinline__ double wave_max(double x) {
 // Rayleigh quotients, the update F, and the stopping decision (one workgroup
 // per problem).
 template <class P>
-__global__ void __launch_bounds__(FT) ref_angles_kernel(P probs, int iter) {
+__global__ void __launch_bounds__(FT) ref_angles_kernel(P probs, int iter, int rk) {
     const RefProb p = probs.get(blockIdx.x);
     const int n = p.n;
     RefBufs B = ref_bufs(p.rw, n);
@@ -350,7 +351,7 @@ __global__ void __launch_bounds__(FT) ref_angles_kernel(P probs, int iter) {
             m = fmax(m, red[w]);
             c |= redc[w];
         }
-        if (m <= TAU_STOP || iter == RK - 1) {
+        if (m <= TAU_STOP || iter == rk - 1) {
             B.ctrl->stop_iter = iter;
             B.ctrl->warn = (m <= TAU_STOP ? 0 : 1) | (c ? 2 : 0);
         }
@@ -443,39 +444,56 @@ struct TabAssump {
     }
 };
 
-// kappa(B) <= ||B||_F ||B^+||_F = sqrt(n) ||D W||_F (B = A D^-1 has unit columns;
-// A = U Sigma V^T gives B^+ = D V Sigma^-1 U^T, so ||B^+||_F = ||D V Sigma^-1||_F,
-// with D = diag(sqrt(m_jj))).  With that kappa the conditions of Remark 1 (the
-// u_h Jacobi) and of the remark after Lemma 1 (Algorithm 2) are checked with the
-// constants of eq. (thm:assump) where it fixes them:
-//   2 (n^2 eps_m + n u_h) kappa^2 <= 1/2        (the Gram and eigensolver at u_h)
+// kappa(B)^2 = lambda_max(H) ||B^+||_2^2 with H = D^-1 M_h D^-1 = B^T B
+// (D = diag(sqrt(m_jj)), B = A D^-1 with unit columns).  Bounds from what the
+// eigensolver produced: lambda_max(H) <= max_i sum_j |h_ij| (Gershgorin), and
+// ||B^+||_2 <= ||B^+||_F = ||D W||_F, since A = U Sigma V^T gives
+// B^+ = D V Sigma^-1 U^T and W = V Sigma^-1.  With that kappa the conditions of
+// Remark 1 (the u_h Jacobi) and of the remark after Lemma 1 (Algorithm 2) are
+// checked, with the constants of eq. (thm:assump):
+//   2 (e_gram + n u_h) kappa^2 <= 1/2, e_gram bounding ||D^-1 dM D^-1|| for the
+//     Gram's error dM (n^2 u_h for the plain Gram, as in eq. (thm:assump);
+//     n eps for a split Gram whose entries carry |dM_ij| <= eps sqrt(m_ii m_jj)),
 //   c_w u kappa <= 1/2, c_w = n for Algorithm 2 (its O(u) kappa(B) term), else 0;
 // a failed condition sets GSVD_INFO_WARN_ASSUMPTION (Theorem 1's bounds are then
 // not guaranteed).
 template <typename TW, class P>
 __global__ void __launch_bounds__(256)
-assump_kernel(P probs, double eps_m, double u_h, double u_w, double c_w) {
+assump_kernel(P probs, double e_gram, double u_h, double u_w, double c_w) {
     const AssumpProb p = probs.get(blockIdx.x);
     const int n = p.n;
     const TW *W = reinterpret_cast<const TW *>(p.W);
-    __shared__ double red[4];
-    double s = 0.0;
-    for (int idx = threadIdx.x; idx < n * n; idx += 256) {
-        const int r = idx % n, c = idx / n;
-        const double w = (double)W[r + (int64_t)c * p.ldw];
-        s = __builtin_fma(p.Mhi[r + (int64_t)r * p.ldm] * w, w, s);
+    __shared__ double red[4], redg[4];
+    double s = 0.0, gmax = 0.0;
+    for (int c = threadIdx.x; c < n; c += 256) {
+        const double dc = p.Mhi[c + (int64_t)c * p.ldm];
+        double rs = 0.0;
+        for (int r = 0; r < n; ++r) {
+            const double w = (double)W[r + (int64_t)c * p.ldw];
+            const double dr = p.Mhi[r + (int64_t)r * p.ldm];
+            s = __builtin_fma(dr * w, w, s);
+            rs += __builtin_fabs(p.Mhi[r + (int64_t)c * p.ldm]) / __builtin_sqrt(dr * dc);
+        }
+        gmax = fmax(gmax, rs);
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        gmax = fmax(gmax, __shfl_xor(gmax, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = s;
+        redg[threadIdx.x >> 6] = gmax;
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
     const int info = *p.info;
     if ((info & 0xff) != 0) return;
     const double dn = (double)n;
-    const double kap = __builtin_sqrt(dn * (((red[0] + red[1]) + red[2]) + red[3]));
-    const bool hi_ok = 2.0 * (dn * dn * eps_m + dn * u_h) * kap * kap <= 0.5;
-    const bool w_ok = c_w * u_w * kap <= 0.5;
+    const double g = fmax(fmax(redg[0], redg[1]), fmax(redg[2], redg[3]));
+    const double kap2 = g * (((red[0] + red[1]) + red[2]) + red[3]);
+    const bool hi_ok = 2.0 * (e_gram + dn * u_h) * kap2 <= 0.5;
+    const bool w_ok = c_w * u_w * __builtin_sqrt(kap2) <= 0.5;
     if (!(hi_ok && w_ok)) *p.info = info | GSVD_INFO_WARN_ASSUMPTION;
 }
 
@@ -503,18 +521,20 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(double *__restrict__ p, 
 
 template <class P>
 hipError_t refine_queue(P probs, int count, int max_n, bool f32, hipStream_t st) {
+    const int rk = f32 ? 3 : 2;
     const int nt = (max_n + TB - 1) / TB;
     const unsigned nn_blocks = (unsigned)(((size_t)max_n * max_n + 255) / 256);
     hipLaunchKernelGGL(ref_init_kernel<P>, dim3(nn_blocks, (unsigned)count), dim3(256), 0, st,
-                       probs);
+                       probs, rk);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    for (int it = 0; it < RK; ++it) {
+    for (int it = 0; it < rk; ++it) {
         hipLaunchKernelGGL((ref_gemm_kernel<0, P>), dim3(nt, nt, count), dim3(256), 0, st, probs,
                            it);
         hipLaunchKernelGGL((ref_gemm_kernel<1, P>), dim3(nt, 2 * nt, count), dim3(256), 0, st,
                            probs, it);
-        hipLaunchKernelGGL(ref_angles_kernel<P>, dim3((unsigned)count), dim3(FT), 0, st, probs, it);
+        hipLaunchKernelGGL(ref_angles_kernel<P>, dim3((unsigned)count), dim3(FT), 0, st, probs, it,
+                           rk);
         hipLaunchKernelGGL((ref_gemm_kernel<2, P>), dim3(nt, nt, count), dim3(256), 0, st, probs,
                            it);
         if ((err = hipGetLastError()) != hipSuccess) return err;
@@ -552,7 +572,7 @@ hipError_t refine_batched_launch(const BatchMat *tab, int batch, int max_n, hipS
 }
 
 hipError_t assump_launch(int working, int64_t n, const double *Mhi, int64_t ldm, const void *W,
-                         int64_t ldw, int *info, double eps_m, bool alg2, hipStream_t st) {
+                         int64_t ldw, int *info, double e_gram, bool alg2, hipStream_t st) {
     if (n < 1 || ldm < n || ldw < n) return hipErrorInvalidValue;
     OneAssump a;
     a.p = AssumpProb{Mhi, ldm, W, ldw, info, (int)n};
@@ -561,14 +581,14 @@ hipError_t assump_launch(int working, int64_t n, const double *Mhi, int64_t ldm,
     const double c_w = alg2 ? (double)n : 0.0;
     if (working == GSVD_F64)
         hipLaunchKernelGGL((assump_kernel<double, OneAssump>), dim3(1), dim3(256), 0, st, a,
-                           eps_m, u_h, u_w, c_w);
+                           e_gram, u_h, u_w, c_w);
     else
-        hipLaunchKernelGGL((assump_kernel<float, OneAssump>), dim3(1), dim3(256), 0, st, a, eps_m,
+        hipLaunchKernelGGL((assump_kernel<float, OneAssump>), dim3(1), dim3(256), 0, st, a, e_gram,
                            u_h, u_w, c_w);
     return hipGetLastError();
 }
 
-hipError_t assump_batched_launch(int working, const BatchMat *tab, int batch, double eps_m,
+hipError_t assump_batched_launch(int working, const BatchMat *tab, int batch, double e_gram,
                                  bool alg2, int max_n, hipStream_t st) {
     if (batch < 1) return hipErrorInvalidValue;
     const double u_h = working == GSVD_F64 ? 0x1p-104 : 0x1p-53;
@@ -577,10 +597,10 @@ hipError_t assump_batched_launch(int working, const BatchMat *tab, int batch, do
     const double c_w = alg2 ? (double)max_n : 0.0;
     if (working == GSVD_F64)
         hipLaunchKernelGGL((assump_kernel<double, TabAssump>), dim3((unsigned)batch), dim3(256), 0,
-                           st, TabAssump{tab}, eps_m, u_h, u_w, c_w);
+                           st, TabAssump{tab}, e_gram, u_h, u_w, c_w);
     else
         hipLaunchKernelGGL((assump_kernel<float, TabAssump>), dim3((unsigned)batch), dim3(256), 0,
-                           st, TabAssump{tab}, eps_m, u_h, u_w, c_w);
+                           st, TabAssump{tab}, e_gram, u_h, u_w, c_w);
     return hipGetLastError();
 }
 

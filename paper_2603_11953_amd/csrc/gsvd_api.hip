@@ -75,6 +75,8 @@ void gsvd_opts_default(gsvd_opts *o, int working) {
     o->max_sweeps = 0;
     o->flags = GSVD_WANT_U;
     o->slab_rows = 0;
+    o->target_rel_err = 0.0;
+    o->kappa_b = 0.0;
 }
 
 const char *gsvd_status_string(int code) {
@@ -95,8 +97,9 @@ const char *gsvd_status_string(int code) {
 }
 
 size_t gsvd_gram_workspace_size(int64_t m, int64_t n, const gsvd_opts *o) {
-    if (m < 1 || n < 1 || o == nullptr) return 0;
-    return align_up(gram_part_bytes(m, n, o, false));
+    if (m < 1 || n < 1 || check_opts(o, 3) != 0) return 0;
+    const gsvd_opts r = resolve_opts(o, m, n, false);
+    return align_up(gram_part_bytes(m, n, &r, false));
 }
 
 int gsvd_gram_config(int64_t m, int64_t n, const gsvd_opts *o, int64_t *slab_rows,
@@ -104,6 +107,8 @@ int gsvd_gram_config(int64_t m, int64_t n, const gsvd_opts *o, int64_t *slab_row
     if (m < 1) return -1;
     if (n < 1 || n > GSVD_MAX_N || n > m) return -2;
     if (int e = check_opts(o, 3)) return e;
+    const gsvd_opts r = resolve_opts(o, m, n, false);
+    o = &r;
     if (int e = check_gram_supported(o, n)) return e;
     int64_t rows, slabs;
     int S = 0;
@@ -147,6 +152,8 @@ int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda, double *dMhi, d
     if (o->working == GSVD_F64 && dMlo == nullptr) return -6;
     if (ldm < n) return -7;
     const size_t need = gsvd_gram_workspace_size(m, n, o);
+    const gsvd_opts r = resolve_opts(o, m, n, false);
+    o = &r;
     if (work == nullptr || !aligned(work, kAlign)) return -8;
     if (work_bytes < need) return -9;
     if (int e = check_gram_supported(o, n)) return e;
@@ -177,9 +184,10 @@ int gsvd_eig(int64_t n, const double *dMhi, const double *dMlo, int64_t ldm, voi
     if (need > 0 && (work == nullptr || !aligned(work, kAlign))) return -11;
     if (work_bytes < need) return -12;
     if (int e = check_eig_supported(o, n)) return e;
+    // the Gram's origin is not known here: the plain form's bound
     const double u_h = o->working == GSVD_F64 ? 0x1p-104 : 0x1p-53;
-    hipError_t err = eig_any(o, n, dMhi, dMlo, ldm, dS, dV, ldv, dW, ldw, dInfo, work, u_h,
-                             (hipStream_t)stream);
+    hipError_t err = eig_any(o, n, dMhi, dMlo, ldm, dS, dV, ldv, dW, ldw, dInfo, work,
+                             (double)n * (double)n * u_h, (hipStream_t)stream);
     return err == hipSuccess ? GSVD_OK : GSVD_ERR_HIP;
 }
 
@@ -199,8 +207,9 @@ int gsvd_u_recover(int64_t m, int64_t n, const void *dA, int64_t lda, const void
 }
 
 size_t gsvd_thin_workspace_size(int64_t m, int64_t n, const gsvd_opts *o) {
-    if (m < 1 || n < 1 || o == nullptr) return 0;
-    return thin_layout(m, n, o).total;
+    if (m < 1 || n < 1 || check_opts(o, 3) != 0) return 0;
+    const gsvd_opts r = resolve_opts(o, m, n, false);
+    return thin_layout(m, n, &r).total;
 }
 
 int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void *dV, int64_t ldv,
@@ -214,6 +223,8 @@ int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void 
     if (dV == nullptr) return -6;
     if (ldv < n) return -7;
     if (int e = check_opts(o, 13)) return e;
+    const gsvd_opts r = resolve_opts(o, m, n, false);
+    o = &r;
     const bool want_u = (o->flags & GSVD_WANT_U) != 0;
     if (want_u && dU == nullptr) return -8;
     if (want_u && ldu < m) return -9;
@@ -231,7 +242,7 @@ int gsvd_thin(int64_t m, int64_t n, const void *dA, int64_t lda, void *dS, void 
     void *W = base + L.w;
     hipError_t err = gram_any(o, m, n, dA, lda, Mhi, Mlo, n, base + L.part, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
-    err = eig_any(o, n, Mhi, Mlo, n, dS, dV, ldv, W, n, dInfo, base + L.eigw, gram_eps_of(o, n),
+    err = eig_any(o, n, Mhi, Mlo, n, dS, dV, ldv, W, n, dInfo, base + L.eigw, gram_pert_of(o, n),
                   st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (want_u) {

@@ -181,9 +181,10 @@ hipError_t refine_batched_launch(const BatchMat *tab, int batch, int max_n, hipS
 // The assumption check of Theorem 1 (GSVD_INFO_WARN_ASSUMPTION) after any
 // eigensolver: reads diag(M_h), W and info.
 // alg2: Algorithm 2 was the last eigensolver (its O(u) kappa(B) condition applies).
+// e_gram bounds ||D^-1 dM D^-1|| for the Gram's error dM.
 hipError_t assump_launch(int working, int64_t n, const double *Mhi, int64_t ldm, const void *W,
-                         int64_t ldw, int *info, double eps_m, bool alg2, hipStream_t st);
-hipError_t assump_batched_launch(int working, const BatchMat *tab, int batch, double eps_m,
+                         int64_t ldw, int *info, double e_gram, bool alg2, hipStream_t st);
+hipError_t assump_batched_launch(int working, const BatchMat *tab, int batch, double e_gram,
                                  bool alg2, int max_n, hipStream_t st);
 // zeros into n doubles (a kernel, so a captured graph holds no memset node)
 hipError_t fill_zero_launch(double *p, size_t n, hipStream_t st);

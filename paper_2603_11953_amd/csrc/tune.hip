@@ -14,10 +14,16 @@ int64_t tune_slab_rows(int working, int gram, int64_t n, int64_t m, bool batched
     return 0;
 }
 
-int tune_slices(int working, int64_t n) {
-    for (const TuneSlices &r : kTuneSlices)
-        if (r.working == working && n <= r.n_max) return r.slices;
-    return working == GSVD_F64 ? 10 : 6;
+bool tune_gram_ms(int working, int gram, int64_t n, int64_t m, bool batched, double *ms,
+                  int *slices) {
+    for (const TuneSlab &r : kTuneSlab)
+        if (r.working == working && r.gram == gram && r.batched == (batched ? 1 : 0) &&
+            n <= r.n_max && m <= r.m_max) {
+            *ms = r.ms;
+            *slices = r.slices;
+            return true;
+        }
+    return false;
 }
 
 double tune_eps(int working, int64_t n, int S) {

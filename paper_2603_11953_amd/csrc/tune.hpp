@@ -13,12 +13,8 @@ struct TuneSlab {
     int n_max;         // row applies to n <= n_max ...
     int64_t m_max;     // ... and m <= m_max (first matching row wins)
     int64_t slab_rows; // rows of A per Gram workgroup
-};
-
-struct TuneSlices {
-    int working;
-    int n_max;
-    int slices;        // split Gram slice count
+    double ms;         // Gram time at that height, at the bucket's tuning size
+    int slices;        // split rows: the slice count the time was taken at
 };
 
 struct TuneEps {
@@ -30,7 +26,10 @@ struct TuneEps {
 
 // 0 when no row matches: the plan then uses its own default slab count
 int64_t tune_slab_rows(int working, int gram, int64_t n, int64_t m, bool batched);
-int tune_slices(int working, int64_t n);
+// the tuned Gram time (ms) and, for the split form, the slice count it was taken
+// at, of the row that applies; false when no row applies
+bool tune_gram_ms(int working, int gram, int64_t n, int64_t m, bool batched, double *ms,
+                  int *slices);
 // the split Gram's error for S slices (scaled as above): the table's measurement,
 // else the a-priori 2^(12 - 8 S) (a digit pair's dropped remainder, 2^(-8 S) of
 // the slab's column scale 2^E <= 64 max|a|, summed over a slab)

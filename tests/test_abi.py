@@ -259,3 +259,42 @@ def test_batched_workspace_and_unsupported():
     assert gs.gsvd_thin_batched_workspace_size(3, i64(1000, 2000, 500), i64(16, 128, 8),
                                                ctypes.byref(o32)) > 0
     assert _batch_call(o=gs.opts(gs.GSVD_F64, gs.GSVD_GRAM_SPLIT, n_slices=13)) == -101
+
+
+def test_target_rel_err_sets_the_slice_count():
+    """The split slice count follows the requested accuracy: a tighter target never
+    lowers S, a looser one never raises it; kappa_b enters squared; bad values are
+    refused synchronously."""
+    prev = 0
+    for t in (1e-4, 1e-8, 1e-11, 1e-13, 1e-15):
+        S = gs.gram_config(1_000_000, 64, gs.GSVD_F64, gs.GSVD_GRAM_SPLIT,
+                           target_rel_err=t)["n_slices"]
+        assert S >= prev, (t, S, prev)
+        prev = S
+    assert prev > gs.gram_config(1_000_000, 64, gs.GSVD_F64, gs.GSVD_GRAM_SPLIT,
+                                 target_rel_err=1e-4)["n_slices"]
+    lo = gs.gram_config(1_000_000, 64, gs.GSVD_F64, gs.GSVD_GRAM_SPLIT, kappa_b=10)["n_slices"]
+    hi = gs.gram_config(1_000_000, 64, gs.GSVD_F64, gs.GSVD_GRAM_SPLIT, kappa_b=1e5)["n_slices"]
+    assert lo <= hi
+    # an explicit count wins over the target
+    assert gs.gram_config(1_000_000, 64, gs.GSVD_F64, gs.GSVD_GRAM_SPLIT, n_slices=4,
+                          target_rel_err=1e-15)["n_slices"] == 4
+    for bad in (dict(target_rel_err=-1.0), dict(kappa_b=-2.0), dict(target_rel_err=float("nan"))):
+        o = gs.opts(gs.GSVD_F64, **bad)
+        assert gs.gsvd_gram_config(1000, 4, ctypes.byref(o), None, None, None) == -3
+        assert gs.gsvd_thin_workspace_size(1000, 4, ctypes.byref(o)) == 0
+
+
+def test_auto_gram_form():
+    """GSVD_GRAM_AUTO: the split form for FP64 A (the dd Gram is vector-unit bound), the
+    plain form for FP32 A at n <= 128 (one exact FP64 matrix-core pass beats five int8
+    digit planes), per the tuning table; PLAIN when no slice count meets the target."""
+    assert gs.gram_config(1_000_000, 64, gs.GSVD_F64)["n_slices"] > 0
+    assert gs.gram_config(2_000_000, 512, gs.GSVD_F64)["n_slices"] > 0
+    assert gs.gram_config(4_000_000, 128, gs.GSVD_F32)["n_slices"] == 0
+    assert gs.gram_config(1_000_000, 64, gs.GSVD_F64, target_rel_err=1e-30)["n_slices"] == 0
+    # workspace sizes follow the resolved form
+    o_auto = gs.opts(gs.GSVD_F64)
+    o_split = gs.opts(gs.GSVD_F64, gs.GSVD_GRAM_SPLIT)
+    assert (gs.gsvd_thin_workspace_size(1_000_000, 64, ctypes.byref(o_auto)) ==
+            gs.gsvd_thin_workspace_size(1_000_000, 64, ctypes.byref(o_split)))

@@ -124,5 +124,31 @@ def test_thin_split_end_to_end(spec):
     S, V, Uo, info = _thin_split(A)
     assert info == 0
     rep = check_thin(A, S, V, Uo, o, label=str(spec))
-    if o.kappa_b <= 100.5:
-        assert rep["u_orth_meets_50nu"], rep
+    assert rep["u_orth_meets_50nu"], rep
+
+
+def test_target_rel_err_raises_the_slice_count_and_is_met():
+    """The requested sigma accuracy sets the split Gram's slice count: each tighter target
+    gives at least as many slices, and every run meets its own target (and the
+    tolerance 50 n u kappa(B)) against the oracle."""
+    import paper_2603_11953_amd as gs
+    A = g.make_a(g.MatrixSpec(m=100_000, n=64, kappa_b=100, kappa_d=1e10, mode_b=3, mode_d=3,
+                              seed=12_345, shuffle=True, w1="gauss"))
+    o = ref.svd(A)
+    prev = 0
+    for target in (1e-5, 1e-9, 1e-12):
+        S_used = gs.gram_config(A.shape[0], 64, gs.GSVD_F64, gs.GSVD_GRAM_SPLIT,
+                                target_rel_err=target, kappa_b=100)["n_slices"]
+        assert S_used >= prev
+        prev = S_used
+        say("target", target, "S", S_used)
+        import torch
+        S, V, U, info = gs.thin(to_dev(A), gram=gs.GSVD_GRAM_SPLIT, target_rel_err=target,
+                                kappa_b=100)
+        torch.cuda.synchronize()
+        assert (int(info.item()) & 0xFF) == 0
+        err = ref.sigma_rel_err(to_np(S), o).max()
+        assert err <= target, (target, S_used, err)
+        assert err <= sigma_tol(64, 2.0 ** -53, o.kappa_b)
+    assert prev > gs.gram_config(A.shape[0], 64, gs.GSVD_F64, gs.GSVD_GRAM_SPLIT,
+                                 target_rel_err=1e-5, kappa_b=100)["n_slices"]
