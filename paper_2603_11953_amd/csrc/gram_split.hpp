@@ -187,7 +187,8 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
     constexpr int NPASS = (N16 + CPP - 1) / CPP;  // producer passes
     constexpr bool PREF = NPASS * (int)sizeof(T) <= 32;  // next chunk held in registers
     extern __shared__ unsigned char smem[];
-    int *flagc = reinterpret_cast<int *>(smem + NBUF * BB);  // [2]
+    // [0], [1]: the chunk whose exponents grew, per buffer; [2]: a NaN or Inf was seen
+    int *flagc = reinterpret_cast<int *>(smem + NBUF * BB);
     auto planes_of = [&](int b) { return reinterpret_cast<signed char *>(smem + b * BB); };
     auto expo_of = [&](int b) { return reinterpret_cast<int *>(smem + b * BB + SS * SL); };
 
@@ -199,7 +200,7 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
     const int64_t r1 = (r0 + rows_per_split < m) ? r0 + rows_per_split : m;
     const int nchunk = (int)((r1 - r0 + SP_KT - 1) / SP_KT);
 
-    if (tid < 2) flagc[tid] = 0;
+    if (tid < 3) flagc[tid] = 0;
     __syncthreads();
 
     // ---------------- producer state
@@ -230,6 +231,20 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
         }
         signed char *planes = planes_of(b);
         int *expo = expo_of(b);
+        // a NaN or Inf cannot be cut into digits: it is taken as zero and flagged,
+        // and the workgroup's partial sums become NaN
+        bool nonfinite = false;
+#pragma unroll
+        for (int p = 0; p < NPASS; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double x = __builtin_fabs((double)cur[p][q]);
+                if (!(x <= 1.7976931348623157e308)) {
+                    nonfinite = true;
+                    cur[p][q] = (T)0;
+                }
+            }
+        if (nonfinite) flagc[2] = 1;
 #pragma unroll
         for (int p = 0; p < NPASS; ++p) {
             const int c = CPP * p + pcol;
@@ -380,6 +395,10 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
         }
     }
     if (has_tile) flush(first_flush);
+    if (has_tile && flagc[2] != 0) {  // set before the last barrier of the producers' loop
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dst[k] = __builtin_nan("");
+    }
 }
 
 template <typename T, int NB, int SS>

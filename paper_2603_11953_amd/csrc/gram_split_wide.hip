@@ -21,6 +21,10 @@
 //          the workgroup's slot (written by the first pass, added to by later
 //          ones, always in the same order);
 //   reduce the slots of all groups, in order, into M_h (both triangles).
+// A NaN or Inf entry cannot be cut into digits: the slice kernel treats it as
+// zero and raises a flag in the workspace (cleared at the start of the call);
+// the reduction then writes NaN to every entry of M_h, so the eigensolver
+// reports non-finite input.
 // The int32 sums never exceed 128 chunks x 64 rows x 12 pairs x 128^2 < 2^31.
 #include <hip/hip_runtime.h>
 
@@ -51,22 +55,36 @@ __device__ __forceinline__ void sw_pair(int p, int np, int &I, int &J) {
 }
 
 // grid (npad / 64, slabs of the pass); 4 wavefronts
+__global__ void __launch_bounds__(64) sw_flag_clear_kernel(int *__restrict__ flag) {
+    if (threadIdx.x == 0) *flag = 0;
+}
+
+// |a| of a finite entry, 0 for NaN or Inf (which sets *bad)
+__device__ __forceinline__ double sw_finite_abs(double a, bool &bad) {
+    const double x = __builtin_fabs(a);
+    const bool fin = x <= 1.7976931348623157e308;  // false for NaN and Inf
+    bad = bad || !fin;
+    return fin ? x : 0.0;
+}
+
 template <typename T, int SS>
 __global__ void __launch_bounds__(256)
 sw_slice_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int npad, int64_t row0,
-                int nchp, signed char *__restrict__ planes, int *__restrict__ expo) {
+                int nchp, signed char *__restrict__ planes, int *__restrict__ expo,
+                int *__restrict__ nonfinite) {
     __shared__ int Es[SW_P];
     const int cg = blockIdx.x, sl = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t r0 = row0 + (int64_t)sl * SW_SR;
     const int64_t r1 = (r0 + SW_SR < m) ? r0 + SW_SR : m;
+    bool bad = false;
     // exact column maxima of the slab: wavefront w takes columns 16 w .. 16 w + 15
     for (int j = 0; j < 16; ++j) {
         const int cl = 16 * w + j, c = SW_P * cg + cl;
         double mx = 0.0;
         if (c < n)
             for (int64_t r = r0 + lane; r < r1; r += 64)
-                mx = fmax(mx, __builtin_fabs((double)A[r + (int64_t)c * lda]));
+                mx = fmax(mx, sw_finite_abs((double)A[r + (int64_t)c * lda], bad));
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
         if (lane == 0) {
@@ -75,6 +93,7 @@ sw_slice_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int npad
             expo[(int64_t)sl * npad + c] = e;
         }
     }
+    if (bad) *nonfinite = 1;
     __syncthreads();
     // digits: lane l holds rows 4 (l % 16) .. + 3 of column 16 s + 4 w + l / 16
     constexpr int NW3 = (SS + 3) / 4;
@@ -91,6 +110,9 @@ sw_slice_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int npad
             for (int q = 0; q < 4; ++q) {
                 const int64_t r = rb + q;
                 v[q] = (c < n && r < r1) ? (double)A[r + (int64_t)c * lda] : 0.0;
+                bool nf = false;
+                sw_finite_abs(v[q], nf);
+                if (nf) v[q] = 0.0;  // digits only for finite values (the flag is set above)
             }
             unsigned wd[3][4];
 #pragma unroll
@@ -266,7 +288,8 @@ sw_syrk_kernel(const signed char *__restrict__ planes, const int *__restrict__ e
 // one lane per (pair, tile, lane, q) entry: the groups in order; upper triangle to both halves
 __global__ void __launch_bounds__(256)
 sw_reduce_kernel(const double *__restrict__ slots, int groups, int np, int npair, int n,
-                 double *__restrict__ Mhi, double *__restrict__ Mlo, int64_t ldm) {
+                 double *__restrict__ Mhi, double *__restrict__ Mlo, int64_t ldm,
+                 const int *__restrict__ nonfinite) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t per_pair = 16 * 64 * 4;
     if (id >= (int64_t)npair * per_pair) return;
@@ -284,6 +307,7 @@ sw_reduce_kernel(const double *__restrict__ slots, int groups, int np, int npair
     const size_t stride = (size_t)npair * 16 * 64 * 8;
     const double *p = slots + (((size_t)pair * 16 + w) * 64 + lane) * 8 + 2 * q;
     for (int g = 0; g < groups; ++g) s = dd_add(s, dd_t{p[g * stride], p[g * stride + 1]});
+    if (*nonfinite) s = dd_t{__builtin_nan(""), __builtin_nan("")};
     Mhi[i + (int64_t)j * ldm] = s.hi;
     Mhi[j + (int64_t)i * ldm] = s.hi;
     if (Mlo) {
@@ -299,6 +323,7 @@ hipError_t sw_run(int64_t m, int64_t n, const T *A, int64_t lda, double *Mhi, do
     signed char *planes = reinterpret_cast<signed char *>(work + p.plane_off);
     int *expo = reinterpret_cast<int *>(work + p.expo_off);
     double *slots = reinterpret_cast<double *>(work + p.slot_off);
+    int *nonfinite = reinterpret_cast<int *>(work + p.flag_off);
     const size_t buf = (size_t)SS * 2 * SW_P * SP_KT;
     const size_t lds = 2 * buf <= 160 * 1024 ? 2 * buf : buf;
     auto ks = sw_syrk_kernel<SS, DD>;
@@ -306,13 +331,15 @@ hipError_t sw_run(int64_t m, int64_t n, const T *A, int64_t lda, double *Mhi, do
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     const int nchp = (int)(p.rows_per_pass / SP_KT);
+    hipLaunchKernelGGL(sw_flag_clear_kernel, dim3(1), dim3(64), 0, st, nonfinite);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     for (int64_t ps = 0; ps < p.npass; ++ps) {
         const int64_t row0 = ps * p.rows_per_pass;
         const int64_t rows = (m - row0 < p.rows_per_pass) ? m - row0 : p.rows_per_pass;
         const unsigned slabs = (unsigned)((rows + SW_SR - 1) / SW_SR);
         const unsigned groups = (unsigned)((rows + SW_RW - 1) / SW_RW);
         hipLaunchKernelGGL((sw_slice_kernel<T, SS>), dim3((unsigned)p.np, slabs), dim3(256), 0, st,
-                           A, lda, m, (int)n, p.npad, row0, nchp, planes, expo);
+                           A, lda, m, (int)n, p.npad, row0, nchp, planes, expo, nonfinite);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         hipLaunchKernelGGL(ks, dim3((unsigned)p.npair, groups), dim3(SW_THR), lds, st, planes,
                            expo, p.npad, p.np, nchp, (int)((rows + SP_KT - 1) / SP_KT),
@@ -321,7 +348,8 @@ hipError_t sw_run(int64_t m, int64_t n, const T *A, int64_t lda, double *Mhi, do
     }
     const int64_t entries = (int64_t)p.npair * 16 * 64 * 4;
     hipLaunchKernelGGL(sw_reduce_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st,
-                       slots, (int)p.groups_per_pass, p.np, p.npair, (int)n, Mhi, Mlo, ldm);
+                       slots, (int)p.groups_per_pass, p.np, p.npair, (int)n, Mhi, Mlo, ldm,
+                       nonfinite);
     return hipGetLastError();
 }
 
@@ -368,6 +396,8 @@ SplitWidePlan split_wide_plan(int64_t m, int64_t n, int S, int64_t rows_cap) {
     off = sw_al(off + (size_t)(p.rows_per_pass / SW_SR) * p.npad * sizeof(int));
     p.slot_off = off;
     off = sw_al(off + (size_t)g * p.npair * 16 * 64 * 8 * sizeof(double));
+    p.flag_off = off;
+    off = sw_al(off + sizeof(int));
     p.part_bytes = off;
     return p;
 }

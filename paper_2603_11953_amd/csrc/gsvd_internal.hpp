@@ -95,7 +95,7 @@ struct SplitWidePlan {
     int64_t groups_per_pass; // 8192-row groups (one syrk workgroup row) per pass
     int64_t rows_per_pass;
     int64_t npass;
-    size_t plane_off, expo_off, slot_off, part_bytes;
+    size_t plane_off, expo_off, slot_off, flag_off, part_bytes;
 };
 // rows_cap > 0 caps the rows per pass (rounded down to a multiple of 8192, at least 8192)
 SplitWidePlan split_wide_plan(int64_t m, int64_t n, int S, int64_t rows_cap = 0);

@@ -84,15 +84,17 @@ def test_batched_equals_single_calls(dt, form, slab):
         assert np.array_equal(to_np(u1), U[k]), k
 
 
-def test_batched_info_codes_per_problem():
+@pytest.mark.parametrize("form", ["plain", "split"])
+def test_batched_info_codes_per_problem(form):
+    import paper_2603_11953_amd as gs
     specs = _specs(6100, "f64", (10, 24, 10, 24, 7), 5, 3000)
     As = [g.make_a(s) for s in specs]
     As[1][:, 3] = 0.0          # rank deficient: info 1
     As[2][17, 2] = np.nan      # non-finite: info 3
     As[4][5, 6] = np.inf       # non-finite: info 3
     As = [np.asfortranarray(A) for A in As]
-    say("batched info codes")
-    S, V, U, info = _run(As)
+    say("batched info codes", form)
+    S, V, U, info = _run(As, gram=gs.GSVD_GRAM_SPLIT if form == "split" else gs.GSVD_GRAM_PLAIN)
     assert list(info) == [0, 1, 3, 0, 3], info
     for k in (0, 3):
         check_thin(As[k], S[k], V[k], U[k], ref.svd(As[k]), label=f"problem {k}")

@@ -250,12 +250,18 @@ def test_info_zero_column_not_spd():
     assert _thin(np.asfortranarray(A))[3] == 1
 
 
-@pytest.mark.parametrize("bad", [np.nan, np.inf])
-def test_info_nonfinite(bad):
-    A = g.make_a(g.MatrixSpec(m=500, n=10, kappa_b=10, kappa_d=10, seed=9))
+@pytest.mark.parametrize("form", ["plain", "split"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_info_nonfinite(bad, dt, form):
+    """A NaN or Inf anywhere in A gives info 3, whichever Gram form (the split form cannot
+    cut it into digits and flags it)."""
+    import paper_2603_11953_amd as gs
+    A = g.make_a(g.MatrixSpec(m=500, n=10, kappa_b=10, kappa_d=10, seed=9, dtype=dt))
     A[123, 6] = bad
-    say("info nonfinite", bad)
-    assert _thin(np.asfortranarray(A))[3] == 3
+    say("info nonfinite", bad, dt, form)
+    gram = gs.GSVD_GRAM_SPLIT if form == "split" else gs.GSVD_GRAM_PLAIN
+    assert _thin(np.asfortranarray(A), gram=gram)[3] == 3
 
 
 def test_info_no_convergence():
@@ -289,7 +295,8 @@ def test_two_sided_jacobi_is_O_u_while_alg2_tracks_kappa_b():
         o = ref.svd(A)
         for mode, em in (("jacobi2", gs.GSVD_EIG_JACOBI2), ("alg2", gs.GSVD_EIG_CHOL_JACOBI1)):
             say("accuracy mode", mode, seed)
-            S, V, Uo, info = _thin(A, eig=em)
+            # the plain Gram: the comparison is between eigensolvers
+            S, V, Uo, info = _thin(A, eig=em, gram=gs.GSVD_GRAM_PLAIN)
             # Theorem 1's assumption eps_1 <= 1/2 is not met by FP32 at kappa(B) = 1e4:
             # the warning bit may be set, the results are complete
             assert info_ok(info), info
@@ -314,3 +321,30 @@ def test_full_size_fp32_workload(form):
     assert info == 0
     rows = np.random.default_rng(3).integers(0, spec.m, 20_000)
     check_thin(A, S, V, Uo, o, rows=rows, label=f"fp32 4e6x128 {form}")
+
+
+def test_wrappers_on_a_side_stream():
+    """The torch helpers run on a stream other than the current one: outputs, workspace and
+    info are allocated on that stream, and the results equal the current-stream call's bit
+    for bit."""
+    import paper_2603_11953_amd as gs
+    torch = _torch()
+    A = g.make_a(g.MatrixSpec(m=40_000, n=48, kappa_b=100, kappa_d=1e8, seed=77, shuffle=True,
+                              w1="gauss"))
+    dA = to_dev(A)
+    say("side stream")
+    ref_out = gs.thin(dA)
+    Mref = gs.gram(dA)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    out = gs.thin(dA, stream=s)
+    M = gs.gram(dA, stream=s)
+    E = gs.eig(M[0], M[1], gs.GSVD_F64, stream=s)
+    U = gs.u_recover(dA, E[2], stream=s)
+    s.synchronize()
+    for x, y in zip(out, ref_out):
+        assert torch.equal(x, y)
+    assert torch.equal(M[0], Mref[0]) and torch.equal(M[1], Mref[1])
+    assert torch.equal(E[0], ref_out[0]) and torch.equal(E[1], ref_out[1])
+    assert torch.equal(U, ref_out[2])

@@ -149,19 +149,24 @@ def test_wide_exact_spectrum_n512():
     assert ref.resid(E.A, Uo, S, V) <= 50 * 512 * u
 
 
-def test_wide_info_codes():
-    """Zero column -> 1 (M_h not positive definite), NaN -> 3, one sweep -> 2."""
+@pytest.mark.parametrize("form", ["plain", "split"])
+def test_wide_info_codes(form):
+    """Zero column -> 1 (M_h not positive definite), NaN or Inf -> 3 (also through the split
+    Gram, which flags them), one sweep -> 2."""
+    import paper_2603_11953_amd as gs
+    gram = gs.GSVD_GRAM_SPLIT if form == "split" else gs.GSVD_GRAM_PLAIN
     A = g.make_a(g.MatrixSpec(m=2000, n=160, kappa_b=100, kappa_d=1e4, seed=13, shuffle=True))
     Z = A.copy(order="F")
     Z[:, 77] = 0.0
-    say("wide info zero column")
-    assert _thin(Z)[3] == 1
-    Nn = A.copy(order="F")
-    Nn[5, 140] = np.nan
-    say("wide info nan")
-    assert _thin(Nn)[3] == 3
-    say("wide info max_sweeps=1")
-    assert _thin(A, max_sweeps=1)[3] == 2
+    say("wide info zero column", form)
+    assert _thin(Z, gram=gram)[3] == 1
+    for bad in (np.nan, np.inf):
+        Nn = A.copy(order="F")
+        Nn[5, 140] = bad
+        say("wide info nonfinite", bad, form)
+        assert _thin(Nn, gram=gram)[3] == 3
+    say("wide info max_sweeps=1", form)
+    assert _thin(A, max_sweeps=1, gram=gram)[3] == 2
 
 
 # ------------------------------------------------------------------ wide split Gram
