@@ -333,12 +333,12 @@ def test_wrappers_on_a_side_stream():
                               w1="gauss"))
     dA = to_dev(A)
     say("side stream")
-    ref_out = gs.thin(dA)
+    ref_out = gs.thin(dA, gram=gs.GSVD_GRAM_PLAIN)  # gram() and eig() below: the plain Gram
     Mref = gs.gram(dA)
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
-    out = gs.thin(dA, stream=s)
+    out = gs.thin(dA, gram=gs.GSVD_GRAM_PLAIN, stream=s)
     M = gs.gram(dA, stream=s)
     E = gs.eig(M[0], M[1], gs.GSVD_F64, stream=s)
     U = gs.u_recover(dA, E[2], stream=s)
