@@ -87,6 +87,8 @@ enum {
 #define GSVD_OK 0
 #define GSVD_ERR_HIP (-100)         /* a HIP launch or runtime call failed */
 #define GSVD_ERR_UNSUPPORTED (-101) /* valid but not implemented combination */
+#define GSVD_ERR_SCRATCH (-102)     /* gsvd_thin_noalloc: the problem's workspace exceeds
+                                       GSVD_NOALLOC_MAX_BYTES */
 
 /* asynchronous per-matrix info codes */
 #define GSVD_INFO_OK 0
@@ -255,6 +257,30 @@ int gsvd_thin_batched(int batch, const int64_t *hM, const int64_t *hN,
                       void *const *dS, void *const *dV, const int64_t *hLdv,
                       void *const *dU, const int64_t *hLdu,
                       void *work, size_t work_bytes, int *dInfo,
+                      const gsvd_opts *o, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * gsvd_thin_noalloc: gsvd_thin for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation, kernels and results as gsvd_thin with the
+ * same options, but the workspace is a fixed array inside the library, one per
+ * GPU, of GSVD_NOALLOC_MAX_BYTES bytes, held from library load until the process
+ * ends.  The caller passes inputs and outputs only.
+ *  - Allocates nothing and calls no allocating routine.  The first call on a
+ *    device looks up that device's copy of the array (hipGetSymbolAddress); the
+ *    call runs on the device current in the calling thread.
+ *  - Returns GSVD_ERR_SCRATCH, enqueueing nothing, when
+ *    gsvd_thin_workspace_size(m, n, o) exceeds GSVD_NOALLOC_MAX_BYTES (for the
+ *    wide split Gram, o->slab_rows caps its per-pass planes).
+ *  - Calls that overlap on one GPU (other streams, other host threads) share the
+ *    array and race: order them, e.g. on one stream.
+ * Arguments: 1 m, 2 n, 3 dA, 4 lda, 5 dS, 6 dV, 7 ldv, 8 dU, 9 ldu, 10 dInfo,
+ * 11 o, 12 stream; their meaning as in gsvd_thin.
+ * ------------------------------------------------------------------------- */
+#define GSVD_NOALLOC_MAX_BYTES (64u << 20)
+size_t gsvd_noalloc_max_bytes(void);
+int gsvd_thin_noalloc(int64_t m, int64_t n, const void *dA, int64_t lda,
+                      void *dS, void *dV, int64_t ldv, void *dU, int64_t ldu, int *dInfo,
                       const gsvd_opts *o, void *stream);
 
 #ifdef __cplusplus

@@ -23,7 +23,7 @@ __all__ = [
     "gsvd_opts_default", "gsvd_status_string", "gsvd_thin", "gsvd_thin_workspace_size",
     "gsvd_gram", "gsvd_gram_workspace_size", "gsvd_gram_config", "gram_config", "gsvd_eig", "gsvd_eig_workspace_size",
     "gsvd_u_recover", "gsvd_thin_batched", "gsvd_thin_batched_workspace_size", "thin_batched",
-    "Batch",
+    "Batch", "gsvd_thin_noalloc", "gsvd_noalloc_max_bytes", "GSVD_ERR_SCRATCH",
 ]
 
 GSVD_F32, GSVD_F64 = 0, 1
@@ -31,6 +31,7 @@ GSVD_GRAM_AUTO, GSVD_GRAM_PLAIN, GSVD_GRAM_SPLIT = 0, 1, 2
 GSVD_EIG_AUTO, GSVD_EIG_JACOBI2, GSVD_EIG_CHOL_JACOBI1 = 0, 1, 2
 GSVD_WANT_U = 1
 GSVD_MAX_N = 512
+GSVD_ERR_SCRATCH = -102
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libgsvd.so")
@@ -95,6 +96,10 @@ def _load() -> ctypes.CDLL:
     L.gsvd_thin_batched_workspace_size.restype = sz
     L.gsvd_thin_batched.argtypes = [ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, op, vp]
     L.gsvd_thin_batched.restype = ci
+    L.gsvd_noalloc_max_bytes.argtypes = []
+    L.gsvd_noalloc_max_bytes.restype = sz
+    L.gsvd_thin_noalloc.argtypes = [i64, i64, vp, i64, vp, vp, i64, vp, i64, vp, op, vp]
+    L.gsvd_thin_noalloc.restype = ci
     return L
 
 
@@ -112,6 +117,8 @@ gsvd_eig_workspace_size = lib.gsvd_eig_workspace_size
 gsvd_u_recover = lib.gsvd_u_recover
 gsvd_thin_batched = lib.gsvd_thin_batched
 gsvd_thin_batched_workspace_size = lib.gsvd_thin_batched_workspace_size
+gsvd_thin_noalloc = lib.gsvd_thin_noalloc
+gsvd_noalloc_max_bytes = lib.gsvd_noalloc_max_bytes
 
 
 def gsvd_status_string(code: int) -> str:

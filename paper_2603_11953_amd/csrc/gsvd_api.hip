@@ -90,6 +90,7 @@ const char *gsvd_status_string(int code) {
         case GSVD_INFO_WARN_ASSUMPTION | GSVD_INFO_WARN_REFINE: return "info 768 (warnings 256 and 512)";
         case GSVD_ERR_HIP: return "HIP launch or runtime error";
         case GSVD_ERR_UNSUPPORTED: return "option combination not implemented";
+        case GSVD_ERR_SCRATCH: return "workspace larger than the library's fixed scratch array (gsvd_thin_noalloc)";
         default: break;
     }
     if (code < 0 && code > -100) return "invalid argument (the value is minus its 1-based position)";

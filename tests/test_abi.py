@@ -298,3 +298,22 @@ def test_auto_gram_form():
     o_split = gs.opts(gs.GSVD_F64, gs.GSVD_GRAM_SPLIT)
     assert (gs.gsvd_thin_workspace_size(1_000_000, 64, ctypes.byref(o_auto)) ==
             gs.gsvd_thin_workspace_size(1_000_000, 64, ctypes.byref(o_split)))
+
+
+@fake_pointers
+def test_noalloc_rejects_oversized_and_bad_arguments():
+    """gsvd_thin_noalloc refuses, before touching any device, a problem whose workspace
+    exceeds its fixed array (GSVD_ERR_SCRATCH) and bad arguments (-k)."""
+    assert gs.gsvd_noalloc_max_bytes() == 64 << 20
+    o = gs.opts(gs.GSVD_F64)
+    assert gs.gsvd_thin_workspace_size(2_000_000, 512, ctypes.byref(o)) > 64 << 20
+    rc = gs.gsvd_thin_noalloc(2_000_000, 512, FAKE, 2_000_000, FAKE, FAKE, 512, FAKE, 2_000_000,
+                              FAKE, ctypes.byref(o), None)
+    assert rc == gs.GSVD_ERR_SCRATCH == -102
+    assert "scratch" in gs.gsvd_status_string(rc)
+    assert gs.gsvd_thin_noalloc(100, 8, None, 100, FAKE, FAKE, 8, FAKE, 100, FAKE,
+                                ctypes.byref(o), None) == -3
+    assert gs.gsvd_thin_noalloc(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 100, None,
+                                ctypes.byref(o), None) == -10
+    assert gs.gsvd_thin_noalloc(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 100, FAKE, None,
+                                None) == -11
