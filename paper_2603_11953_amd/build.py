@@ -21,6 +21,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libgsvd.so")
+PROBE_SRC = os.path.join(HERE, "probe", "peaks.hip")
+PROBE_LIB = os.path.join(HERE, "libgsvd_peaks.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -62,6 +64,10 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    # the throughput probes behind the measured ceilings (not part of the library)
+    subprocess.run([HIPCC, *CFLAGS, "-shared", "-o", PROBE_LIB + ".tmp", PROBE_SRC], check=True,
+                   capture_output=True)
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
 
