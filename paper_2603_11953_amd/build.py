@@ -65,8 +65,9 @@ def build(verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     # the throughput probes behind the measured ceilings (not part of the library)
-    subprocess.run([HIPCC, *CFLAGS, "-shared", "-o", PROBE_LIB + ".tmp", PROBE_SRC], check=True,
-                   capture_output=True)
+    # (the VGPR form of the MFMA keeps the probe's accumulators out of register moves)
+    subprocess.run([HIPCC, *CFLAGS, "-mllvm", "-amdgpu-mfma-vgpr-form", "-shared", "-o",
+                    PROBE_LIB + ".tmp", PROBE_SRC], check=True, capture_output=True)
     os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
