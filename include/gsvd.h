@@ -260,6 +260,28 @@ int gsvd_thin_batched(int batch, const int64_t *hM, const int64_t *hN,
                       const gsvd_opts *o, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Mixed precision Cholesky QR (Sec. 3.3, Theorem 3): the method's Gram stage
+ * reused for a thin QR factorization A = Q R.
+ *   M_h = A^T A at u_h                (as gsvd_gram, in the form o->gram selects)
+ *   M_h = R_h^T R_h at u_h            (Cholesky: double-double for FP64 A, of the
+ *                                      power-of-two column-scaled Gram, scaled back)
+ *   R = fl(R_h), Q from Q R = A at u  (row-wise forward substitution)
+ * Theorem 3: with u_h = O(u^2) (both working precisions here) the loss of
+ * orthogonality ||Q^T Q - I|| is O(u) kappa(B), A = B D with B of unit columns.
+ * Outputs: dQ (m x n, ldq >= m) and dR (n x n upper triangular with zeros below,
+ * ldr >= n) in the working precision; *dInfo = 0, 1 (M_h not positive definite
+ * at u_h: A not of full column rank) or 3 (non-finite input); Q is not written
+ * when info != 0.  Conventions as gsvd_thin (device pointers, caller's
+ * workspace of gsvd_cholqr_workspace_size bytes, no allocation or host sync).
+ * Arguments: 1 m, 2 n, 3 dA, 4 lda, 5 dQ, 6 ldq, 7 dR, 8 ldr, 9 work,
+ * 10 work_bytes, 11 dInfo, 12 o, 13 stream.
+ * ------------------------------------------------------------------------- */
+size_t gsvd_cholqr_workspace_size(int64_t m, int64_t n, const gsvd_opts *o);
+int gsvd_cholqr(int64_t m, int64_t n, const void *dA, int64_t lda, void *dQ, int64_t ldq,
+                void *dR, int64_t ldr, void *work, size_t work_bytes, int *dInfo,
+                const gsvd_opts *o, void *stream);
+
+/* ---------------------------------------------------------------------------
  * gsvd_thin_noalloc: gsvd_thin for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same computation, kernels and results as gsvd_thin with the

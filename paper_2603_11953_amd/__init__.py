@@ -23,7 +23,7 @@ __all__ = [
     "gsvd_opts_default", "gsvd_status_string", "gsvd_thin", "gsvd_thin_workspace_size",
     "gsvd_gram", "gsvd_gram_workspace_size", "gsvd_gram_config", "gram_config", "gsvd_eig", "gsvd_eig_workspace_size",
     "gsvd_u_recover", "gsvd_thin_batched", "gsvd_thin_batched_workspace_size", "thin_batched",
-    "Batch", "gsvd_thin_noalloc", "gsvd_noalloc_max_bytes", "GSVD_ERR_SCRATCH",
+    "Batch", "gsvd_cholqr", "gsvd_cholqr_workspace_size", "cholqr", "gsvd_thin_noalloc", "gsvd_noalloc_max_bytes", "GSVD_ERR_SCRATCH",
 ]
 
 GSVD_F32, GSVD_F64 = 0, 1
@@ -96,6 +96,10 @@ def _load() -> ctypes.CDLL:
     L.gsvd_thin_batched_workspace_size.restype = sz
     L.gsvd_thin_batched.argtypes = [ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, op, vp]
     L.gsvd_thin_batched.restype = ci
+    L.gsvd_cholqr_workspace_size.argtypes = [i64, i64, op]
+    L.gsvd_cholqr_workspace_size.restype = sz
+    L.gsvd_cholqr.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp, op, vp]
+    L.gsvd_cholqr.restype = ci
     L.gsvd_noalloc_max_bytes.argtypes = []
     L.gsvd_noalloc_max_bytes.restype = sz
     L.gsvd_thin_noalloc.argtypes = [i64, i64, vp, i64, vp, vp, i64, vp, i64, vp, op, vp]
@@ -118,6 +122,8 @@ gsvd_u_recover = lib.gsvd_u_recover
 gsvd_thin_batched = lib.gsvd_thin_batched
 gsvd_thin_batched_workspace_size = lib.gsvd_thin_batched_workspace_size
 gsvd_thin_noalloc = lib.gsvd_thin_noalloc
+gsvd_cholqr = lib.gsvd_cholqr
+gsvd_cholqr_workspace_size = lib.gsvd_cholqr_workspace_size
 gsvd_noalloc_max_bytes = lib.gsvd_noalloc_max_bytes
 
 
@@ -229,6 +235,28 @@ def thin(A, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, want_u: boo
                            info.data_ptr(), ctypes.byref(o), _stream(stream))
     _check(rc, "gsvd_thin")
     return S, V, U, info
+
+
+def cholqr(A, *, gram: int = GSVD_GRAM_AUTO, n_slices: int = 0, target_rel_err: float = 0.0,
+           kappa_b: float = 0.0, stream=None):
+    """Mixed precision Cholesky QR of a column-major CUDA tensor A (m x n): returns
+    (Q, R, info) with Q m x n and R n x n upper triangular in A's precision."""
+    torch = _torch()
+    w = _working_of(A)
+    m, n = int(A.shape[0]), int(A.shape[1])
+    lda = _ld(A)
+    o = opts(w, gram, n_slices=n_slices, target_rel_err=target_rel_err, kappa_b=kappa_b)
+    with _on(stream):
+        Q = colmajor_empty(m, n, A.dtype, A.device)
+        R = colmajor_empty(n, n, A.dtype, A.device)
+        info = torch.full((1,), -1, dtype=torch.int32, device=A.device)
+        need = lib.gsvd_cholqr_workspace_size(m, n, ctypes.byref(o))
+        work = workspace(need, A.device)
+        rc = lib.gsvd_cholqr(m, n, A.data_ptr(), lda, Q.data_ptr(), m, R.data_ptr(), n,
+                             work.data_ptr(), work.numel(), info.data_ptr(), ctypes.byref(o),
+                             _stream(stream))
+    _check(rc, "gsvd_cholqr")
+    return Q, R, info
 
 
 def gram(A, *, work=None, stream=None):

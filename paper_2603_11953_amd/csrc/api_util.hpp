@@ -319,6 +319,29 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
                          eig_mode_of(o) == GSVD_EIG_CHOL_JACOBI1, st);
 }
 
+// The Gram stage (Alg. 1 steps 1-2) in the form the options select.
+inline hipError_t gram_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A, int64_t lda,
+                    double *Mhi, double *Mlo, int64_t ldm, void *part, hipStream_t st) {
+    if (wide_n(n) && use_split(o)) {
+        SplitWidePlan p = split_wide_plan(m, n, slices_of(o, n), o->slab_rows);
+        return split_wide_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
+    }
+    if (wide_n(n)) {
+        WidePlan p = gram_wide_plan(m, n, o->slab_rows);
+        return gram_wide_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
+    }
+    if (use_split(o)) {
+        SplitPlan p = split_plan_of(o, m, n, false);
+        return split_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
+    }
+    if (f32_mfma(o, n, false)) {
+        F32MfmaPlan p = f32mfma_plan_of(o, m, n);
+        return gram_f32mfma_launch(m, n, (const float *)A, lda, Mhi, Mlo, ldm, part, p, st);
+    }
+    GramPlan p = gram_plan_of(o, m, n, false);
+    return gram_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
+}
+
 inline hipError_t urecover_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A,
                                int64_t lda, const void *W, int64_t ldw, void *U, int64_t ldu,
                                hipStream_t st) {

@@ -578,6 +578,36 @@ weig_out_kernel(int n, const Ctl *ctl, const double *__restrict__ Vw,
     if (threadIdx.x == 0) S[pos] = sp;
 }
 
+// The blocked dd Cholesky of H (upper triangle of Hh/Hl, in place).
+hipError_t chol_blocked(int n, Ctl *ctl, double *Hh, double *Hl, hipStream_t st) {
+    hipError_t err;
+    const size_t lds_potrf = (size_t)CB * CB * sizeof(dd_t);
+    const size_t lds_panel = (size_t)CB * (CB + 16) * sizeof(dd_t);
+    const size_t lds_update = (size_t)2 * CB * 32 * sizeof(dd_t);
+    if ((err = hipFuncSetAttribute((const void *)weig_potrf_kernel,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_potrf)) ||
+        (err = hipFuncSetAttribute((const void *)weig_panel_kernel,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_panel)) ||
+        (err = hipFuncSetAttribute((const void *)weig_update_kernel,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_update)))
+        return err;
+    for (int k0 = 0; k0 < n; k0 += CB) {
+        hipLaunchKernelGGL(weig_potrf_kernel, dim3(1), dim3(1024), lds_potrf, st, n, k0, ctl, Hh, Hl);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        const int right = n - (k0 + CB);
+        if (right > 0) {
+            hipLaunchKernelGGL(weig_panel_kernel, dim3((unsigned)((right + 15) / 16)), dim3(1024),
+                               lds_panel, st, n, k0, ctl, Hh, Hl);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+            const int nt = (right + 31) / 32;
+            hipLaunchKernelGGL(weig_update_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(UT),
+                               lds_update, st, n, k0, nt, ctl, Hh, Hl);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
+    }
+    return hipSuccess;
+}
+
 template <int RPL>
 hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double tol2,
                         int max_sweeps, hipStream_t st) {
@@ -599,7 +629,54 @@ hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double
     return hipSuccess;
 }
 
+// ---- the Cholesky factor alone (mixed precision Cholesky QR, Sec. 3.3)
+
+// R = fl_w(R_H) D~ in the working precision (exact power-of-two column scaling),
+// zeros below the diagonal; info from the checks and the factorization.
+template <typename TW>
+__global__ void __launch_bounds__(256)
+chol_out_kernel(int n, const Ctl *ctl, const int *__restrict__ sexp,
+                const double *__restrict__ Hh, TW *__restrict__ R, int64_t ldr,
+                int *__restrict__ info) {
+    const int bad = wg_read(&ctl->bad);
+    const int j = blockIdx.x;
+    if (j == 0 && threadIdx.x == 0) *info = bad;
+    if (bad) return;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        R[i + (int64_t)j * ldr] = i <= j ? (TW)ldexp(Hh[i + (size_t)j * n], sexp[j]) : (TW)0;
+}
+
 }  // namespace
+
+size_t chol_work_bytes(int64_t n) { return wlayout(n).total; }
+
+hipError_t chol_launch(int working, int64_t n64, const double *Mhi, const double *Mlo, int64_t ldm,
+                       void *R, int64_t ldr, int *info, void *work, hipStream_t st) {
+    if (n64 < 1 || n64 > GSVD_WIDE_MAX_N || Mlo == nullptr || work == nullptr || ldr < n64)
+        return hipErrorInvalidValue;
+    const int n = (int)n64;
+    const WLayout L = wlayout(n);
+    char *base = (char *)work;
+    Ctl *ctl = reinterpret_cast<Ctl *>(base + L.ctl);
+    int *sexp = reinterpret_cast<int *>(base + L.sexp);
+    double *Hh = reinterpret_cast<double *>(base + L.hh);
+    double *Hl = reinterpret_cast<double *>(base + L.hl);
+    double *Vw = reinterpret_cast<double *>(base + L.v);
+    hipError_t err;
+    hipLaunchKernelGGL(weig_diag_kernel, dim3(1), dim3(1024), 0, st, n, Mhi, ldm, ctl, sexp);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(weig_fill_kernel, dim3((unsigned)n), dim3(256), 0, st, n, Mhi, Mlo, ldm, ctl,
+                       sexp, Hh, Hl, Vw);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = chol_blocked(n, ctl, Hh, Hl, st)) != hipSuccess) return err;
+    if (working == 1)
+        hipLaunchKernelGGL(chol_out_kernel<double>, dim3((unsigned)n), dim3(256), 0, st, n, ctl,
+                           sexp, Hh, (double *)R, ldr, info);
+    else
+        hipLaunchKernelGGL(chol_out_kernel<float>, dim3((unsigned)n), dim3(256), 0, st, n, ctl,
+                           sexp, Hh, (float *)R, ldr, info);
+    return hipGetLastError();
+}
 
 size_t eig_wide_work_bytes(int64_t n) { return wlayout(n).total; }
 
@@ -631,30 +708,7 @@ hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, in
     hipLaunchKernelGGL(weig_fill_kernel, dim3((unsigned)n), dim3(256), 0, st, n, Mhi, Mlo, ldm, ctl,
                        sexp, Hh, Hl, Vw);
     WCHK();
-    const size_t lds_potrf = (size_t)CB * CB * sizeof(dd_t);
-    const size_t lds_panel = (size_t)CB * (CB + 16) * sizeof(dd_t);
-    const size_t lds_update = (size_t)2 * CB * 32 * sizeof(dd_t);
-    if ((err = hipFuncSetAttribute((const void *)weig_potrf_kernel,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_potrf)) ||
-        (err = hipFuncSetAttribute((const void *)weig_panel_kernel,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_panel)) ||
-        (err = hipFuncSetAttribute((const void *)weig_update_kernel,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_update)))
-        return err;
-    for (int k0 = 0; k0 < n; k0 += CB) {
-        hipLaunchKernelGGL(weig_potrf_kernel, dim3(1), dim3(1024), lds_potrf, st, n, k0, ctl, Hh, Hl);
-        WCHK();
-        const int right = n - (k0 + CB);
-        if (right > 0) {
-            hipLaunchKernelGGL(weig_panel_kernel, dim3((unsigned)((right + 15) / 16)), dim3(1024),
-                               lds_panel, st, n, k0, ctl, Hh, Hl);
-            WCHK();
-            const int nt = (right + 31) / 32;
-            hipLaunchKernelGGL(weig_update_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(UT),
-                               lds_update, st, n, k0, nt, ctl, Hh, Hl);
-            WCHK();
-        }
-    }
+    if ((err = chol_blocked(n, ctl, Hh, Hl, st)) != hipSuccess) return err;
     hipLaunchKernelGGL(weig_cast_kernel, dim3((unsigned)n), dim3(256), 0, st, n, ctl, sexp, Hh, X);
     WCHK();
     const int nbb = (n + JB - 1) / JB;

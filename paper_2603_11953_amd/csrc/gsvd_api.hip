@@ -16,28 +16,6 @@ using namespace gsvd;
 
 namespace {
 
-hipError_t gram_any(const gsvd_opts *o, int64_t m, int64_t n, const void *A, int64_t lda,
-                    double *Mhi, double *Mlo, int64_t ldm, void *part, hipStream_t st) {
-    if (wide_n(n) && use_split(o)) {
-        SplitWidePlan p = split_wide_plan(m, n, slices_of(o, n), o->slab_rows);
-        return split_wide_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
-    }
-    if (wide_n(n)) {
-        WidePlan p = gram_wide_plan(m, n, o->slab_rows);
-        return gram_wide_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
-    }
-    if (use_split(o)) {
-        SplitPlan p = split_plan_of(o, m, n, false);
-        return split_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
-    }
-    if (f32_mfma(o, n, false)) {
-        F32MfmaPlan p = f32mfma_plan_of(o, m, n);
-        return gram_f32mfma_launch(m, n, (const float *)A, lda, Mhi, Mlo, ldm, part, p, st);
-    }
-    GramPlan p = gram_plan_of(o, m, n, false);
-    return gram_launch(o->working, m, n, A, lda, Mhi, Mlo, ldm, part, p, st);
-}
-
 struct ThinLayout {
     size_t mhi, mlo, w, eigw, part, total;
 };

@@ -155,6 +155,14 @@ hipError_t eig_wide_launch(int64_t n, const double *Mhi, const double *Mlo, int6
                            void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
                            int max_sweeps, void *work, hipStream_t st);
 
+// Cholesky factor of M_h alone (eig_wide.hip; any n <= 512): the scaled blocked dd
+// Cholesky of Algorithm 2's first step, R = fl_w(R_H) D~ written upper triangular
+// (zeros below) in the working precision; *info = 0, 1 (not positive definite) or
+// 3 (non-finite).  Mlo must be non-null.
+size_t chol_work_bytes(int64_t n);
+hipError_t chol_launch(int working, int64_t n, const double *Mhi, const double *Mlo, int64_t ldm,
+                       void *R, int64_t ldr, int *info, void *work, hipStream_t st);
+
 // Two-sided Jacobi eigensolver for FP32 working (eig_jacobi2.hip).  V needs
 // j2_work_bytes(n, max_sweeps) of device scratch (0 while it fits LDS, n <= 96; beyond,
 // the rotations are logged and V is formed from the log afterwards).
@@ -193,6 +201,12 @@ hipError_t fill_zero_launch(double *p, size_t n, hipStream_t st);
 hipError_t cast_eig_f32_launch(int64_t n, const double *S64, const double *V64, void *S, void *V,
                                int64_t ldv, void *W, int64_t ldw, const int *info,
                                hipStream_t st);
+
+// Q from Q R = A, R upper triangular (cholqr.hip): row-wise forward substitution in
+// the working precision; nothing runs when *info != 0.
+hipError_t trsm_rows_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
+                            const void *R, int64_t ldr, void *Q, int64_t ldq, const int *info,
+                            hipStream_t st);
 
 // U = A W (urecover.hip).
 hipError_t urecover_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,

@@ -38,9 +38,12 @@ __global__ void __launch_bounds__(256) probe_mfma64_kernel(int iters, double see
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
     const double a = seed + threadIdx.x * 1e-9, b = 1.0 - seed;
-    for (int i = 0; i < iters; ++i) {
+    // 8 steps per trip so that the compiler's register moves at the loop edge are amortised
+    for (int i = 0; i < iters; i += 8) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
     }
     double s = 0.0;
 #pragma unroll
@@ -53,9 +56,12 @@ __global__ void __launch_bounds__(256) probe_mfma32_kernel(int iters, float seed
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const float a = seed + threadIdx.x * 1e-6f, b = 1.0f - seed;
-    for (int i = 0; i < iters; ++i) {
+    // 8 steps per trip so that the compiler's register moves at the loop edge are amortised
+    for (int i = 0; i < iters; i += 8) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
     }
     float s = 0.f;
 #pragma unroll
@@ -69,9 +75,12 @@ __global__ void __launch_bounds__(256) probe_mfma_i8_kernel(int iters, int seed,
     for (int c = 0; c < 4; ++c) acc[c] = i32x4{0, 0, 0, 0};
     const i32x4 a = i32x4{seed + (int)threadIdx.x, seed, 1, 2};
     const i32x4 b = i32x4{3, seed ^ 5, 7, (int)threadIdx.x};
-    for (int i = 0; i < iters; ++i) {
+    // 8 steps per trip so that the compiler's register moves at the loop edge are amortised
+    for (int i = 0; i < iters; i += 8) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[c], 0, 0, 0);
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[c], 0, 0, 0);
     }
     int s = 0;
 #pragma unroll

@@ -317,3 +317,20 @@ def test_noalloc_rejects_oversized_and_bad_arguments():
                                 ctypes.byref(o), None) == -10
     assert gs.gsvd_thin_noalloc(100, 8, FAKE, 100, FAKE, FAKE, 8, FAKE, 100, FAKE, None,
                                 None) == -11
+
+
+@fake_pointers
+def test_cholqr_arguments():
+    o = gs.opts(gs.GSVD_F64)
+    assert gs.gsvd_cholqr_workspace_size(1000, 64, ctypes.byref(o)) % 256 == 0
+    assert gs.gsvd_cholqr_workspace_size(1000, 64, ctypes.byref(o)) > 2 * 64 * 64 * 8
+    a = dict(m=100, n=8, A=FAKE, lda=100, Q=FAKE, ldq=100, R=FAKE, ldr=8, work=FAKE,
+             wb=1 << 40, info=FAKE)
+    for k, v, code in (("m", 0, -1), ("n", 0, -2), ("A", None, -3), ("lda", 50, -4),
+                       ("Q", None, -5), ("ldq", 50, -6), ("R", None, -7), ("ldr", 7, -8),
+                       ("work", FAKE + 8, -9), ("wb", 10, -10), ("info", None, -11)):
+        b = dict(a)
+        b[k] = v
+        rc = gs.gsvd_cholqr(b["m"], b["n"], b["A"], b["lda"], b["Q"], b["ldq"], b["R"], b["ldr"],
+                            b["work"], b["wb"], b["info"], ctypes.byref(o), None)
+        assert rc == code, (k, rc, code)

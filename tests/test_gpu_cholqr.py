@@ -1,0 +1,97 @@
+"""Mixed precision Cholesky QR (Sec. 3.3, Theorem 3) against the oracle: R against the
+oracle's double-double Cholesky factor of the dd Gram, ||Q^T Q - I|| within Theorem 3's
+O(u) kappa(B) (u_h = O(u^2)) whatever kappa(A), and the residual ||A - Q R|| / ||A||."""
+import numpy as np
+import pytest
+
+from gen import matrices as g
+from oracle import ref
+from tests.helpers import say, to_dev, to_np, u_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _qr(A, **kw):
+    import torch
+
+    import paper_2603_11953_amd as gs
+    Q, R, info = gs.cholqr(to_dev(A), **kw)
+    torch.cuda.synchronize()
+    return to_np(Q), to_np(R), int(info.item())
+
+
+CASES = [
+    g.MatrixSpec(m=2000, n=20, kappa_b=10, kappa_d=1e8, seed=501),
+    g.MatrixSpec(m=20_000, n=48, kappa_b=1e3, kappa_d=1e12, mode_b=3, mode_d=3, seed=502,
+                 shuffle=True),
+    g.MatrixSpec(m=50_001, n=64, kappa_b=100, kappa_d=1e10, mode_b=5, mode_d=3, seed=503,
+                 shuffle=True, w1="gauss"),
+    g.MatrixSpec(m=30_000, n=200, kappa_b=1e3, kappa_d=1e12, mode_b=3, mode_d=3, seed=504,
+                 shuffle=True, w1="gauss"),
+    g.MatrixSpec(m=20_000, n=33, kappa_b=100, kappa_d=1e6, seed=505, dtype="f32"),
+    g.MatrixSpec(m=40_000, n=130, kappa_b=100, kappa_d=1e6, seed=506, dtype="f32", w1="gauss"),
+]
+
+
+@pytest.mark.parametrize("spec", CASES, ids=["m2000n20", "n48-kb1e3", "n64-mode5", "n200-kb1e3",
+                                             "f32-n33", "f32-n130"])
+@pytest.mark.parametrize("form", ["plain", "split"])
+def test_cholqr_against_oracle(spec, form):
+    import paper_2603_11953_amd as gs
+    A = g.make_a(spec)
+    m, n = A.shape
+    u = u_of(A)
+    Mhi, Mlo = ref.gram_dd(A)
+    Rh, Rl, oinfo = ref.chol_dd(Mhi, Mlo)
+    assert oinfo == 0
+    kb = ref.kappa_b(Mhi, Mlo)
+    say("cholqr", m, n, spec.dtype, form)
+    gram = gs.GSVD_GRAM_SPLIT if form == "split" else gs.GSVD_GRAM_PLAIN
+    Q, R, info = _qr(A, gram=gram)
+    assert info == 0
+    R64 = R.astype(np.float64)
+    # R: the rounding of the u_h Cholesky factor, upper triangular.  The Gram's own error
+    # (scaled: |dM_ij| <= eps sqrt(m_ii m_jj)) moves R_H by about n eps kappa(B)^2
+    # relative: eps = u_h for the plain Gram, the a-priori 2^(12 - 8 S) for S slices.
+    assert np.all(np.tril(R64, -1) == 0.0)
+    Rex = Rh + Rl
+    if form == "plain":
+        eps = 2.0 ** -104 if spec.dtype == "f64" else 2.0 ** -53
+    else:
+        S = gs.gram_config(m, n, gs.GSVD_F64 if spec.dtype == "f64" else gs.GSVD_F32,
+                           gs.GSVD_GRAM_SPLIT)["n_slices"]
+        eps = 2.0 ** (12 - 8 * S)
+    tol = 4 * u + 8 * n * eps * kb * kb
+    assert np.all(np.abs(R64 - Rex) <= tol * np.abs(np.diag(Rex))[None, :] + 1e-300), \
+        float(np.max(np.abs(R64 - Rex) / np.abs(np.diag(Rex))[None, :]))
+    # Theorem 3: ||Q^T Q - I|| = O(u) kappa(B) with u_h = O(u^2)
+    orth = ref.orth(np.asfortranarray(Q))
+    assert orth <= 50 * n * u * kb, (orth, 50 * n * u * kb, kb)
+    rows = np.unique(np.r_[0, m - 1, np.random.default_rng(1).integers(0, m, 3000)])
+    res = ref.resid(np.asfortranarray(A[rows]), np.asfortranarray(Q[rows]), np.ones(n, A.dtype),
+                    np.asfortranarray(R.T))
+    assert res <= 50 * n * u, res
+
+
+def test_cholqr_orthogonality_tracks_kappa_b_not_kappa_a():
+    """At fixed kappa(B) the loss of orthogonality does not grow with kappa(D) (so kappa(A))."""
+    orths = []
+    for kd in (1.0, 1e6, 1e12):
+        A = g.make_a(g.MatrixSpec(m=10_000, n=40, kappa_b=300, kappa_d=kd, mode_b=3, mode_d=3,
+                                  seed=507, shuffle=True))
+        say("cholqr kappa_d", kd)
+        Q, R, info = _qr(A)
+        assert info == 0
+        orths.append(ref.orth(np.asfortranarray(Q)))
+    assert max(orths) <= 20 * min(orths) + 1e-15, orths
+
+
+@pytest.mark.parametrize("bad", [0.0, np.nan])
+def test_cholqr_info(bad):
+    A = g.make_a(g.MatrixSpec(m=500, n=10, kappa_b=10, kappa_d=10, seed=508))
+    if bad == 0.0:
+        A[:, 4] = 0.0
+    else:
+        A[77, 3] = bad
+    say("cholqr info", bad)
+    assert _qr(np.asfortranarray(A))[2] == (1 if bad == 0.0 else 3)
