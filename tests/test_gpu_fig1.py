@@ -1,0 +1,99 @@
+"""The accuracy study of Sec. 4.1.1 (Fig. 1) on the GPU path, for both eigensolvers and both
+working precisions.
+
+Test matrices as the paper builds them (Tables 2-3): n = 64, m = 16 n, A = B D with D and the
+singular values of B from DLATM1 modes, B with unit columns; kappa(B) in {10, 1e2, 1e3, 1e4,
+1e5} x kappa(D) in {1, 1e2, 1e4, 1e6, 1e8} x the 16 (MODE of D, MODE of Sigma) pairs of
+Table 2: 400 matrices per working precision, run through gsvd_thin_batched with the plain
+higher-precision Gram.  The reference sigma is the oracle's (dd Gram, dd Jacobi) of each
+stored matrix, and kappa(B) the oracle's.
+
+Asserted, per matrix:
+  * Theorem 1 with the two-sided Jacobi on M_h (Remark 1):
+    err <= 4 u + 4 (n^2 + n) u_h kappa(B)^2, the shape of eq. (thm:highaccuracy_sv) with
+    eps_sqrt, eps_eig = O(u) and eps_M, eps_eigM = O(u_h), unit constants;
+  * Algorithm 2 (the remark after Lemma 1): err <= n u kappa(B) + 4 (n^2 + n) u_h kappa(B)^2;
+  * both: the tolerance 50 n u kappa(B).
+Asserted over the grid: at kappa(B) <= 100 the two-sided Jacobi is the more accurate (median),
+as the paper observes in the first two panels of Fig. 1; along kappa(D) (so kappa(A)) the
+error does not grow (median over the 16 MODE pairs at each kappa(D) within a factor 10 of the
+smallest).  The curves are printed (max and median error per kappa(B) and kappa(D)).
+"""
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from gen import matrices as g
+from oracle import ref
+from tests.helpers import say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+N, M = 64, 16 * 64
+KB = (10.0, 1e2, 1e3, 1e4, 1e5)
+KD = (1.0, 1e2, 1e4, 1e6, 1e8)
+MODES = [(1, 2), (1, 3), (1, 4), (1, 5), (2, 3), (2, 4), (2, 5), (3, 2), (3, 4), (3, 5),
+         (4, 2), (4, 3), (4, 5), (5, 2), (5, 3), (5, 4)]  # (MODE of D, MODE of Sigma), Table 2
+
+
+def _grid(dtype):
+    specs = []
+    for ib, kb in enumerate(KB):
+        for idd, kd in enumerate(KD):
+            for im, (md, ms) in enumerate(MODES):
+                specs.append(g.MatrixSpec(m=M, n=N, kappa_b=kb, kappa_d=kd, mode_b=ms, mode_d=md,
+                                          seed=60_000 + 1000 * ib + 100 * idd + im, dtype=dtype))
+    return specs
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fig1_accuracy_grid(dtype):
+    import torch
+
+    import paper_2603_11953_amd as gs
+    specs = _grid(dtype)
+    with ThreadPoolExecutor(8) as ex:
+        As = list(ex.map(g.make_a, specs))
+    u = 2.0 ** -24 if dtype == "f32" else 2.0 ** -53
+    u_h = 2.0 ** -53 if dtype == "f32" else 2.0 ** -104
+    errs = {}
+    for mode, em in (("jacobi2", gs.GSVD_EIG_JACOBI2), ("alg2", gs.GSVD_EIG_CHOL_JACOBI1)):
+        say("fig1", dtype, mode, len(As))
+        b = gs.Batch([to_dev(A) for A in As], gram=gs.GSVD_GRAM_PLAIN, eig=em, want_u=False)
+        b.run()
+        torch.cuda.synchronize()
+        info = b.info.cpu().numpy()
+        assert np.all((info & 0xFF) == 0), (mode, np.nonzero(info & 0xFF))
+        errs[mode] = [to_np(s).astype(np.float64) for s in b.S]
+        del b
+    with ThreadPoolExecutor(8) as ex:
+        oracles = list(ex.map(ref.svd, As))
+    kbs, out = [], {"jacobi2": [], "alg2": []}
+    for k, A in enumerate(As):
+        o = oracles[k]
+        kb = o.kappa_b
+        kbs.append(kb)
+        hi = 4.0 * (N * N + N) * u_h * kb * kb
+        for mode in ("jacobi2", "alg2"):
+            e = float(ref.sigma_rel_err(errs[mode][k], o).max())
+            out[mode].append(e)
+            bound = (4 * u if mode == "jacobi2" else N * u * kb) + hi
+            assert e <= bound, (dtype, mode, specs[k], kb, e, bound)
+            assert e <= 50 * N * u * kb, (dtype, mode, specs[k], e)
+    kbs = np.array(kbs)
+    E = {m: np.array(v).reshape(len(KB), len(KD), len(MODES)) for m, v in out.items()}
+    lines = [f"[fig1] {dtype}: max / median sigma error per kappa(B) (rows) and kappa(D) (cols)"]
+    for mode in ("jacobi2", "alg2"):
+        for ib, kb in enumerate(KB):
+            cells = " ".join(f"{E[mode][ib, idd].max():8.1e}/{np.median(E[mode][ib, idd]):8.1e}"
+                             for idd in range(len(KD)))
+            lines.append(f"[fig1] {dtype} {mode:8s} kB={kb:7.0e}: {cells}")
+    print("\n".join(lines), file=sys.stderr, flush=True)
+    for ib, kb in enumerate(KB):
+        for mode in ("jacobi2", "alg2"):
+            med = np.median(E[mode][ib], axis=1)  # per kappa(D), over the 16 MODE pairs
+            assert med.max() <= 10 * med.min() + 4 * u, (dtype, mode, kb, med)
+        if kb <= 100:
+            assert np.median(E["jacobi2"][ib]) <= np.median(E["alg2"][ib]), (dtype, kb)
