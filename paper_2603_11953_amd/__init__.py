@@ -23,7 +23,7 @@ __all__ = [
     "gsvd_opts_default", "gsvd_status_string", "gsvd_thin", "gsvd_thin_workspace_size",
     "gsvd_gram", "gsvd_gram_workspace_size", "gsvd_gram_config", "gram_config", "gsvd_eig", "gsvd_eig_workspace_size",
     "gsvd_u_recover", "gsvd_thin_batched", "gsvd_thin_batched_workspace_size", "thin_batched",
-    "Batch", "gsvd_cholqr", "gsvd_cholqr_workspace_size", "cholqr", "gsvd_thin_noalloc", "gsvd_noalloc_max_bytes", "GSVD_ERR_SCRATCH",
+    "Batch", "gsvd_cholqr", "gsvd_cholqr_workspace_size", "cholqr", "gsvd_thin_noalloc", "gsvd_noalloc_max_bytes", "GSVD_ERR_SCRATCH", "GSVD_INFO_WARN_ASSUMPTION", "GSVD_INFO_WARN_REFINE",
 ]
 
 GSVD_F32, GSVD_F64 = 0, 1
@@ -32,6 +32,7 @@ GSVD_EIG_AUTO, GSVD_EIG_JACOBI2, GSVD_EIG_CHOL_JACOBI1 = 0, 1, 2
 GSVD_WANT_U = 1
 GSVD_MAX_N = 512
 GSVD_ERR_SCRATCH = -102
+GSVD_INFO_WARN_ASSUMPTION, GSVD_INFO_WARN_REFINE = 256, 512
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libgsvd.so")
