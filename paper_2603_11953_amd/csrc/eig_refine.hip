@@ -64,7 +64,9 @@ constexpr int FT = 1024;               // lanes of the per-problem kernels
 struct RefCtrl {
     int stop_iter;  // sweeps 0 .. stop_iter run; -1: nothing (the preconditioner failed)
     int warn;       // bit 0: last sweep above TAU_STOP; bit 1: cluster pairs left
-    int pad[14];
+    unsigned long long maxbits;  // the sweep's largest angle (bits of a non-negative double)
+    int clus;       // the sweep met a cluster pair
+    int pad[11];
 };
 
 // Per-problem scratch, in doubles after the 64-byte control block: X twice
@@ -166,6 +168,7 @@ __global__ void __launch_bounds__(256) ref_init_kernel(P probs, int rk) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         B.ctrl->stop_iter = (*p.info != 0) ? -1 : rk - 1;
         B.ctrl->warn = 0;
+        B.ctrl->pad[0] = rk;
     }
     const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= nn) return;
@@ -189,6 +192,21 @@ __global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter) {
     const int cur = iter & 1;
     const double *__restrict__ Xh = B.xh[cur];
     const double *__restrict__ Xl = B.xl[cur];
+    if (MODE == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        B.ctrl->maxbits = 0ull;  // the angle kernel of this sweep reduces into these
+        B.ctrl->clus = 0;
+    }
+    if (MODE == 2 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        // the decision of this sweep (its angles are all in): the last sweep if every
+        // angle is below TAU_STOP, or if it is the last one queued.  Other workgroups
+        // of this launch read stop_iter as iter or rk - 1, both >= iter: they all run.
+        const double mx = __longlong_as_double((long long)B.ctrl->maxbits);
+        const int rk = B.ctrl->pad[0];
+        if (mx <= TAU_STOP || iter == rk - 1) {
+            B.ctrl->stop_iter = iter;
+            B.ctrl->warn = (mx <= TAU_STOP ? 0 : 1) | (B.ctrl->clus ? 2 : 0);
+        }
+    }
 
     __shared__ double Ah[TB][KC + 1], Al[TB][KC + 1], Bh[KC][TB + 1], Bl[KC][TB + 1];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -293,30 +311,36 @@ __device__ __forceinline__ double wave_max(double x) {
     return x;
 }
 
-// Rayleigh quotients, the update F, and the stopping decision (one workgroup
-// per problem).
+// Rayleigh quotients and the update F: grid (slices of the n^2 entries, problems).
+// Every workgroup forms all n quotients (n dd divisions); its slice of F follows,
+// and its largest angle and cluster flag go to the sweep's control words.
+constexpr int AE = 8;  // entries of F per lane
+
 template <class P>
-__global__ void __launch_bounds__(FT) ref_angles_kernel(P probs, int iter, int rk) {
-    const RefProb p = probs.get(blockIdx.x);
+__global__ void __launch_bounds__(FT) ref_angles_kernel(P probs, int iter) {
+    const RefProb p = probs.get(blockIdx.y);
     const int n = p.n;
+    const int e0 = blockIdx.x * FT * AE;
+    if (e0 >= n * n) return;
     RefBufs B = ref_bufs(p.rw, n);
     if (iter > B.ctrl->stop_iter) return;
     __shared__ double lam_h[GSVD_WIDE_MAX_N], lam_l[GSVD_WIDE_MAX_N];
-    __shared__ double red[FT / 64];
-    __shared__ int redc[FT / 64];
     const int tid = threadIdx.x;
     for (int i = tid; i < n; i += FT) {
         const int o = i + i * n;
         const dd_t lam = dd_div(dd_t{B.sh[o], B.sl[o]}, dd_t{B.gh[o], B.gl[o]});
         lam_h[i] = lam.hi;
         lam_l[i] = lam.lo;
-        B.lh[i] = lam.hi;
-        B.ll[i] = lam.lo;
+        if (blockIdx.x == 0) {
+            B.lh[i] = lam.hi;
+            B.ll[i] = lam.lo;
+        }
     }
     __syncthreads();
     double mx = 0.0;
     int clus = 0;
-    for (int idx = tid; idx < n * n; idx += FT) {
+    const int e1 = (e0 + FT * AE < n * n) ? e0 + FT * AE : n * n;
+    for (int idx = e0 + tid; idx < e1; idx += FT) {
         const int i = idx % n, j = idx / n;
         double f;
         if (i == j) {
@@ -340,84 +364,85 @@ __global__ void __launch_bounds__(FT) ref_angles_kernel(P probs, int iter, int r
     mx = wave_max(mx);
     const unsigned long long any = __ballot(clus != 0);
     if ((tid & 63) == 0) {
-        red[tid >> 6] = mx;
-        redc[tid >> 6] = any != 0ull;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double m = 0.0;
-        int c = 0;
-        for (int w = 0; w < FT / 64; ++w) {
-            m = fmax(m, red[w]);
-            c |= redc[w];
-        }
-        if (m <= TAU_STOP || iter == rk - 1) {
-            B.ctrl->stop_iter = iter;
-            B.ctrl->warn = (m <= TAU_STOP ? 0 : 1) | (c ? 2 : 0);
-        }
+        atomicMax(&B.ctrl->maxbits, (unsigned long long)__double_as_longlong(mx));
+        if (any) atomicOr(&B.ctrl->clus, 1);
     }
 }
 
-// sigma, ordering, signs, cast, W (one workgroup per problem).
-template <typename TW, class P>
-__global__ void __launch_bounds__(FT) ref_final_kernel(P probs) {
-    const RefProb p = probs.get(blockIdx.x);
+// sigma_c = sqrt(lambda_c) and the sign of column c of the final X (its entry of
+// largest magnitude made positive, the lowest index on ties): grid (groups of 16
+// columns, problems), one wavefront per column; written to the T planes (free once
+// the last sweep has run).
+template <class P>
+__global__ void __launch_bounds__(FT) ref_colstat_kernel(P probs) {
+    const RefProb p = probs.get(blockIdx.y);
     const int n = p.n;
+    const int c = blockIdx.x * (FT / 64) + (threadIdx.x >> 6);
+    if (c >= n) return;
     RefBufs B = ref_bufs(p.rw, n);
     const int stop = B.ctrl->stop_iter;
     if (stop < 0) return;
     const double *__restrict__ Xh = B.xh[(stop + 1) & 1];
-    __shared__ double sig[GSVD_WIDE_MAX_N], sgn[GSVD_WIDE_MAX_N];
-    __shared__ int rank[GSVD_WIDE_MAX_N];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int c = wv; c < n; c += FT / 64) {
-        double best = -1.0;
-        int barg = 0;
-        for (int r = lane; r < n; r += 64) {
-            const double av = __builtin_fabs(Xh[r + c * n]);
-            if (av > best) {
-                best = av;
-                barg = r;
-            }
+    const int lane = threadIdx.x & 63;
+    double best = -1.0;
+    int barg = 0;
+    for (int r = lane; r < n; r += 64) {
+        const double av = __builtin_fabs(Xh[r + c * n]);
+        if (av > best) {
+            best = av;
+            barg = r;
         }
+    }
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oa = __shfl_xor(barg, off, 64);
-            if (ob > best || (ob == best && oa < barg)) {
-                best = ob;
-                barg = oa;
-            }
-        }
-        if (lane == 0) {
-            sgn[c] = Xh[barg + c * n] < 0.0 ? -1.0 : 1.0;
-            sig[c] = dd_sqrt(dd_t{B.lh[c], B.ll[c]}).hi;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oa = __shfl_xor(barg, off, 64);
+        if (ob > best || (ob == best && oa < barg)) {
+            best = ob;
+            barg = oa;
         }
     }
-    __syncthreads();
-    for (int c = tid; c < n; c += FT) {
-        const double sc = sig[c];
-        int rk = 0;
-        for (int q = 0; q < n; ++q) {
-            const double sq = sig[q];
-            rk += (sq > sc) || (sq == sc && q < c);
-        }
-        rank[c] = rk;
+    if (lane == 0) {
+        B.th[c] = dd_sqrt(dd_t{B.lh[c], B.ll[c]}).hi;         // sigma_c
+        B.tl[c] = Xh[barg + c * n] < 0.0 ? -1.0 : 1.0;     // sign of column c
     }
+}
+
+// Ordering (sigma descending, stable), cast, W: grid (groups of 16 columns,
+// problems), one wavefront per column.
+template <typename TW, class P>
+__global__ void __launch_bounds__(FT) ref_write_kernel(P probs) {
+    const RefProb p = probs.get(blockIdx.y);
+    const int n = p.n;
+    const int c0 = blockIdx.x * (FT / 64);
+    if (c0 >= n) return;
+    RefBufs B = ref_bufs(p.rw, n);
+    const int stop = B.ctrl->stop_iter;
+    if (stop < 0) return;
+    const double *__restrict__ Xh = B.xh[(stop + 1) & 1];
+    __shared__ double sig[GSVD_WIDE_MAX_N];
+    for (int q = threadIdx.x; q < n; q += FT) sig[q] = B.th[q];
     __syncthreads();
+    const int c = c0 + (threadIdx.x >> 6);
+    if (c >= n) return;
+    const int lane = threadIdx.x & 63;
+    const double sc = sig[c];
+    int rk = 0;
+    for (int q = lane; q < n; q += 64) rk += (sig[q] > sc) || (sig[q] == sc && q < c);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) rk += __shfl_xor(rk, off, 64);
+    const double sg = B.tl[c];
     TW *S = reinterpret_cast<TW *>(p.S);
     TW *V = reinterpret_cast<TW *>(p.V);
     TW *W = reinterpret_cast<TW *>(p.W);
-    for (int idx = tid; idx < n * n; idx += FT) {
-        const int r = idx % n, c = idx / n;
-        const int pos = rank[c];
-        const TW sw = (TW)sig[c];
-        const TW vw = (TW)(sgn[c] * Xh[idx]);
-        V[r + (int64_t)pos * p.ldv] = vw;
-        W[r + (int64_t)pos * p.ldw] = vw / sw;
-        if (r == 0) S[pos] = sw;
+    const TW sw = (TW)sc;
+    for (int r = lane; r < n; r += 64) {
+        const TW vw = (TW)(sg * Xh[r + c * n]);
+        V[r + (int64_t)rk * p.ldv] = vw;
+        W[r + (int64_t)rk * p.ldw] = vw / sw;
     }
-    if (tid == 0 && B.ctrl->warn != 0) *p.info = GSVD_INFO_WARN_REFINE;
+    if (lane == 0) S[rk] = sw;
+    if (c == 0 && lane == 0 && B.ctrl->warn != 0) *p.info = GSVD_INFO_WARN_REFINE;
 }
 
 // ---- the assumption check of Theorem 1 (every eigensolver) ----------------
@@ -463,27 +488,33 @@ assump_kernel(P probs, double e_gram, double u_h, double u_w, double c_w) {
     const AssumpProb p = probs.get(blockIdx.x);
     const int n = p.n;
     const TW *W = reinterpret_cast<const TW *>(p.W);
+    __shared__ double dg[GSVD_WIDE_MAX_N], isq[GSVD_WIDE_MAX_N];
     __shared__ double red[4], redg[4];
+    for (int r = threadIdx.x; r < n; r += 256) {
+        const double d = p.Mhi[r + (int64_t)r * p.ldm];
+        dg[r] = d;
+        isq[r] = 1.0 / __builtin_sqrt(d);
+    }
+    __syncthreads();
+    // wavefront w takes columns w, w + 4, ...; its lanes the rows (coalesced)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double s = 0.0, gmax = 0.0;
-    for (int c = threadIdx.x; c < n; c += 256) {
-        const double dc = p.Mhi[c + (int64_t)c * p.ldm];
+    for (int c = w; c < n; c += 4) {
         double rs = 0.0;
-        for (int r = 0; r < n; ++r) {
-            const double w = (double)W[r + (int64_t)c * p.ldw];
-            const double dr = p.Mhi[r + (int64_t)r * p.ldm];
-            s = __builtin_fma(dr * w, w, s);
-            rs += __builtin_fabs(p.Mhi[r + (int64_t)c * p.ldm]) / __builtin_sqrt(dr * dc);
+        for (int r = lane; r < n; r += 64) {
+            const double x = (double)W[r + (int64_t)c * p.ldw];
+            s = __builtin_fma(dg[r] * x, x, s);
+            rs = __builtin_fma(__builtin_fabs(p.Mhi[r + (int64_t)c * p.ldm]), isq[r], rs);
         }
-        gmax = fmax(gmax, rs);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rs += __shfl_xor(rs, off, 64);
+        gmax = fmax(gmax, rs * isq[c]);
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        s += __shfl_xor(s, off, 64);
-        gmax = fmax(gmax, __shfl_xor(gmax, off, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[threadIdx.x >> 6] = s;
-        redg[threadIdx.x >> 6] = gmax;
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        red[w] = s;
+        redg[w] = gmax;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -524,6 +555,7 @@ hipError_t refine_queue(P probs, int count, int max_n, bool f32, hipStream_t st)
     const int rk = f32 ? 3 : 2;
     const int nt = (max_n + TB - 1) / TB;
     const unsigned nn_blocks = (unsigned)(((size_t)max_n * max_n + 255) / 256);
+    const unsigned ablocks = (unsigned)(((size_t)max_n * max_n + FT * AE - 1) / (FT * AE));
     hipLaunchKernelGGL(ref_init_kernel<P>, dim3(nn_blocks, (unsigned)count), dim3(256), 0, st,
                        probs, rk);
     hipError_t err = hipGetLastError();
@@ -533,18 +565,21 @@ hipError_t refine_queue(P probs, int count, int max_n, bool f32, hipStream_t st)
                            it);
         hipLaunchKernelGGL((ref_gemm_kernel<1, P>), dim3(nt, 2 * nt, count), dim3(256), 0, st,
                            probs, it);
-        hipLaunchKernelGGL(ref_angles_kernel<P>, dim3((unsigned)count), dim3(FT), 0, st, probs, it,
-                           rk);
+        hipLaunchKernelGGL(ref_angles_kernel<P>, dim3(ablocks, (unsigned)count), dim3(FT), 0, st,
+                           probs, it);
         hipLaunchKernelGGL((ref_gemm_kernel<2, P>), dim3(nt, nt, count), dim3(256), 0, st, probs,
                            it);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
+    const unsigned cblocks = (unsigned)((max_n + FT / 64 - 1) / (FT / 64));
+    hipLaunchKernelGGL(ref_colstat_kernel<P>, dim3(cblocks, (unsigned)count), dim3(FT), 0, st,
+                       probs);
     if (f32)
-        hipLaunchKernelGGL((ref_final_kernel<float, P>), dim3((unsigned)count), dim3(FT), 0, st,
-                           probs);
+        hipLaunchKernelGGL((ref_write_kernel<float, P>), dim3(cblocks, (unsigned)count), dim3(FT),
+                           0, st, probs);
     else
-        hipLaunchKernelGGL((ref_final_kernel<double, P>), dim3((unsigned)count), dim3(FT), 0, st,
-                           probs);
+        hipLaunchKernelGGL((ref_write_kernel<double, P>), dim3(cblocks, (unsigned)count), dim3(FT),
+                           0, st, probs);
     return hipGetLastError();
 }
 
