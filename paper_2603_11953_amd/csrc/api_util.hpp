@@ -215,6 +215,13 @@ inline double alg2_tol_of(const gsvd_opts *o, int64_t n) {
     return __builtin_sqrt((double)n) * unit_roundoff(o->working);
 }
 
+// rotation threshold of the preconditioner before the double-double stage: its
+// basis need only fall inside that stage's quadratic convergence (angles far
+// below 2^-15); 2^-24 leaves a wide margin
+inline double pre_tol_of(const gsvd_opts *o) {
+    return o->jacobi_tol > 0 ? o->jacobi_tol : 0x1p-24;
+}
+
 // default rotation threshold: n u_h for the one-workgroup two-sided Jacobi on
 // M_h (FP32 working, FP64), else Algorithm 2's
 inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
@@ -290,18 +297,20 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
             lo = z;
         }
         void *scr = base + L.scratch;
-        err = eig_wide_launch(n, Mhi, lo, ldm, s64, v64, n, w64, n, info, alg2_tol_of(o, n),
-                              sweeps, scr, st);
+        const bool pre = eig_refined(o, n);
+        err = eig_wide_launch(n, Mhi, lo, ldm, s64, v64, n, w64, n, info,
+                              pre ? pre_tol_of(o) : alg2_tol_of(o, n), sweeps, pre, scr, st);
         if (err == hipSuccess)
             err = eig_refined(o, n)
                       ? refine_launch(GSVD_F32, n, Mhi, lo, ldm, v64, n, S, V, ldv, W, ldw, info,
                                       scr, st)
                       : cast_eig_f32_launch(n, s64, v64, S, V, ldv, W, ldw, info, st);
     } else if (o->working == GSVD_F64) {
-        const double tol = alg2_tol_of(o, n);
+        const bool pre = wide_eig(o, n) && eig_refined(o, n);
+        const double tol = pre ? pre_tol_of(o) : alg2_tol_of(o, n);
         err = wide_eig(o, n)
-                  ? eig_wide_launch(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps, work,
-                                    st)
+                  ? eig_wide_launch(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps, pre,
+                                    work, st)
                   : eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps,
                                st);
         if (err == hipSuccess && eig_refined(o, n))

@@ -38,6 +38,23 @@
 //   5. sigma_p = ||x_p|| 2^e_max, ordering, sign of the V columns (entry of
 //      largest magnitude positive, lowest index on ties), W = fl(V Sigma^-1).
 //   The same outputs and info codes as the one-workgroup kernel for n <= 96.
+//
+// Preconditioner form (when the double-double Jacobi stage follows): the same
+// steps on a reordered and transposed problem, stopped at a looser tolerance,
+// whose only output is an eigenvector basis accurate in the graded sense.
+//   1'. pi orders the columns by decreasing m_jj (a static form of the column
+//      pivoting of a pivoted Cholesky); H' = P^T H P.
+//   3'. X' = R' D~' 2^-emax as before, and the Jacobi runs on Z = X'^T: for a
+//      row-graded triangular factor the columns of Z are far closer to
+//      orthogonal than those of X', so fewer sweeps are needed (the idea of the
+//      QR-preconditioned Jacobi SVD of Drmac and Veselic).  The rotations
+//      still accumulate in Q.
+//   5'. Z Q = V' Sigma and X' = Q Sigma V'^T give V' = X'^-1 Q Sigma: V' comes
+//      from a back substitution with R' and the exact scalings D~'^-1, which
+//      keeps every column of V' accurate relative to its graded pattern
+//      (normalising the columns of Z Q instead loses that: its errors are of
+//      order u relative to the largest entry).  V = P V', columns normalised,
+//      in no particular order or sign (the next stage sorts and signs).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -71,7 +88,7 @@ struct Ctl {
 };
 
 struct WLayout {
-    size_t ctl, sexp, rank, sig, sgn, hh, hl, x, v, total;
+    size_t ctl, sexp, rank, perm, sig, sgn, hh, hl, x, v, total;
 };
 
 __host__ __device__ inline size_t wal(size_t x) { return (x + 255) / 256 * 256; }
@@ -83,6 +100,7 @@ WLayout wlayout(int64_t n) {
     L.ctl = o;  o = wal(o + sizeof(Ctl));
     L.sexp = o; o = wal(o + (size_t)n * sizeof(int));
     L.rank = o; o = wal(o + (size_t)n * sizeof(int));
+    L.perm = o; o = wal(o + (size_t)n * sizeof(int));
     L.sig = o;  o = wal(o + (size_t)n * sizeof(double));
     L.sgn = o;  o = wal(o + (size_t)n * sizeof(double));
     L.hh = o;   o = wal(o + nn * sizeof(double));
@@ -101,9 +119,14 @@ __device__ __forceinline__ int wg_read(const int *p) {
 
 // ---- 1. scaling exponents, checks, H, V = I
 
+// Also the order pi of the preconditioner form: perm[r] is the column of rank r
+// by decreasing m_jj, ties by index (a total order: rejected diagonals count as
+// 0, so perm is a permutation whatever the input).
 __global__ void __launch_bounds__(1024)
-weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, int *sexp) {
+weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, int *sexp,
+                 int *perm) {
     __shared__ int bad, emax;
+    __shared__ double key[GSVD_WIDE_MAX_N];
     if (threadIdx.x == 0) {
         bad = 0;
         emax = -100000;
@@ -115,13 +138,21 @@ weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, i
         if (!(mjj > 0.0) || !__builtin_isfinite(mjj)) {
             atomicMax(&bad, __builtin_isfinite(mjj) ? 1 : 3);
             sexp[j] = 0;
+            key[j] = 0.0;
         } else {
             const int e = ilogb(__builtin_sqrt(mjj));
             sexp[j] = e;
+            key[j] = mjj;
             atomicMax(&emax, e);
         }
     }
     __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double kj = key[j];
+        int r = 0;
+        for (int q = 0; q < n; ++q) r += (key[q] > kj) || (key[q] == kj && q < j);
+        perm[r] = j;
+    }
     if (threadIdx.x == 0) {
         ctl->bad = bad;
         ctl->emax = emax;
@@ -131,21 +162,26 @@ weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, i
     }
 }
 
-// one workgroup per column j: finiteness of column j, H(:, j) (upper part), V(:, j) = e_j
+// one workgroup per column j: finiteness of column j, H(:, j) (upper part), V(:, j) = e_j.
+// perm non-null (the preconditioner form): H'(:, j) = H(pi, pi_j), read from the
+// upper triangle of M_h.
 __global__ void __launch_bounds__(256)
 weig_fill_kernel(int n, const double *__restrict__ Mhi, const double *__restrict__ Mlo,
-                 int64_t ldm, Ctl *ctl, const int *__restrict__ sexp, double *__restrict__ Hh,
-                 double *__restrict__ Hl, double *__restrict__ Vw) {
+                 int64_t ldm, Ctl *ctl, const int *__restrict__ sexp, const int *__restrict__ perm,
+                 double *__restrict__ Hh, double *__restrict__ Hl, double *__restrict__ Vw) {
     const int j = blockIdx.x;
+    const int pj = perm ? perm[j] : j;
     bool nonfinite = false;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double h = Mhi[i + (int64_t)j * ldm];
-        const double l = Mlo[i + (int64_t)j * ldm];
-        if (!__builtin_isfinite(h) || !__builtin_isfinite(l)) nonfinite = true;
+        if (!__builtin_isfinite(Mhi[i + (int64_t)j * ldm]) ||
+            !__builtin_isfinite(Mlo[i + (int64_t)j * ldm]))
+            nonfinite = true;
         if (i <= j) {
-            const int sc = -(sexp[i] + sexp[j]);
-            Hh[i + (size_t)j * n] = ldexp(h, sc);
-            Hl[i + (size_t)j * n] = ldexp(l, sc);
+            const int pi = perm ? perm[i] : i;
+            const int a = pi < pj ? pi : pj, b = pi < pj ? pj : pi;
+            const int sc = -(sexp[pi] + sexp[pj]);
+            Hh[i + (size_t)j * n] = ldexp(Mhi[a + (int64_t)b * ldm], sc);
+            Hl[i + (size_t)j * n] = ldexp(Mlo[a + (int64_t)b * ldm], sc);
         }
         Vw[i + (size_t)j * n] = i == j ? 1.0 : 0.0;
     }
@@ -275,15 +311,22 @@ weig_update_kernel(int n, int k0, int ntile, const Ctl *ctl, double *__restrict_
     }
 }
 
-// ---- 3. X = fl64(R_H) D~ 2^-emax (upper triangle; zeros below)
+// ---- 3. X = fl64(R_H) D~ 2^-emax (upper triangle; zeros below).  perm non-null:
+//      X' = fl64(R') D~' 2^-emax stored transposed (Z = X'^T, lower triangular).
 __global__ void __launch_bounds__(256)
 weig_cast_kernel(int n, const Ctl *ctl, const int *__restrict__ sexp,
-                 const double *__restrict__ Hh, double *__restrict__ X) {
+                 const int *__restrict__ perm, const double *__restrict__ Hh,
+                 double *__restrict__ X) {
     if (wg_read(&ctl->bad)) return;
     const int j = blockIdx.x;
-    const int sc = sexp[j] - ctl->emax;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        X[i + (size_t)j * n] = i <= j ? ldexp(Hh[i + (size_t)j * n], sc) : 0.0;
+    const int sc = sexp[perm ? perm[j] : j] - ctl->emax;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double x = i <= j ? ldexp(Hh[i + (size_t)j * n], sc) : 0.0;
+        if (perm)
+            X[j + (size_t)i * n] = x;
+        else
+            X[i + (size_t)j * n] = x;
+    }
 }
 
 // ---- 4. block one-sided Jacobi
@@ -578,6 +621,90 @@ weig_out_kernel(int n, const Ctl *ctl, const double *__restrict__ Vw,
     if (threadIdx.x == 0) S[pos] = sp;
 }
 
+// ---- 5'. the preconditioner's basis: V' = X'^-1 Q Sigma_Z, V = P V'
+//
+// One workgroup per 16 columns c (wavefront w owns column c0 + w for the
+// column-wise steps).  With X' = R' D~' 2^-emax, V' = 2^emax D~'^-1 R'^-1 (Q Sigma_Z):
+//   a. sigma_c = ||z_c|| and T(:, c) = Q(:, c) sigma_c in LDS;
+//   b. R' T' = T by back substitution in row blocks of 64 from the bottom: the
+//      diagonal block is solved in LDS (lane (w, i) keeps row k0 + i of column
+//      w in a register; one barrier per row), then the rows above take the
+//      block's contribution, sum_k R'(i, k) T'(k, c), in one pass;
+//   c. V'(r, c) = T'(r, c) 2^(emax - e_pi_r) (exact), the column normalised and
+//      written to V(pi_r, c).
+constexpr int SB = 64;   // row block of the back substitution
+constexpr int SC = 16;   // columns per workgroup
+
+__global__ void __launch_bounds__(1024)
+weig_pre_out_kernel(int n, const Ctl *ctl, const int *__restrict__ sexp,
+                    const int *__restrict__ perm, const double *__restrict__ Hh,
+                    const double *__restrict__ X, const double *__restrict__ Vw,
+                    double *__restrict__ V, int64_t ldv, int *__restrict__ info) {
+    extern __shared__ __attribute__((aligned(16))) double psm[];
+    double *T = psm;                    // GSVD_WIDE_MAX_N x SC, column-major
+    double *Dg = T + GSVD_WIDE_MAX_N * SC;  // SB x SB diagonal block, column-major, ld SB + 1
+    double *Xb = Dg + SB * (SB + 1);    // SB x SC block solution
+    const int bad = wg_read(&ctl->bad);
+    const int code = bad ? bad : (wg_read(&ctl->notconv) ? 2 : 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *info = code;
+    if (code) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int c0 = blockIdx.x * SC, c = c0 + w;
+    const bool cv = c < n;
+    // a.
+    {
+        double ss = 0.0;
+        if (cv)
+            for (int r = lane; r < n; r += 64) {
+                const double z = X[r + (size_t)c * n];
+                ss = __builtin_fma(z, z, ss);
+            }
+        const double sg = __builtin_sqrt(wave_sum(ss));
+        for (int r = lane; r < n; r += 64) T[r + w * GSVD_WIDE_MAX_N] = cv ? Vw[r + (size_t)c * n] * sg : 0.0;
+    }
+    __syncthreads();
+    // b.
+    const int nb = (n + SB - 1) / SB;
+    for (int kb = nb - 1; kb >= 0; --kb) {
+        const int k0 = kb * SB;
+        const int bs = (n - k0 < SB) ? n - k0 : SB;
+        for (int q = tid; q < SB * SB; q += 1024) {
+            const int i = q % SB, j = q / SB;
+            Dg[i + j * (SB + 1)] = (i <= j && j < bs) ? Hh[(k0 + i) + (size_t)(k0 + j) * n] : 0.0;
+        }
+        __syncthreads();
+        double t = lane < bs ? T[(k0 + lane) + w * GSVD_WIDE_MAX_N] : 0.0;
+        for (int kk = bs - 1; kk >= 0; --kk) {
+            if (lane == kk) {
+                t = t / Dg[kk + kk * (SB + 1)];
+                Xb[kk + w * SB] = t;
+            }
+            __syncthreads();
+            if (lane < kk) t = __builtin_fma(-Dg[lane + kk * (SB + 1)], Xb[kk + w * SB], t);
+        }
+        if (lane < bs) T[(k0 + lane) + w * GSVD_WIDE_MAX_N] = Xb[lane + w * SB];
+        // rows above the block: T(i, w) -= sum_k R'(i, k0 + k) T'(k0 + k, w)
+        for (int i = lane; i < k0; i += 64) {
+            double acc = 0.0;
+            for (int k = 0; k < bs; ++k)
+                acc = __builtin_fma(Hh[i + (size_t)(k0 + k) * n], Xb[k + w * SB], acc);
+            T[i + w * GSVD_WIDE_MAX_N] -= acc;
+        }
+        __syncthreads();
+    }
+    // c.
+    if (!cv) return;
+    const int emax = ctl->emax;
+    double ss = 0.0;
+    for (int r = lane; r < n; r += 64) {
+        const double v = ldexp(T[r + w * GSVD_WIDE_MAX_N], emax - sexp[perm[r]]);
+        T[r + w * GSVD_WIDE_MAX_N] = v;
+        ss = __builtin_fma(v, v, ss);
+    }
+    const double inv = 1.0 / __builtin_sqrt(wave_sum(ss));
+    for (int r = lane; r < n; r += 64) V[perm[r] + (int64_t)c * ldv] = T[r + w * GSVD_WIDE_MAX_N] * inv;
+}
+
 // The blocked dd Cholesky of H (upper triangle of Hh/Hl, in place).
 hipError_t chol_blocked(int n, Ctl *ctl, double *Hh, double *Hl, hipStream_t st) {
     hipError_t err;
@@ -663,10 +790,11 @@ hipError_t chol_launch(int working, int64_t n64, const double *Mhi, const double
     double *Hl = reinterpret_cast<double *>(base + L.hl);
     double *Vw = reinterpret_cast<double *>(base + L.v);
     hipError_t err;
-    hipLaunchKernelGGL(weig_diag_kernel, dim3(1), dim3(1024), 0, st, n, Mhi, ldm, ctl, sexp);
+    int *perm = reinterpret_cast<int *>(base + L.perm);
+    hipLaunchKernelGGL(weig_diag_kernel, dim3(1), dim3(1024), 0, st, n, Mhi, ldm, ctl, sexp, perm);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(weig_fill_kernel, dim3((unsigned)n), dim3(256), 0, st, n, Mhi, Mlo, ldm, ctl,
-                       sexp, Hh, Hl, Vw);
+                       sexp, nullptr, Hh, Hl, Vw);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if ((err = chol_blocked(n, ctl, Hh, Hl, st)) != hipSuccess) return err;
     if (working == 1)
@@ -682,7 +810,7 @@ size_t eig_wide_work_bytes(int64_t n) { return wlayout(n).total; }
 
 hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, int64_t ldm, void *S,
                            void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
-                           int max_sweeps, void *work, hipStream_t st) {
+                           int max_sweeps, bool pre, void *work, hipStream_t st) {
     if (n64 < 2 || n64 > GSVD_WIDE_MAX_N || Mlo == nullptr || work == nullptr || max_sweeps < 1)
         return hipErrorInvalidValue;
     const int n = (int)n64;
@@ -691,6 +819,7 @@ hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, in
     Ctl *ctl = reinterpret_cast<Ctl *>(base + L.ctl);
     int *sexp = reinterpret_cast<int *>(base + L.sexp);
     int *rank = reinterpret_cast<int *>(base + L.rank);
+    int *perm = reinterpret_cast<int *>(base + L.perm);
     double *sig = reinterpret_cast<double *>(base + L.sig);
     double *sgn = reinterpret_cast<double *>(base + L.sgn);
     double *Hh = reinterpret_cast<double *>(base + L.hh);
@@ -703,13 +832,15 @@ hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, in
         if ((err = hipGetLastError()) != hipSuccess) return err; \
     } while (0)
 
-    hipLaunchKernelGGL(weig_diag_kernel, dim3(1), dim3(1024), 0, st, n, Mhi, ldm, ctl, sexp);
+    const int *pp = pre ? perm : nullptr;
+    hipLaunchKernelGGL(weig_diag_kernel, dim3(1), dim3(1024), 0, st, n, Mhi, ldm, ctl, sexp, perm);
     WCHK();
     hipLaunchKernelGGL(weig_fill_kernel, dim3((unsigned)n), dim3(256), 0, st, n, Mhi, Mlo, ldm, ctl,
-                       sexp, Hh, Hl, Vw);
+                       sexp, pp, Hh, Hl, Vw);
     WCHK();
     if ((err = chol_blocked(n, ctl, Hh, Hl, st)) != hipSuccess) return err;
-    hipLaunchKernelGGL(weig_cast_kernel, dim3((unsigned)n), dim3(256), 0, st, n, ctl, sexp, Hh, X);
+    hipLaunchKernelGGL(weig_cast_kernel, dim3((unsigned)n), dim3(256), 0, st, n, ctl, sexp, pp, Hh,
+                       X);
     WCHK();
     const int nbb = (n + JB - 1) / JB;
     const int nblk = nbb + (nbb & 1);
@@ -726,6 +857,16 @@ hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, in
         default: return hipErrorInvalidValue;
     }
     if (err != hipSuccess) return err;
+    if (pre) {
+        const size_t lds = ((size_t)GSVD_WIDE_MAX_N * SC + SB * (SB + 1) + SB * SC) * sizeof(double);
+        if ((err = hipFuncSetAttribute((const void *)weig_pre_out_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
+            return err;
+        hipLaunchKernelGGL(weig_pre_out_kernel, dim3((unsigned)((n + SC - 1) / SC)), dim3(1024), lds,
+                           st, n, ctl, sexp, perm, Hh, X, Vw, (double *)V, ldv, info);
+        WCHK();
+        return hipSuccess;
+    }
     hipLaunchKernelGGL(weig_sigma_kernel, dim3((unsigned)((n + 15) / 16)), dim3(1024), 0, st, n, ctl,
                        X, Vw, sig, sgn);
     WCHK();

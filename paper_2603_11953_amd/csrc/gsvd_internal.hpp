@@ -150,10 +150,13 @@ hipError_t eig_batched_launch(int working, const BatchMat *tab, const int *order
 
 // Algorithm 2 for FP64 working and n > 96 (eig_wide.hip): a sequence of
 // launches (blocked dd Cholesky, block one-sided Jacobi) over device scratch.
+// pre: the preconditioner form for the double-double stage (columns ordered by
+// norm, Jacobi on the transposed factor, V by back substitution); it writes only
+// V (FP64, unordered, unsigned) and info.
 size_t eig_wide_work_bytes(int64_t n);
 hipError_t eig_wide_launch(int64_t n, const double *Mhi, const double *Mlo, int64_t ldm, void *S,
                            void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
-                           int max_sweeps, void *work, hipStream_t st);
+                           int max_sweeps, bool pre, void *work, hipStream_t st);
 
 // Cholesky factor of M_h alone (eig_wide.hip; any n <= 512): the scaled blocked dd
 // Cholesky of Algorithm 2's first step, R = fl_w(R_H) D~ written upper triangular
