@@ -232,6 +232,9 @@ inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
 }
 
 inline int sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 30; }
+// sweep limit of the preconditioner before the double-double stage (its sweeps
+// are queued whether needed or not; it converges in 5 to 8 at the sizes measured)
+inline int pre_sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 16; }
 
 // Bound on ||D^-1 dM D^-1|| for the Gram's error dM, for the assumption check:
 // n^2 u_h for the plain Gram (the n^2 eps_M of eq. (thm:assump)); n eps for the
@@ -299,7 +302,8 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
         void *scr = base + L.scratch;
         const bool pre = eig_refined(o, n);
         err = eig_wide_launch(n, Mhi, lo, ldm, s64, v64, n, w64, n, info,
-                              pre ? pre_tol_of(o) : alg2_tol_of(o, n), sweeps, pre, scr, st);
+                              pre ? pre_tol_of(o) : alg2_tol_of(o, n),
+                              pre ? pre_sweeps_of(o) : sweeps, pre, scr, st);
         if (err == hipSuccess)
             err = eig_refined(o, n)
                       ? refine_launch(GSVD_F32, n, Mhi, lo, ldm, v64, n, S, V, ldv, W, ldw, info,
@@ -309,8 +313,8 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
         const bool pre = wide_eig(o, n) && eig_refined(o, n);
         const double tol = pre ? pre_tol_of(o) : alg2_tol_of(o, n);
         err = wide_eig(o, n)
-                  ? eig_wide_launch(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps, pre,
-                                    work, st)
+                  ? eig_wide_launch(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol,
+                                    pre ? pre_sweeps_of(o) : sweeps, pre, work, st)
                   : eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps,
                                st);
         if (err == hipSuccess && eig_refined(o, n))

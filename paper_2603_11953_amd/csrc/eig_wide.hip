@@ -29,12 +29,13 @@
 //      reduction that leaves bitwise identical sums in every lane; the rotation
 //      parameters use the hardware reciprocal and reciprocal square root
 //      refined by Newton steps, as in the one-workgroup kernel.  The
-//      rotations of a step accumulate in a 32 x 32 product Q, and the same 32
-//      columns of V, staged through LDS, are multiplied by Q once at the end of
-//      the step, on the FP64 matrix cores.  One launch per
-//      step; after each tournament round a one-lane kernel marks convergence
-//      when no rotation passed the test |x_p^T x_q| > tol ||x_p|| ||x_q||, and
-//      later launches return at once.
+//      rotations of a step accumulate in a 32 x 32 product Q, which goes to a
+//      buffer: V never feeds back into the rotations, so after each tournament
+//      round one launch applies that round's products to V in step order, over
+//      16-row strips of V on many workgroups (FP64 matrix cores).  One launch
+//      per step; after each tournament round a one-lane kernel marks
+//      convergence when no rotation passed the test
+//      |x_p^T x_q| > tol ||x_p|| ||x_q||, and later launches return at once.
 //   5. sigma_p = ||x_p|| 2^e_max, ordering, sign of the V columns (entry of
 //      largest magnitude positive, lowest index on ties), W = fl(V Sigma^-1).
 //   The same outputs and info codes as the one-workgroup kernel for n <= 96.
@@ -68,11 +69,7 @@ namespace gsvd {
 namespace {
 
 constexpr int CB = 64;       // Cholesky panel width
-constexpr int JB = 16;       // Jacobi block width (columns)
-constexpr int JC = 2 * JB;   // columns held by one workgroup
-constexpr int JT = 64 * JB;  // Jacobi workgroup size: one wavefront per column pair of a round
 constexpr int UT = 1024;     // update-kernel workgroup (32 x 32 tile)
-constexpr int QLD = JC + 2;  // column stride of Q in LDS: conflict-free matrix-core operand reads
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -84,12 +81,21 @@ struct Ctl {
     int done;     // converged
     int notconv;  // max_sweeps reached without convergence
     int abort;    // the output kernel must not write
+    int nswept;   // tournament rounds checked so far (those that ran)
     int rot[MAXWG];  // per step workgroup: some rotation in the current tournament round
 };
 
 struct WLayout {
-    size_t ctl, sexp, rank, perm, sig, sgn, hh, hl, x, v, total;
+    size_t ctl, sexp, rank, perm, sig, sgn, hh, hl, x, v, qbuf, total;
 };
+
+constexpr int JBW = 16;  // Jacobi block width of the launches (8 measured no faster at n = 512)
+
+// blocks of the tournament (an even count; an odd one gets a bye block)
+__host__ __device__ inline int jac_nblk(int n) {
+    const int nbb = (n + JBW - 1) / JBW;
+    return nbb + (nbb & 1);
+}
 
 __host__ __device__ inline size_t wal(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -107,6 +113,8 @@ WLayout wlayout(int64_t n) {
     L.hl = o;   o = wal(o + nn * sizeof(double));
     L.x = o;    o = wal(o + nn * sizeof(double));
     L.v = o;    o = wal(o + nn * sizeof(double));
+    const int nblk = jac_nblk((int)n);
+    L.qbuf = o; o = wal(o + (size_t)(nblk - 1) * (nblk / 2) * (4 * JBW * JBW) * sizeof(double));
     L.total = o;
     return L;
 }
@@ -159,6 +167,7 @@ weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, i
         ctl->done = 0;
         ctl->notconv = 0;
         ctl->abort = 0;
+        ctl->nswept = 0;
     }
 }
 
@@ -369,11 +378,22 @@ __device__ __forceinline__ void rr_pair(int r, int g, int m, int &p, int &q) {
     }
 }
 
-template <int RPL>
-__global__ void __launch_bounds__(JT)
+// JB: Jacobi block width (columns); a workgroup holds JC = 2 JB columns and has
+// one wavefront per column pair of a round; Q's column stride QLD = JC + 2 keeps
+// the matrix-core operand reads free of bank conflicts.
+template <int JB>
+struct JGeom {
+    static constexpr int JC = 2 * JB;
+    static constexpr int JT = 64 * JB;
+    static constexpr int QLD = JC + 2;
+};
+
+template <int RPL, int JB>
+__global__ void __launch_bounds__(64 * JB)
 weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
-                 double *__restrict__ Vw, double tol2) {
+                 double *__restrict__ Qbuf, double tol2) {
     extern __shared__ __attribute__((aligned(16))) double jsm[];
+    constexpr int JC = JGeom<JB>::JC, JT = JGeom<JB>::JT, QLD = JGeom<JB>::QLD;
     constexpr int LDL = 64 * RPL;  // rows of a column in LDS (n rounded up to 64)
     double *Xl = jsm;              // JC columns of X
     double *Qs = jsm + JC * LDL;   // JC x JC rotation product, column-major, stride QLD
@@ -483,40 +503,16 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
         for (int i = 0; i < RPL; ++i) xp[64 * i] = x0[i];
     }
     __syncthreads();
-    // X back; then V(:, block pair) = V(:, block pair) Q with the V columns staged in LDS
+    // X back; the step's rotation product Q (JC x JC) to its slot of the round's buffer
+    // (applied to V once the round is over)
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
         const int q = tid + k * JT;
         const int r = q % LDL, g = gcol(q / LDL);
         if (r < n && g < n) X[r + (size_t)g * n] = Xl[q];
     }
-    __syncthreads();
-    stage(Vw);
-    __syncthreads();
-    // V_new = V Q on the FP64 matrix cores: (LDL x 32) by (32 x 32) in 16 x 16 tiles,
-    // LDL / 16 x 2 of them dealt to the wavefronts, 8 steps of 16x16x4 each.
-    // Operands (16x16x4): lane l supplies V(r0 + l % 16, k0 + l / 16) and
-    // Q(k0 + l / 16, c0 + l % 16); result register r is V_new(r0 + 4 r + l / 16, c0 + l % 16).
-    {
-        constexpr int NTI = LDL / 16 * (JC / 16);
-        const int li = lane & 15, lk = lane >> 4;
-        for (int ti = wave; ti < NTI; ti += JT / 64) {
-            const int r0 = 16 * (ti >> 1), c0 = 16 * (ti & 1);
-            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int k0 = 0; k0 < JC; k0 += 4) {
-                const double a = Xl[(r0 + li) + (k0 + lk) * LDL];
-                const double b = Qs[(k0 + lk) + (c0 + li) * QLD];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-            }
-            const int g = gcol(c0 + li);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = r0 + 4 * r + lk;
-                if (row < n && g < n) Vw[row + (size_t)g * n] = acc[r];
-            }
-        }
-    }
+    double *Qo = Qbuf + ((size_t)step * gridDim.x + blockIdx.x) * (JC * JC);
+    for (int q = tid; q < JC * JC; q += JT) Qo[q] = Qs[(q % JC) + (q / JC) * QLD];
     // one plain store per workgroup into its own word (no contended atomics)
     if (__syncthreads_or(any) && tid == 0) ctl->rot[blockIdx.x] = 1;
 }
@@ -530,8 +526,71 @@ __global__ void __launch_bounds__(64) weig_sweep_kernel(Ctl *ctl, int nwg, int l
     const bool anyrot = __any(r != 0);
     if (t < nwg) ctl->rot[t] = 0;
     if (t == 0) {
+        ctl->nswept += 1;
         if (!anyrot) ctl->done = 1;
         else if (last) ctl->notconv = 1;
+    }
+}
+
+// V <- V Q_s for the steps s of the tournament round just checked, in order (the
+// rotations never feed back into the Jacobi, so V follows a round behind).  One
+// workgroup per 16 rows of V, held in LDS for the whole round; wavefront b applies
+// the product of step workgroup b to the 32 columns of its block pair on the FP64
+// matrix cores (the pairs of a step are disjoint).  Skipped when the round did not
+// run or rotated nothing.
+// Operands (16x16x4): lane l supplies V(l % 16, k0 + l / 16) and Q(k0 + l / 16,
+// c0 + l % 16); result register r is (V Q)(4 r + l / 16, c0 + l % 16).
+constexpr int VRW = 16;  // rows of V per workgroup
+
+template <int JB>
+__global__ void __launch_bounds__(1024)
+weig_vapply_kernel(int n, int nblk, int sweep, const Ctl *ctl, const double *__restrict__ Qbuf,
+                   double *__restrict__ Vw) {
+    constexpr int JC = JGeom<JB>::JC;
+    extern __shared__ __attribute__((aligned(16))) double vsm[];  // VRW x n, column-major
+    if (wg_read(&ctl->bad) || wg_read(&ctl->done) || wg_read(&ctl->nswept) != sweep + 1) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * VRW;
+    for (int q = tid; q < VRW * n; q += 1024) {
+        const int r = q % VRW, c = q / VRW;
+        vsm[q] = (r0 + r < n) ? Vw[(r0 + r) + (size_t)c * n] : 0.0;
+    }
+    __syncthreads();
+    const int nbb = (n + JB - 1) / JB;
+    const int npair = nblk / 2;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int st = 0; st < nblk - 1; ++st) {
+        int P = 0, Qb = 0;
+        if (wave < npair) rr_pair(st, wave, nblk, P, Qb);
+        // the step kernel's own early return (a bye block) wrote no product
+        const bool act = wave < npair && !((P >= nbb && Qb >= nbb) ||
+                                            ((P >= nbb || Qb >= nbb) && st != 0));
+        if (act) {  // uniform per wavefront
+            auto gcol = [&](int c) { return c < JB ? JB * P + c : JB * Qb + (c - JB); };
+            const double *Q = Qbuf + ((size_t)st * npair + wave) * (JC * JC);
+            f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k0 = 0; k0 < JC; k0 += 4) {
+                const int gk = gcol(k0 + lk);
+                const double a = gk < n ? vsm[li + gk * VRW] : 0.0;
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Q[(k0 + lk) + li * JC], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Q[(k0 + lk) + (16 + li) * JC], acc1,
+                                                            0, 0, 0);
+            }
+            // (this wavefront alone reads and writes the pair's columns: its reads above
+            // precede these writes)
+            const int g0 = gcol(li), g1 = gcol(16 + li);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (g0 < n) vsm[(4 * r + lk) + g0 * VRW] = acc0[r];
+                if (g1 < n) vsm[(4 * r + lk) + g1 * VRW] = acc1[r];
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < VRW * n; q += 1024) {
+        const int r = q % VRW, c = q / VRW;
+        if (r0 + r < n) Vw[(r0 + r) + (size_t)c * n] = vsm[q];
     }
 }
 
@@ -735,22 +794,31 @@ hipError_t chol_blocked(int n, Ctl *ctl, double *Hh, double *Hl, hipStream_t st)
     return hipSuccess;
 }
 
-template <int RPL>
-hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double tol2,
-                        int max_sweeps, hipStream_t st) {
+template <int RPL, int JB>
+hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double *Qbuf,
+                        double tol2, int max_sweeps, hipStream_t st) {
+    constexpr int JC = JGeom<JB>::JC, JT = JGeom<JB>::JT, QLD = JGeom<JB>::QLD;
     const size_t lds = ((size_t)JC * 64 * RPL + JC * QLD) * sizeof(double);
-    auto k = weig_step_kernel<RPL>;
+    auto k = weig_step_kernel<RPL, JB>;
+    auto kv = weig_vapply_kernel<JB>;
+    const size_t lds_v = (size_t)VRW * n * sizeof(double);
     hipError_t err = hipFuncSetAttribute((const void *)k,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    err = hipFuncSetAttribute((const void *)kv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_v);
     if (err != hipSuccess) return err;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         for (int s = 0; s < nblk - 1; ++s) {
             hipLaunchKernelGGL(k, dim3((unsigned)(nblk / 2)), dim3(JT), lds, st, n, nblk, s, ctl,
-                               X, Vw, tol2);
+                               X, Qbuf, tol2);
             if ((err = hipGetLastError()) != hipSuccess) return err;
         }
         hipLaunchKernelGGL(weig_sweep_kernel, dim3(1), dim3(64), 0, st, ctl, nblk / 2,
                            sw + 1 == max_sweeps ? 1 : 0);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        hipLaunchKernelGGL(kv, dim3((unsigned)((n + VRW - 1) / VRW)), dim3(1024), lds_v, st, n,
+                           nblk, sw, ctl, Qbuf, Vw);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     return hipSuccess;
@@ -826,6 +894,7 @@ hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, in
     double *Hl = reinterpret_cast<double *>(base + L.hl);
     double *X = reinterpret_cast<double *>(base + L.x);
     double *Vw = reinterpret_cast<double *>(base + L.v);
+    double *Qbuf = reinterpret_cast<double *>(base + L.qbuf);
     hipError_t err;
 #define WCHK()                                                  \
     do {                                                        \
@@ -842,20 +911,16 @@ hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, in
     hipLaunchKernelGGL(weig_cast_kernel, dim3((unsigned)n), dim3(256), 0, st, n, ctl, sexp, pp, Hh,
                        X);
     WCHK();
-    const int nbb = (n + JB - 1) / JB;
-    const int nblk = nbb + (nbb & 1);
     const double tol2 = tol * tol;
     const int rpl = (n + 63) / 64;
+    const int nblk = jac_nblk(n);
+#define STEPS(R)                                                                              \
+    case R: err = launch_steps<R, JBW>(n, nblk, ctl, X, Vw, Qbuf, tol2, max_sweeps, st); break;
     switch (rpl) {
-        case 2: err = launch_steps<2>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
-        case 3: err = launch_steps<3>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
-        case 4: err = launch_steps<4>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
-        case 5: err = launch_steps<5>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
-        case 6: err = launch_steps<6>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
-        case 7: err = launch_steps<7>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
-        case 8: err = launch_steps<8>(n, nblk, ctl, X, Vw, tol2, max_sweeps, st); break;
+        STEPS(2) STEPS(3) STEPS(4) STEPS(5) STEPS(6) STEPS(7) STEPS(8)
         default: return hipErrorInvalidValue;
     }
+#undef STEPS
     if (err != hipSuccess) return err;
     if (pre) {
         const size_t lds = ((size_t)GSVD_WIDE_MAX_N * SC + SB * (SB + 1) + SB * SC) * sizeof(double);
