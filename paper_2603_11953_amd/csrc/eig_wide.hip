@@ -86,7 +86,7 @@ struct Ctl {
 };
 
 struct WLayout {
-    size_t ctl, sexp, rank, perm, sig, sgn, hh, hl, x, v, qbuf, total;
+    size_t ctl, sexp, rank, perm, sig, sgn, hh, hl, x, v, qbuf, dinv, total;
 };
 
 constexpr int JBW = 16;  // Jacobi block width of the launches (8 measured no faster at n = 512)
@@ -115,6 +115,7 @@ WLayout wlayout(int64_t n) {
     L.v = o;    o = wal(o + nn * sizeof(double));
     const int nblk = jac_nblk((int)n);
     L.qbuf = o; o = wal(o + (size_t)(nblk - 1) * (nblk / 2) * (4 * JBW * JBW) * sizeof(double));
+    L.dinv = o; o = wal(o + (size_t)((n + 63) / 64) * 64 * 64 * sizeof(double));
     L.total = o;
     return L;
 }
@@ -199,11 +200,24 @@ weig_fill_kernel(int n, const double *__restrict__ Mhi, const double *__restrict
 
 // ---- 2. blocked dd Cholesky
 
-// Factor the diagonal block [k0, k0 + 64) in place (upper triangle).
+// 1 / h in double-double: the FP64 estimate r corrected once, r + r (1 - h r)
+__device__ __forceinline__ dd_t dd_rcp(dd_t h) {
+    const double r0 = rcp_nr(h.hi);
+    const dd_t hr = dd_mul_d(h, r0);
+    const double e = (1.0 - hr.hi) - hr.lo;
+    return quick_two_sum(r0, r0 * e);
+}
+
+// Factor the diagonal block [k0, k0 + 64) in place (upper triangle), right-looking
+// in the square-root-free form h_ij -= h_ki (h_kj / h_kk) over k < i <= j, one
+// barrier per column: each lane owns fixed entries of the triangle (at most 3), the
+// owner of the next pivot also forms its reciprocal.  Row k of R is then
+// h_kj / sqrt(h_kk), formed for all rows at once.
 __global__ void __launch_bounds__(1024)
 weig_potrf_kernel(int n, int k0, Ctl *ctl, double *__restrict__ Hh, double *__restrict__ Hl) {
     extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
     dd_t *Rs = reinterpret_cast<dd_t *>(wsm);  // CB x CB, column-major
+    dd_t *rp = Rs + CB * CB;                    // reciprocal pivots
     if (wg_read(&ctl->bad)) return;
     const int nb = (n - k0 < CB) ? n - k0 : CB;
     const int tid = threadIdx.x;
@@ -214,47 +228,68 @@ weig_potrf_kernel(int n, int k0, Ctl *ctl, double *__restrict__ Hh, double *__re
             v = dd_t{Hh[(k0 + i) + (size_t)(k0 + j) * n], Hl[(k0 + i) + (size_t)(k0 + j) * n]};
         Rs[q] = v;
     }
+    // the lane's entries (i, j), i <= j, numbered q = j (j + 1) / 2 + i
+    constexpr int NE = (CB * (CB + 1) / 2 + 1023) / 1024;
+    int ei[NE], ej[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int q = tid + 1024 * e;
+        int j = (int)((__builtin_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+        while (j * (j + 1) / 2 > q) --j;
+        while ((j + 1) * (j + 2) / 2 <= q) ++j;
+        ei[e] = q - j * (j + 1) / 2;
+        ej[e] = j < CB ? j : CB;  // CB: no entry
+    }
     __syncthreads();
-    bool fail = false;
-    const int tx = tid & 31, ty = tid >> 5;
+    if (tid == 0) rp[0] = dd_rcp(Rs[0]);
+    __syncthreads();
     for (int k = 0; k < nb; ++k) {
-        const dd_t hkk = Rs[k + k * CB];
-        if (!(hkk.hi > 0.0)) {  // uniform: every lane read the same LDS word
-            fail = true;
-            break;
+        if (!(Rs[k + k * CB].hi > 0.0)) {  // uniform: every lane read the same LDS word
+            if (tid == 0) atomicMax(&ctl->bad, 1);
+            return;
         }
-        const dd_t rkk = dd_sqrt(hkk);
-        __syncthreads();
-        for (int j = k + 1 + tid; j < nb; j += blockDim.x) Rs[k + j * CB] = dd_div(Rs[k + j * CB], rkk);
-        if (tid == 0) Rs[k + k * CB] = rkk;
-        __syncthreads();
-        for (int j = k + 1 + ty; j < nb; j += 32)
-            for (int i = k + 1 + tx; i <= j; i += 32)
-                Rs[i + j * CB] = dd_sub(Rs[i + j * CB], dd_mul(Rs[k + i * CB], Rs[k + j * CB]));
+        const dd_t rinv = rp[k];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int i = ei[e], j = ej[e];
+            if (i > k && j < nb) {
+                const dd_t v = dd_sub(Rs[i + j * CB], dd_mul(Rs[k + i * CB], dd_mul(Rs[k + j * CB], rinv)));
+                Rs[i + j * CB] = v;
+                if (i == k + 1 && j == k + 1) rp[k + 1] = dd_rcp(v);
+            }
+        }
         __syncthreads();
     }
-    if (fail) {
-        if (tid == 0) atomicMax(&ctl->bad, 1);
-        return;
+    // r_kj = h_kj / sqrt(h_kk): 1 / sqrt(h) as y + y (1 - h y^2) / 2 from the FP64 estimate
+    if (tid < nb) {
+        const dd_t hkk = Rs[tid + tid * CB];
+        const double y = rsq_nr(hkk.hi);
+        const dd_t hy2 = dd_mul_d(dd_mul_d(hkk, y), y);
+        rp[tid] = dd_add(dd_t{y, 0.0}, dd_mul_d(dd_sub(dd_t{1.0, 0.0}, hy2), 0.5 * y));
     }
+    __syncthreads();
     for (int q = tid; q < CB * CB; q += blockDim.x) {
         const int i = q % CB, j = q / CB;
         if (i < nb && j < nb && i <= j) {
-            Hh[(k0 + i) + (size_t)(k0 + j) * n] = Rs[q].hi;
-            Hl[(k0 + i) + (size_t)(k0 + j) * n] = Rs[q].lo;
+            const dd_t r = dd_mul(Rs[q], rp[i]);
+            Hh[(k0 + i) + (size_t)(k0 + j) * n] = r.hi;
+            Hl[(k0 + i) + (size_t)(k0 + j) * n] = r.lo;
         }
     }
 }
 
 // R(k0 + i, j) for the 16 columns j0 .. j0 + 15 right of the panel: solve
-// R_kk^T x = H(k0 .. k0 + 63, j) by forward substitution, right-looking:
-// step t divides x_t by R(t, t), then x_i -= R(t, i) x_t for i > t.
+// R_kk^T x = H(k0 .. k0 + 63, j) by forward substitution, right-looking: step t
+// forms x_t = h_t / R(t, t) (times the reciprocal of R(t, t)), then h_i -= R(t, i) x_t
+// for i > t.  Lane (i, c) keeps h_i of column c in registers; x_t reaches the
+// other lanes through its own LDS slot, so each step needs one barrier.
 __global__ void __launch_bounds__(1024)
 weig_panel_kernel(int n, int k0, const Ctl *ctl, double *__restrict__ Hh,
                   double *__restrict__ Hl) {
     extern __shared__ __attribute__((aligned(16))) unsigned char wsm[];
     dd_t *Rk = reinterpret_cast<dd_t *>(wsm);  // CB x CB, column-major (upper)
-    dd_t *Hs = Rk + CB * CB;                    // CB x 16
+    dd_t *rd = Rk + CB * CB;                    // 1 / R(t, t)
+    dd_t *xs = rd + CB;                         // CB x 16 solved values
     if (wg_read(&ctl->bad)) return;
     const int tid = threadIdx.x;
     const int j0 = k0 + CB + 16 * blockIdx.x;
@@ -266,18 +301,21 @@ weig_panel_kernel(int n, int k0, const Ctl *ctl, double *__restrict__ Hh,
     const int i = tid % CB, c = tid / CB;  // 64 rows x 16 columns
     const int j = j0 + c;
     const bool jv = j < n;
-    Hs[i + c * CB] = jv ? dd_t{Hh[(k0 + i) + (size_t)j * n], Hl[(k0 + i) + (size_t)j * n]}
-                        : dd_t{0.0, 0.0};
+    dd_t h = jv ? dd_t{Hh[(k0 + i) + (size_t)j * n], Hl[(k0 + i) + (size_t)j * n]} : dd_t{0.0, 0.0};
+    __syncthreads();
+    if (tid < CB) rd[tid] = dd_rcp(Rk[tid + tid * CB]);
     __syncthreads();
     for (int t = 0; t < CB; ++t) {
-        if (i == t) Hs[t + c * CB] = dd_div(Hs[t + c * CB], Rk[t + t * CB]);
+        if (i == t) {
+            h = dd_mul(h, rd[t]);
+            xs[t + c * CB] = h;
+        }
         __syncthreads();
-        if (i > t) Hs[i + c * CB] = dd_sub(Hs[i + c * CB], dd_mul(Rk[t + i * CB], Hs[t + c * CB]));
-        __syncthreads();
+        if (i > t) h = dd_sub(h, dd_mul(Rk[t + i * CB], xs[t + c * CB]));
     }
     if (jv) {
-        Hh[(k0 + i) + (size_t)j * n] = Hs[i + c * CB].hi;
-        Hl[(k0 + i) + (size_t)j * n] = Hs[i + c * CB].lo;
+        Hh[(k0 + i) + (size_t)j * n] = h.hi;
+        Hl[(k0 + i) + (size_t)j * n] = h.lo;
     }
 }
 
@@ -503,8 +541,8 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
         for (int i = 0; i < RPL; ++i) xp[64 * i] = x0[i];
     }
     __syncthreads();
-    // X back; the step's rotation product Q (JC x JC) to its slot of the round's buffer
-    // (applied to V once the round is over)
+    // X back; the step's rotation product Q (JC x JC, row-major) to its slot of the
+    // round's buffer (applied to V once the round is over)
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
         const int q = tid + k * JT;
@@ -512,7 +550,7 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
         if (r < n && g < n) X[r + (size_t)g * n] = Xl[q];
     }
     double *Qo = Qbuf + ((size_t)step * gridDim.x + blockIdx.x) * (JC * JC);
-    for (int q = tid; q < JC * JC; q += JT) Qo[q] = Qs[(q % JC) + (q / JC) * QLD];
+    for (int q = tid; q < JC * JC; q += JT) Qo[q] = Qs[(q / JC) + (q % JC) * QLD];
     // one plain store per workgroup into its own word (no contended atomics)
     if (__syncthreads_or(any) && tid == 0) ctl->rot[blockIdx.x] = 1;
 }
@@ -539,7 +577,8 @@ __global__ void __launch_bounds__(64) weig_sweep_kernel(Ctl *ctl, int nwg, int l
 // matrix cores (the pairs of a step are disjoint).  Skipped when the round did not
 // run or rotated nothing.
 // Operands (16x16x4): lane l supplies V(l % 16, k0 + l / 16) and Q(k0 + l / 16,
-// c0 + l % 16); result register r is (V Q)(4 r + l / 16, c0 + l % 16).
+// c0 + l % 16) (Q row-major: four 128-byte runs per read); result register r is
+// (V Q)(4 r + l / 16, c0 + l % 16).
 constexpr int VRW = 16;  // rows of V per workgroup
 
 template <int JB>
@@ -568,14 +607,19 @@ weig_vapply_kernel(int n, int nblk, int sweep, const Ctl *ctl, const double *__r
         if (act) {  // uniform per wavefront
             auto gcol = [&](int c) { return c < JB ? JB * P + c : JB * Qb + (c - JB); };
             const double *Q = Qbuf + ((size_t)st * npair + wave) * (JC * JC);
+            double b0[JC / 4], b1[JC / 4];
+#pragma unroll
+            for (int k = 0; k < JC / 4; ++k) {  // every operand load issued first
+                b0[k] = Q[li + (4 * k + lk) * JC];
+                b1[k] = Q[(16 + li) + (4 * k + lk) * JC];
+            }
             f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int k0 = 0; k0 < JC; k0 += 4) {
-                const int gk = gcol(k0 + lk);
+            for (int k = 0; k < JC / 4; ++k) {
+                const int gk = gcol(4 * k + lk);
                 const double a = gk < n ? vsm[li + gk * VRW] : 0.0;
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Q[(k0 + lk) + li * JC], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Q[(k0 + lk) + (16 + li) * JC], acc1,
-                                                            0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0[k], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1[k], acc1, 0, 0, 0);
             }
             // (this wavefront alone reads and writes the pair's columns: its reads above
             // precede these writes)
@@ -682,27 +726,61 @@ weig_out_kernel(int n, const Ctl *ctl, const double *__restrict__ Vw,
 
 // ---- 5'. the preconditioner's basis: V' = X'^-1 Q Sigma_Z, V = P V'
 //
-// One workgroup per 16 columns c (wavefront w owns column c0 + w for the
-// column-wise steps).  With X' = R' D~' 2^-emax, V' = 2^emax D~'^-1 R'^-1 (Q Sigma_Z):
-//   a. sigma_c = ||z_c|| and T(:, c) = Q(:, c) sigma_c in LDS;
-//   b. R' T' = T by back substitution in row blocks of 64 from the bottom: the
-//      diagonal block is solved in LDS (lane (w, i) keeps row k0 + i of column
-//      w in a register; one barrier per row), then the rows above take the
-//      block's contribution, sum_k R'(i, k) T'(k, c), in one pass;
-//   c. V'(r, c) = T'(r, c) 2^(emax - e_pi_r) (exact), the column normalised and
-//      written to V(pi_r, c).
+// With X' = R' D~' 2^-emax, V' = 2^emax D~'^-1 R'^-1 (Q Sigma_Z), R' = fl64(R_H') the
+// (unscaled) Cholesky factor in Hh.  R'^-1 is applied by block back substitution in
+// row blocks of SB = 64 from the bottom, with the inverses of the diagonal blocks
+// formed first (weig_dinv_kernel, all blocks at once), so that no step of the solve
+// waits on a chain of single rows.
 constexpr int SB = 64;   // row block of the back substitution
 constexpr int SC = 16;   // columns per workgroup
 
+// inv(R'_kk) for the diagonal block kb = blockIdx.x / 4, columns 16 (blockIdx.x % 4)
+// .. + 15: back substitution on those identity columns (lane (i, w): row i of
+// column w in a register, one barrier per row).  Written to Dinv (SB x SB per
+// block, column-major; zeros outside the block's size).
+__global__ void __launch_bounds__(1024)
+weig_dinv_kernel(int n, const Ctl *ctl, const double *__restrict__ Hh, double *__restrict__ Dinv) {
+    __shared__ double Dg[SB * (SB + 1)];
+    __shared__ double xb[SB * SC];
+    if (wg_read(&ctl->bad) || wg_read(&ctl->notconv)) return;
+    const int kb = blockIdx.x / 4, c = (blockIdx.x % 4) * SC + (threadIdx.x >> 6);
+    const int k0 = kb * SB;
+    const int bs = (n - k0 < SB) ? n - k0 : SB;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int q = tid; q < SB * SB; q += 1024) {
+        const int i = q % SB, j = q / SB;
+        Dg[i + j * (SB + 1)] = (i <= j && j < bs) ? Hh[(k0 + i) + (size_t)(k0 + j) * n] : 0.0;
+    }
+    __syncthreads();
+    double t = (lane == c && c < bs) ? 1.0 : 0.0;
+    for (int kk = bs - 1; kk >= 0; --kk) {
+        if (lane == kk) {
+            t = t / Dg[kk + kk * (SB + 1)];
+            xb[kk + w * SB] = t;
+        }
+        __syncthreads();
+        if (lane < kk) t = __builtin_fma(-Dg[lane + kk * (SB + 1)], xb[kk + w * SB], t);
+    }
+    Dinv[(size_t)kb * SB * SB + lane + (size_t)c * SB] = (lane < bs && c < bs) ? t : 0.0;
+}
+
+// One workgroup per 16 columns c (wavefront w owns column c0 + w):
+//   a. sigma_c = ||z_c|| and T(:, c) = Q(:, c) sigma_c in LDS;
+//   b. for the row blocks from the bottom: T'(block) = inv(R'_kk) T(block), then
+//      the rows above take the block's contribution, T(i) -= sum_k R'(i, k) T'(k),
+//      with R' staged through LDS in 64-row chunks;
+//   c. V'(r, c) = T'(r, c) 2^(emax - e_pi_r) (exact), the column normalised and
+//      written to V(pi_r, c).
 __global__ void __launch_bounds__(1024)
 weig_pre_out_kernel(int n, const Ctl *ctl, const int *__restrict__ sexp,
                     const int *__restrict__ perm, const double *__restrict__ Hh,
-                    const double *__restrict__ X, const double *__restrict__ Vw,
-                    double *__restrict__ V, int64_t ldv, int *__restrict__ info) {
+                    const double *__restrict__ Dinv, const double *__restrict__ X,
+                    const double *__restrict__ Vw, double *__restrict__ V, int64_t ldv,
+                    int *__restrict__ info) {
     extern __shared__ __attribute__((aligned(16))) double psm[];
-    double *T = psm;                    // GSVD_WIDE_MAX_N x SC, column-major
-    double *Dg = T + GSVD_WIDE_MAX_N * SC;  // SB x SB diagonal block, column-major, ld SB + 1
-    double *Xb = Dg + SB * (SB + 1);    // SB x SC block solution
+    double *T = psm;                        // GSVD_WIDE_MAX_N x SC, column-major
+    double *Dg = T + GSVD_WIDE_MAX_N * SC;  // SB x SB staging, column-major, ld SB + 1
+    double *Xb = Dg + SB * (SB + 1);        // SB x SC block solution
     const int bad = wg_read(&ctl->bad);
     const int code = bad ? bad : (wg_read(&ctl->notconv) ? 2 : 0);
     if (blockIdx.x == 0 && threadIdx.x == 0) *info = code;
@@ -710,6 +788,7 @@ weig_pre_out_kernel(int n, const Ctl *ctl, const int *__restrict__ sexp,
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int c0 = blockIdx.x * SC, c = c0 + w;
     const bool cv = c < n;
+    double *Tw = T + w * GSVD_WIDE_MAX_N;
     // a.
     {
         double ss = 0.0;
@@ -719,56 +798,52 @@ weig_pre_out_kernel(int n, const Ctl *ctl, const int *__restrict__ sexp,
                 ss = __builtin_fma(z, z, ss);
             }
         const double sg = __builtin_sqrt(wave_sum(ss));
-        for (int r = lane; r < n; r += 64) T[r + w * GSVD_WIDE_MAX_N] = cv ? Vw[r + (size_t)c * n] * sg : 0.0;
+        for (int r = lane; r < n; r += 64) Tw[r] = cv ? Vw[r + (size_t)c * n] * sg : 0.0;
     }
-    __syncthreads();
     // b.
     const int nb = (n + SB - 1) / SB;
     for (int kb = nb - 1; kb >= 0; --kb) {
         const int k0 = kb * SB;
         const int bs = (n - k0 < SB) ? n - k0 : SB;
-        for (int q = tid; q < SB * SB; q += 1024) {
-            const int i = q % SB, j = q / SB;
-            Dg[i + j * (SB + 1)] = (i <= j && j < bs) ? Hh[(k0 + i) + (size_t)(k0 + j) * n] : 0.0;
-        }
+        const double *Di = Dinv + (size_t)kb * SB * SB;
+        for (int q = tid; q < SB * SB; q += 1024) Dg[(q % SB) + (q / SB) * (SB + 1)] = Di[q];
         __syncthreads();
-        double t = lane < bs ? T[(k0 + lane) + w * GSVD_WIDE_MAX_N] : 0.0;
-        for (int kk = bs - 1; kk >= 0; --kk) {
-            if (lane == kk) {
-                t = t / Dg[kk + kk * (SB + 1)];
-                Xb[kk + w * SB] = t;
+        double x = 0.0;
+        if (lane < bs)
+            for (int j = lane; j < bs; ++j) x = __builtin_fma(Dg[lane + j * (SB + 1)], Tw[k0 + j], x);
+        if (lane < bs) Xb[lane + w * SB] = x;
+        __syncthreads();
+        if (lane < bs) Tw[k0 + lane] = x;
+        for (int rc = 0; rc < k0; rc += SB) {  // rows rc .. rc + 63 (all < k0)
+            for (int q = tid; q < SB * SB; q += 1024) {
+                const int i = q % SB, k = q / SB;
+                Dg[i + k * (SB + 1)] = k < bs ? Hh[(rc + i) + (size_t)(k0 + k) * n] : 0.0;
             }
             __syncthreads();
-            if (lane < kk) t = __builtin_fma(-Dg[lane + kk * (SB + 1)], Xb[kk + w * SB], t);
-        }
-        if (lane < bs) T[(k0 + lane) + w * GSVD_WIDE_MAX_N] = Xb[lane + w * SB];
-        // rows above the block: T(i, w) -= sum_k R'(i, k0 + k) T'(k0 + k, w)
-        for (int i = lane; i < k0; i += 64) {
             double acc = 0.0;
-            for (int k = 0; k < bs; ++k)
-                acc = __builtin_fma(Hh[i + (size_t)(k0 + k) * n], Xb[k + w * SB], acc);
-            T[i + w * GSVD_WIDE_MAX_N] -= acc;
+            for (int k = 0; k < bs; ++k) acc = __builtin_fma(Dg[lane + k * (SB + 1)], Xb[k + w * SB], acc);
+            Tw[rc + lane] -= acc;
+            __syncthreads();
         }
-        __syncthreads();
     }
     // c.
     if (!cv) return;
     const int emax = ctl->emax;
     double ss = 0.0;
     for (int r = lane; r < n; r += 64) {
-        const double v = ldexp(T[r + w * GSVD_WIDE_MAX_N], emax - sexp[perm[r]]);
-        T[r + w * GSVD_WIDE_MAX_N] = v;
+        const double v = ldexp(Tw[r], emax - sexp[perm[r]]);
+        Tw[r] = v;
         ss = __builtin_fma(v, v, ss);
     }
     const double inv = 1.0 / __builtin_sqrt(wave_sum(ss));
-    for (int r = lane; r < n; r += 64) V[perm[r] + (int64_t)c * ldv] = T[r + w * GSVD_WIDE_MAX_N] * inv;
+    for (int r = lane; r < n; r += 64) V[perm[r] + (int64_t)c * ldv] = Tw[r] * inv;
 }
 
 // The blocked dd Cholesky of H (upper triangle of Hh/Hl, in place).
 hipError_t chol_blocked(int n, Ctl *ctl, double *Hh, double *Hl, hipStream_t st) {
     hipError_t err;
-    const size_t lds_potrf = (size_t)CB * CB * sizeof(dd_t);
-    const size_t lds_panel = (size_t)CB * (CB + 16) * sizeof(dd_t);
+    const size_t lds_potrf = (size_t)CB * (CB + 1) * sizeof(dd_t);
+    const size_t lds_panel = (size_t)CB * (CB + 1 + 16) * sizeof(dd_t);
     const size_t lds_update = (size_t)2 * CB * 32 * sizeof(dd_t);
     if ((err = hipFuncSetAttribute((const void *)weig_potrf_kernel,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_potrf)) ||
@@ -923,12 +998,16 @@ hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, in
 #undef STEPS
     if (err != hipSuccess) return err;
     if (pre) {
+        double *Dinv = reinterpret_cast<double *>(base + L.dinv);
+        hipLaunchKernelGGL(weig_dinv_kernel, dim3((unsigned)(4 * ((n + SB - 1) / SB))), dim3(1024),
+                           0, st, n, ctl, Hh, Dinv);
+        WCHK();
         const size_t lds = ((size_t)GSVD_WIDE_MAX_N * SC + SB * (SB + 1) + SB * SC) * sizeof(double);
         if ((err = hipFuncSetAttribute((const void *)weig_pre_out_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
             return err;
         hipLaunchKernelGGL(weig_pre_out_kernel, dim3((unsigned)((n + SC - 1) / SC)), dim3(1024), lds,
-                           st, n, ctl, sexp, perm, Hh, X, Vw, (double *)V, ldv, info);
+                           st, n, ctl, sexp, perm, Hh, Dinv, X, Vw, (double *)V, ldv, info);
         WCHK();
         return hipSuccess;
     }
