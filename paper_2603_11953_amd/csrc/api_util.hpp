@@ -310,12 +310,13 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
                                       scr, st)
                       : cast_eig_f32_launch(n, s64, v64, S, V, ldv, W, ldw, info, st);
     } else if (o->working == GSVD_F64) {
-        const bool pre = wide_eig(o, n) && eig_refined(o, n);
+        const bool pre = eig_refined(o, n);
         const double tol = pre ? pre_tol_of(o) : alg2_tol_of(o, n);
+        const int nsw = pre ? pre_sweeps_of(o) : sweeps;
         err = wide_eig(o, n)
-                  ? eig_wide_launch(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol,
-                                    pre ? pre_sweeps_of(o) : sweeps, pre, work, st)
-                  : eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, sweeps,
+                  ? eig_wide_launch(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, nsw, pre, work,
+                                    st)
+                  : eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol, nsw, pre,
                                st);
         if (err == hipSuccess && eig_refined(o, n))
             err = refine_launch(GSVD_F64, n, Mhi, Mlo, ldm, (const double *)V, ldv, S, V, ldv, W,
@@ -325,7 +326,7 @@ inline hipError_t eig_any(const gsvd_opts *o, int64_t n, const double *Mhi, cons
                                  jacobi_tol_of(o, n), sweeps, work, st);
     } else {
         err = eig_launch(o->working, n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info,
-                         jacobi_tol_of(o, n), sweeps, st);
+                         jacobi_tol_of(o, n), sweeps, false, st);
     }
     if (err != hipSuccess) return err;
     return assump_launch(o->working, n, Mhi, ldm, W, ldw, info, e_gram,

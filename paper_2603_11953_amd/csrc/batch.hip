@@ -261,16 +261,18 @@ int gsvd_thin_batched(int batch, const int64_t *hM, const int64_t *hN, const voi
                        : gram_reduce_batched_launch(tab, batch, P.max_n, st);
     if (err != hipSuccess) return GSVD_ERR_HIP;
     if (o->working == GSVD_F64) {
-        err = eig_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol,
-                                 sweeps_of(o), st);
-        if (err == hipSuccess && eig_mode_of(o) == GSVD_EIG_JACOBI2)
-            err = refine_batched_launch(tab, batch, P.max_n, st);
+        const bool pre = eig_mode_of(o) == GSVD_EIG_JACOBI2;
+        err = pre ? eig_batched_launch(o->working, tab, order, batch, P.max_n, pre_tol_of(o),
+                                       pre_sweeps_of(o), true, st)
+                  : eig_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol,
+                                       sweeps_of(o), false, st);
+        if (err == hipSuccess && pre) err = refine_batched_launch(tab, batch, P.max_n, st);
     } else {
         err = eig_mode_of(o) == GSVD_EIG_JACOBI2
                   ? eig_jacobi2_batched_launch(o->working, tab, order, batch, P.max_n,
                                                o->jacobi_tol, sweeps_of(o), st)
                   : eig_batched_launch(o->working, tab, order, batch, P.max_n, o->jacobi_tol,
-                                       sweeps_of(o), st);
+                                       sweeps_of(o), false, st);
     }
     if (err == hipSuccess)
         err = assump_batched_launch(o->working, tab, batch, gram_pert_of(o, P.max_n),

@@ -118,17 +118,26 @@ struct EigSmem {
     double ssig[GSVD_KMAX_N];
     int srank[GSVD_KMAX_N];
     double ssign[GSVD_KMAX_N];
+    int sperm[GSVD_KMAX_N];  // preconditioner form: the column of rank r by m_jj, descending
     dd_t rowk[GSVD_KMAX_N];
     dd_t rpiv[GSVD_KMAX_N + 1];  // reciprocal pivots of the Cholesky
 };
 
 // Algorithm 2 for one n x n Gram (one workgroup; n <= GRP * RPL, RPL even).
+//
+// pre (FP64 working only): the preconditioner form for the double-double stage,
+// as in the multi-workgroup eigensolver: the columns ordered by decreasing m_jj
+// (pi), the Jacobi run on the transposed factor Z = X'^T of the reordered problem,
+// and V' = X'^-1 Q Sigma_Z by back substitution (R' is kept in W for it; W is
+// rewritten by the next stage), V = P V' with unit columns in no particular order
+// or sign.  S is not written.
 template <typename TW, typename TS, bool DDGRAM, int RPL>
 __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                                          const double *__restrict__ Mlo, int64_t ldm,
                                          TW *__restrict__ S, TW *__restrict__ V, int64_t ldv,
                                          TW *__restrict__ W, int64_t ldw, int *__restrict__ info,
-                                         double tol2, int max_sweeps, EigSmem &sm, double *lds) {
+                                         double tol2, int max_sweeps, bool pre, EigSmem &sm,
+                                         double *lds) {
     EigShared &sh = sm.sh;
     int *sexp = sm.sexp;
     double *ssig = sm.ssig;
@@ -138,6 +147,7 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
+    pre = pre && sizeof(TS) == sizeof(double);  // FP64 working only
 
     if (tid == 0) {
         sh.flag_rot = 0;
@@ -168,6 +178,20 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
         if (tid == 0) *info = sh.flag_bad;
         return;
     }
+    int *sperm = sm.sperm;
+    if (pre) {  // rank by m_jj descending, ties by index (every m_jj is positive here)
+        for (int j = tid; j < n; j += nthr) {
+            const double mj = Mhi[j + (int64_t)j * ldm];
+            int r = 0;
+            for (int q = 0; q < n; ++q) {
+                const double mq = Mhi[q + (int64_t)q * ldm];
+                r += (mq > mj) || (mq == mj && q < j);
+            }
+            sperm[r] = j;
+        }
+        __syncthreads();
+    }
+    auto pix = [&](int i) { return pre ? sperm[i] : i; };
 
     // ---- 2. H = D~^-1 M D~^-1 (exact) in the upper triangle of an n x n square
     //      in LDS, leading dimension n + 1 (a row's entries fall in different
@@ -178,10 +202,12 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
     for (int q = tid; q < n * n; q += nthr) {
         const int i = q % n, j = q / n;
         if (i > j) continue;
-        const int sc = -(sexp[i] + sexp[j]);
-        const double hi = ldexp(Mhi[i + (int64_t)j * ldm], sc);
+        const int pi = pix(i), pj = pix(j);
+        const int a = pi < pj ? pi : pj, b = pi < pj ? pj : pi;  // upper triangle of M_h
+        const int sc = -(sexp[pi] + sexp[pj]);
+        const double hi = ldexp(Mhi[a + (int64_t)b * ldm], sc);
         if (DDGRAM) {
-            Hd[i + j * lh] = dd_t{hi, ldexp(Mlo[i + (int64_t)j * ldm], sc)};
+            Hd[i + j * lh] = dd_t{hi, ldexp(Mlo[a + (int64_t)b * ldm], sc)};
         } else {
             Hs[i + j * lh] = hi;
         }
@@ -289,7 +315,8 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
             if (i <= j) {
                 const double h = DDGRAM ? dd_mul(Hd[i + j * lh], rowk[i]).hi
                                         : Hs[i + j * lh] * rowk[i].hi;  // r_ij
-                rv[c] = ldexp((double)(TW)h, sexp[j] - emax);  // round to working, rescale
+                rv[c] = ldexp((double)(TW)h, sexp[pix(j)] - emax);  // round to working, rescale
+                if (pre) W[i + (int64_t)j * ldw] = (TW)h;  // R' for the back substitution
             }
         }
     }
@@ -308,7 +335,10 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
         const int q = tid + c * nthr;
         if (q < n * n) {
             const int r = q % n, col = q / n;
-            Y[r + col * ld] = (TS)rv[c];
+            if (pre)
+                Y[col + r * ld] = (TS)rv[c];  // Z = X'^T
+            else
+                Y[r + col * ld] = (TS)rv[c];
             if (r == col) Vs[r + col * ld] = (TS)1;
         }
     }
@@ -496,6 +526,57 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
         return;
     }
 
+    if (pre) {
+        // ---- 5'. V' = X'^-1 Q Sigma_Z: T = Q Sigma_Z over Q in Vs, R' (in W) to the Y
+        //      area, back substitution one row per barrier, the reciprocal of R'_kk
+        //      applied to each row once it is final; then V(pi_r, p) = V'(r, p)
+        //      2^-e_pi_r (exact), columns normalised
+        for (int p = grp; p < n; p += ngrp) {
+            double ss = 0.0;
+            for (int r = gl; r < n; r += GRP) {
+                const double x = (double)Y[r + p * ld];
+                ss = __builtin_fma(x, x, ss);
+            }
+            ss = group_sum(ss);
+            if (gl == 0) ssig[p] = __builtin_sqrt(ss);
+        }
+        __syncthreads();
+        double *T = reinterpret_cast<double *>(Vs);  // TS = double in this form
+        double *Rt = reinterpret_cast<double *>(Y);
+        for (int q = tid; q < n * n; q += nthr) {
+            const int r = q % n, p = q / n;
+            T[r + p * ld] *= ssig[p];
+            Rt[r + p * ld] = r <= p ? (double)W[r + (int64_t)p * ldw] : 0.0;
+        }
+        __syncthreads();
+        for (int k = tid; k < n; k += nthr) ssign[k] = 1.0 / Rt[k + k * ld];
+        __syncthreads();
+        for (int k = n - 1; k >= 1; --k) {
+            // rows r < k take row k's contribution; row k is final (not yet scaled)
+            const double rk = ssign[k];
+            for (int q = tid; q < k * n; q += nthr) {
+                const int r = q % k, p = q / k;
+                T[r + p * ld] = __builtin_fma(-Rt[r + k * ld], rk * T[k + p * ld], T[r + p * ld]);
+            }
+            __syncthreads();
+        }
+        const int emaxp = emax;
+        for (int q = tid; q < n * n; q += nthr) {
+            const int r = q % n, p = q / n;
+            T[r + p * ld] = ldexp(T[r + p * ld] * ssign[r], emaxp - sexp[sperm[r]]);
+        }
+        __syncthreads();
+        for (int p = grp; p < n; p += ngrp) {
+            double ss = 0.0;
+            for (int r = gl; r < n; r += GRP) ss = __builtin_fma(T[r + p * ld], T[r + p * ld], ss);
+            ss = group_sum(ss);
+            const double inv = 1.0 / __builtin_sqrt(ss);
+            for (int r = gl; r < n; r += GRP) V[sperm[r] + (int64_t)p * ldv] = (TW)(T[r + p * ld] * inv);
+        }
+        if (tid == 0) *info = 0;
+        return;
+    }
+
     // ---- 5. sigma_p = ||y_p|| 2^emax, ordering, sign of V columns, cast, W
     for (int p = grp; p < n; p += ngrp) {
         const TS *yp = Y + p * ld;
@@ -554,11 +635,11 @@ __global__ void __launch_bounds__(eig_bound(RPL))
 eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__restrict__ Mlo,
                         int64_t ldm, TW *__restrict__ S, TW *__restrict__ V, int64_t ldv,
                         TW *__restrict__ W, int64_t ldw, int *__restrict__ info, double tol2,
-                        int max_sweeps) {
+                        int max_sweeps, bool pre) {
     extern __shared__ double lds[];
     __shared__ EigSmem sm;
-    eig_body<TW, TS, DDGRAM, RPL>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2, max_sweeps, sm,
-                                  lds);
+    eig_body<TW, TS, DDGRAM, RPL>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2, max_sweeps, pre,
+                                  sm, lds);
 }
 
 // Batched: one workgroup per problem, the largest first (order is ascending in
@@ -567,7 +648,7 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
 template <typename TW, typename TS, bool DDGRAM, int MAXRPL>
 __global__ void __launch_bounds__(eig_bound(MAXRPL))
 eig_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order, int batch,
-                   double tol, int max_sweeps) {
+                   double tol, int max_sweeps, bool pre) {
     extern __shared__ double lds[];
     __shared__ EigSmem sm;
     const BatchMat &d = tab[order[batch - 1 - (int)blockIdx.x]];
@@ -580,7 +661,7 @@ eig_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ ord
         if (R <= MAXRPL)                                                                        \
             eig_body<TW, TS, DDGRAM, (R <= MAXRPL ? R : 2)>(                                    \
                 n, d.Mhi, Mlo, n, (TW *)d.S, (TW *)d.V, d.ldv, (TW *)d.W, n, d.info, tol2,      \
-                max_sweeps, sm, lds);                                                           \
+                max_sweeps, pre, sm, lds);                                                      \
         break;
     switch (eig_rpl(n)) {
         GSVD_EIG_BODY(2) GSVD_EIG_BODY(4) GSVD_EIG_BODY(6) GSVD_EIG_BODY(8)
@@ -614,24 +695,24 @@ int eig_threads(int64_t n) {
 template <typename TW, typename TS, bool DD, int RPL>
 static hipError_t launch_rpl(int64_t n, const double *Mhi, const double *Mlo, int64_t ldm, void *S,
                              void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol2,
-                             int max_sweeps, size_t lds, int thr, hipStream_t st) {
+                             int max_sweeps, bool pre, size_t lds, int thr, hipStream_t st) {
     auto k = eig_chol_jacobi1_kernel<TW, TS, DD, RPL>;
     hipError_t err = hipFuncSetAttribute((const void *)k,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k, dim3(1), dim3(thr), lds, st, (int)n, Mhi, Mlo, ldm, (TW *)S, (TW *)V,
-                       ldv, (TW *)W, ldw, info, tol2, max_sweeps);
+                       ldv, (TW *)W, ldw, info, tol2, max_sweeps, pre);
     return hipGetLastError();
 }
 
 template <typename TW, typename TS, bool DD>
 static hipError_t launch_t(int64_t n, const double *Mhi, const double *Mlo, int64_t ldm, void *S,
                            void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol2,
-                           int max_sweeps, size_t lds, int thr, hipStream_t st) {
+                           int max_sweeps, bool pre, size_t lds, int thr, hipStream_t st) {
 #define GSVD_EIG_CASE(R)                                                                       \
     case R:                                                                                    \
         return launch_rpl<TW, TS, DD, R>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2,     \
-                                         max_sweeps, lds, thr, st);
+                                         max_sweeps, pre, lds, thr, st);
     switch (eig_rpl((int)n)) {
         GSVD_EIG_CASE(2)
         GSVD_EIG_CASE(4)
@@ -648,7 +729,7 @@ static hipError_t launch_t(int64_t n, const double *Mhi, const double *Mlo, int6
 
 hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *Mlo, int64_t ldm,
                       void *S, void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
-                      int max_sweeps, hipStream_t st) {
+                      int max_sweeps, bool pre, hipStream_t st) {
     const size_t lds = eig_lds_bytes(working, n);
     const int thr = eig_threads(n);
     if (n < 1 || n > eig_max_n(working)) return hipErrorInvalidValue;
@@ -658,26 +739,27 @@ hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *M
     if (working == 1) {
         if (Mlo == nullptr) return hipErrorInvalidValue;
         return launch_t<double, double, true>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2,
-                                              max_sweeps, lds, thr, st);
+                                              max_sweeps, pre, lds, thr, st);
     }
+    if (pre) return hipErrorInvalidValue;
     return launch_t<float, float, false>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2,
-                                         max_sweeps, lds, thr, st);
+                                         max_sweeps, false, lds, thr, st);
 }
 
 template <typename TW, typename TS, bool DD, int MAXRPL>
 static hipError_t eig_batched_t(const BatchMat *tab, const int *order, int batch, size_t lds,
-                                int thr, double tol, int max_sweeps, hipStream_t st) {
+                                int thr, double tol, int max_sweeps, bool pre, hipStream_t st) {
     auto k = eig_batched_kernel<TW, TS, DD, MAXRPL>;
     hipError_t err = hipFuncSetAttribute((const void *)k,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k, dim3((unsigned)batch), dim3(thr), lds, st, tab, order, batch, tol,
-                       max_sweeps);
+                       max_sweeps, pre);
     return hipGetLastError();
 }
 
 hipError_t eig_batched_launch(int working, const BatchMat *tab, const int *order, int batch,
-                              int max_n, double tol, int max_sweeps, hipStream_t st) {
+                              int max_n, double tol, int max_sweeps, bool pre, hipStream_t st) {
     if (batch < 1 || max_n < 1 || max_n > eig_max_n(working)) return hipErrorInvalidValue;
     const size_t lds = eig_lds_bytes(working, max_n);
     // every problem runs with the lanes and register depth of the largest one
@@ -687,13 +769,14 @@ hipError_t eig_batched_launch(int working, const BatchMat *tab, const int *order
     if (thr / GRP < eig_pow2(max_n) / 2) return hipErrorInvalidValue;  // one group per pair
     if (working == 1)
         return big ? eig_batched_t<double, double, true, 12>(tab, order, batch, lds, thr, tol,
-                                                               max_sweeps, st)
+                                                               max_sweeps, pre, st)
                    : eig_batched_t<double, double, true, 8>(tab, order, batch, lds, thr, tol,
-                                                              max_sweeps, st);
+                                                              max_sweeps, pre, st);
+    if (pre) return hipErrorInvalidValue;
     return big ? eig_batched_t<float, float, false, 16>(tab, order, batch, lds, thr, tol,
-                                                         max_sweeps, st)
+                                                         max_sweeps, false, st)
                : eig_batched_t<float, float, false, 8>(tab, order, batch, lds, thr, tol,
-                                                        max_sweeps, st);
+                                                        max_sweeps, false, st);
 }
 
 }  // namespace gsvd

@@ -140,13 +140,16 @@ hipError_t split_batched_f32(const BatchMat *tab, const int *order, int first, i
 size_t eig_lds_bytes(int working, int64_t n);
 int eig_max_n(int working);
 int eig_threads(int64_t n);
+// pre (FP64 working): the preconditioner form for the double-double stage (columns
+// ordered by norm, Jacobi on the transposed factor, V by back substitution); it
+// writes V (unit columns, unordered, unsigned), uses W as scratch, and sets info.
 hipError_t eig_launch(int working, int64_t n, const double *Mhi, const double *Mlo, int64_t ldm,
                       void *S, void *V, int64_t ldv, void *W, int64_t ldw, int *info, double tol,
-                      int max_sweeps, hipStream_t st);
+                      int max_sweeps, bool pre, hipStream_t st);
 // Batched: one workgroup per problem, problems taken in the order given
 // (order[batch - 1 - block]); tol = 0 means sqrt(n) u per problem.
 hipError_t eig_batched_launch(int working, const BatchMat *tab, const int *order, int batch,
-                              int max_n, double tol, int max_sweeps, hipStream_t st);
+                              int max_n, double tol, int max_sweeps, bool pre, hipStream_t st);
 
 // Algorithm 2 for FP64 working and n > 96 (eig_wide.hip): a sequence of
 // launches (blocked dd Cholesky, block one-sided Jacobi) over device scratch.
