@@ -62,18 +62,21 @@ enum {
 enum {
     GSVD_EIG_AUTO = 0,       /* JACOBI2 */
     GSVD_EIG_JACOBI2 = 1,    /* two-sided Jacobi on M_h at u_h (Sec. 2.1, Remark 1).
-                                FP32 working, n <= 128: M_h and the rotations in FP64,
+                                FP32 working, n <= 96: M_h and the rotations in FP64,
                                 round-robin sweeps in one workgroup; default threshold
-                                n * 2^-53; V needs gsvd_eig_workspace_size bytes of
-                                scratch when n > 96.
-                                FP64 working (any n), and FP32 working with n > 128: the
+                                n * 2^-53.
+                                FP64 working (any n), and FP32 working with n > 96: the
                                 Jacobi sweeps run in double-double on the Gram matrix
-                                preconditioned by Algorithm 2's eigenvectors X, i.e. on
-                                X^T M_h X, whose rotations are all small; a sweep applies
-                                its rotations together to first order in the angles
-                                (X <- X (I + F), Ogita-Aishima form, which also restores
-                                X^T X = I), until the largest angle is <= 2^-30.  The
-                                threshold option applies to the Algorithm 2 stage. */
+                                expressed in a preconditioning eigenvector basis X, i.e.
+                                on X^T M_h X, whose rotations are all small; a sweep
+                                applies its rotations together to first order in the
+                                angles (X <- X (I + F), Ogita-Aishima form, which also
+                                restores X^T X = I), until the largest angle is <= 2^-30.
+                                X comes from Algorithm 2's steps in FP64 with the columns
+                                ordered by decreasing m_jj and the one-sided Jacobi run on
+                                the transposed Cholesky factor (X by back substitution);
+                                its threshold is jacobi_tol (default 2^-24) and its sweep
+                                limit max_sweeps (default 16). */
     GSVD_EIG_CHOL_JACOBI1 = 2 /* Algorithm 2: Cholesky of M_h at u_h, R cast to u,
                                  one-sided Jacobi SVD of R (Thm. 2, Lemma 1); default
                                  threshold sqrt(n) * u.  FP32 working with n > 128: the
@@ -107,7 +110,7 @@ enum {
                                      table's measured error) or, with Algorithm 2, when
                                      n u kappa > 1/2 (its O(u) kappa(B) condition) */
 #define GSVD_INFO_WARN_REFINE 512 /* the double-double Jacobi stage of JACOBI2 (FP64
-                                     working, or n > 128) left pairs of eigenvalues that
+                                     working, or FP32 with n > 96) left pairs of eigenvalues that
                                      agree to within their coupling unrotated, or its
                                      last sweep had an angle above 2^-30 */
 
@@ -115,9 +118,9 @@ enum {
                                      the wide kernels (64-column panel pairs, blocked
                                      Cholesky, block Jacobi) */
 #define GSVD_MAX_N_EIG_F32 512    /* FP32 working: largest n of the eigensolver stage
-                                     (n > 128: Algorithm 2 over many workgroups with the
-                                     SVD of R in FP64, plus the double-double Jacobi
-                                     stage for JACOBI2) */
+                                     (n > 128, or n > 96 for JACOBI2: Algorithm 2's steps
+                                     over many workgroups in FP64, plus the double-double
+                                     Jacobi stage for JACOBI2) */
 #define GSVD_MAX_N_BATCHED_F64 96 /* largest n of a batched problem, FP64 working */
 #define GSVD_MAX_N_BATCHED_F32 128 /* largest n of a batched problem, FP32 working */
 #define GSVD_MAX_SLICES 12        /* largest n_slices of the split Gram, FP64 A */
@@ -207,8 +210,9 @@ int gsvd_gram(int64_t m, int64_t n, const void *dA, int64_t lda,
  * for FP32 working) compute S (n, descending, working precision), V (n x n,
  * ldv >= n, working precision) and W = fl(V diag(S)^{-1}) (n x n, ldw >= n,
  * working precision, the matrix that Alg. 1 step 6 multiplies A by), and *dInfo.
- * work: gsvd_eig_workspace_size(n, o) bytes (0 except for JACOBI2 with n > 96;
- * may then be NULL).
+ * work: gsvd_eig_workspace_size(n, o) bytes (0 only for CHOL_JACOBI1 with n <= 96
+ * (FP64 working) or n <= 128 (FP32), and for JACOBI2 with FP32 working and n <= 96;
+ * work may then be NULL).
  * Arguments: 1 n, 2 dMhi, 3 dMlo, 4 ldm, 5 dS, 6 dV, 7 ldv, 8 dW, 9 ldw,
  * 10 dInfo, 11 work, 12 work_bytes, 13 o, 14 stream.
  */

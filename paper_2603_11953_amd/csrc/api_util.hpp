@@ -55,19 +55,22 @@ inline int check_supported(const gsvd_opts *o) {
 
 // n > 128: the wide Gram and U kernels (64-column panels)
 inline bool wide_n(int64_t n) { return n > GSVD_KMAX_N; }
-// FP32 working beyond the one-workgroup eigensolvers: Algorithm 2 over many
-// workgroups with the SVD of R in FP64, results rounded to FP32
+// FP32 working on the multi-workgroup eigensolver (Algorithm 2's steps in FP64,
+// results rounded to FP32): beyond the one-workgroup kernels (n > 128), and for
+// JACOBI2 from n > 96 on, where its preconditioner and the double-double stage
+// beat the one-workgroup two-sided Jacobi
 inline bool f32_wide_eig(const gsvd_opts *o, int64_t n) {
-    return o->working == GSVD_F32 && n > GSVD_KMAX_N;
+    return o->working == GSVD_F32 &&
+           (n > GSVD_KMAX_N || (eig_mode_of(o) == GSVD_EIG_JACOBI2 && n > GSVD_KMAX_N_F64));
 }
 // beyond the one-workgroup eigensolver: the multi-launch Algorithm 2
 inline bool wide_eig(const gsvd_opts *o, int64_t n) {
     return (o->working == GSVD_F64 && n > GSVD_KMAX_N_F64) || f32_wide_eig(o, n);
 }
-// the double-double Jacobi stage after Algorithm 2 (JACOBI2 for FP64 working,
-// and for FP32 working beyond the one-workgroup two-sided Jacobi)
+// the double-double Jacobi stage after the preconditioner (JACOBI2 for FP64
+// working, and for FP32 working beyond the one-workgroup two-sided Jacobi)
 inline bool eig_refined(const gsvd_opts *o, int64_t n) {
-    return eig_mode_of(o) == GSVD_EIG_JACOBI2 && (o->working == GSVD_F64 || n > GSVD_KMAX_N);
+    return eig_mode_of(o) == GSVD_EIG_JACOBI2 && (o->working == GSVD_F64 || f32_wide_eig(o, n));
 }
 
 inline int check_eig_supported(const gsvd_opts *o, int64_t n) {
@@ -226,7 +229,7 @@ inline double pre_tol_of(const gsvd_opts *o) {
 // M_h (FP32 working, FP64), else Algorithm 2's
 inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
     if (o->jacobi_tol > 0) return o->jacobi_tol;
-    if (eig_mode_of(o) == GSVD_EIG_JACOBI2 && o->working == GSVD_F32 && !wide_n(n))
+    if (eig_mode_of(o) == GSVD_EIG_JACOBI2 && o->working == GSVD_F32 && !f32_wide_eig(o, n))
         return (double)n * 0x1p-53;
     return alg2_tol_of(o, n);
 }
@@ -260,7 +263,7 @@ inline EigLayout eig_layout(const gsvd_opts *o, int64_t n) {
     size_t scratch = 0;
     if (wide_eig(o, n)) scratch = eig_wide_work_bytes(n);
     if (eig_refined(o, n)) scratch = scratch > refine_work_bytes(n) ? scratch : refine_work_bytes(n);
-    if (o->working == GSVD_F32 && !wide_n(n) && eig_mode_of(o) == GSVD_EIG_JACOBI2)
+    if (o->working == GSVD_F32 && !f32_wide_eig(o, n) && eig_mode_of(o) == GSVD_EIG_JACOBI2)
         scratch = j2_work_bytes(n, sweeps_of(o));
     size_t off = 0;
     if (f32_wide_eig(o, n)) {

@@ -178,15 +178,17 @@ def test_single_hip_runtime_in_process():
 
 
 def test_wide_limits():
-    """n in 129..512 runs the wide kernels, for both working precisions; the eigensolver
-    scratch covers Algorithm 2 and the double-double Jacobi stage (11 n^2 doubles)."""
+    """n in 129..512 runs the wide kernels, for both working precisions (from n = 97 on
+    for the default eigensolver); the eigensolver scratch covers the multi-workgroup
+    preconditioner and the double-double Jacobi stage (11 n^2 doubles)."""
     for w in (gs.GSVD_F64, gs.GSVD_F32):
         for eig in (gs.GSVD_EIG_AUTO, gs.GSVD_EIG_CHOL_JACOBI1):
             o = gs.opts(w, eig=eig)
-            for n in (97, 129, 512):
+            for n in (97, 128, 129, 512):
                 t = gs.gsvd_thin_workspace_size(4 * n, n, ctypes.byref(o))
                 e = gs.gsvd_eig_workspace_size(n, ctypes.byref(o))
-                if w == gs.GSVD_F32 and n <= 128:
+                if w == gs.GSVD_F32 and n <= 128 and eig == gs.GSVD_EIG_CHOL_JACOBI1:
+                    assert e == 0  # the one-workgroup Algorithm 2
                     continue
                 assert t % 256 == 0 and e > 4 * n * n * 8 and t > e, (w, eig, n)
                 if eig == gs.GSVD_EIG_AUTO:
