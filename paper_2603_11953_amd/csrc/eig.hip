@@ -82,8 +82,10 @@ struct Vec2<float> {
 struct EigShared {
     int flag_rot;
     int flag_big;  // a rotation of the sweep had |sin| >= 2^-22
+    int flag_pre;  // a pair rotated in the sweep had a cosine >= 2^-10
     int flag_bad;  // GSVD info code, 0 = fine
     int emax;
+    int pad[3];    // 32 bytes: the arrays after it stay 16-byte aligned
 };
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -130,14 +132,15 @@ struct EigSmem {
 // (pi), the Jacobi run on the transposed factor Z = X'^T of the reordered problem,
 // and V' = X'^-1 Q Sigma_Z by back substitution (R' is kept in W for it; W is
 // rewritten by the next stage), V = P V' with unit columns in no particular order
-// or sign.  S is not written.
+// or sign.  S is not written.  early: the sweep whose rotated pairs all had cosines
+// below 2^-10 is the last (single problems; the batched call converges fully).
 template <typename TW, typename TS, bool DDGRAM, int RPL>
 __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                                          const double *__restrict__ Mlo, int64_t ldm,
                                          TW *__restrict__ S, TW *__restrict__ V, int64_t ldv,
                                          TW *__restrict__ W, int64_t ldw, int *__restrict__ info,
-                                         double tol2, int max_sweeps, bool pre, EigSmem &sm,
-                                         double *lds) {
+                                         double tol2, int max_sweeps, bool pre, bool early,
+                                         EigSmem &sm, double *lds) {
     EigShared &sh = sm.sh;
     int *sexp = sm.sexp;
     double *ssig = sm.ssig;
@@ -152,6 +155,7 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
     if (tid == 0) {
         sh.flag_rot = 0;
         sh.flag_big = 0;
+        sh.flag_pre = 0;
         sh.flag_bad = 0;
         sh.emax = -100000;
     }
@@ -444,6 +448,7 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
                         if (gl == 0) {
                             sh.flag_rot = 1;
                             if (__builtin_fabs(sn) >= 0x1p-22) sh.flag_big = 1;
+                            if (ga * ga >= 0x1p-20 * (al * be)) sh.flag_pre = 1;
                         }
                     }
                 }
@@ -465,13 +470,17 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
             }
             __syncthreads();
         }
-        const bool any = sh.flag_rot != 0, big = sh.flag_big != 0;
+        const bool any = sh.flag_rot != 0, big = sh.flag_big != 0, bigpre = sh.flag_pre != 0;
         __syncthreads();
         if (tid == 0) {
             sh.flag_rot = 0;
             sh.flag_big = 0;
+            sh.flag_pre = 0;
         }
-        if (!any) {
+        if (!any || (early && !bigpre)) {
+            // preconditioner form, early stop: a sweep whose rotated pairs all had
+            // cosines below 2^-10 is the last (quadratic convergence leaves cosines of
+            // order 2^-20 or less)
             converged = true;
         } else if (!big) {
             // The rotations of this sweep were all tiny, so the next sweep most
@@ -636,10 +645,10 @@ eig_chol_jacobi1_kernel(int n, const double *__restrict__ Mhi, const double *__r
                         int64_t ldm, TW *__restrict__ S, TW *__restrict__ V, int64_t ldv,
                         TW *__restrict__ W, int64_t ldw, int *__restrict__ info, double tol2,
                         int max_sweeps, bool pre) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     __shared__ EigSmem sm;
     eig_body<TW, TS, DDGRAM, RPL>(n, Mhi, Mlo, ldm, S, V, ldv, W, ldw, info, tol2, max_sweeps, pre,
-                                  sm, lds);
+                                  pre, sm, lds);
 }
 
 // Batched: one workgroup per problem, the largest first (order is ascending in
@@ -649,7 +658,7 @@ template <typename TW, typename TS, bool DDGRAM, int MAXRPL>
 __global__ void __launch_bounds__(eig_bound(MAXRPL))
 eig_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order, int batch,
                    double tol, int max_sweeps, bool pre) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     __shared__ EigSmem sm;
     const BatchMat &d = tab[order[batch - 1 - (int)blockIdx.x]];
     const int n = d.n;
@@ -661,7 +670,7 @@ eig_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ ord
         if (R <= MAXRPL)                                                                        \
             eig_body<TW, TS, DDGRAM, (R <= MAXRPL ? R : 2)>(                                    \
                 n, d.Mhi, Mlo, n, (TW *)d.S, (TW *)d.V, d.ldv, (TW *)d.W, n, d.info, tol2,      \
-                max_sweeps, pre, sm, lds);                                                      \
+                max_sweeps, pre, false, sm, lds);                                               \
         break;
     switch (eig_rpl(n)) {
         GSVD_EIG_BODY(2) GSVD_EIG_BODY(4) GSVD_EIG_BODY(6) GSVD_EIG_BODY(8)

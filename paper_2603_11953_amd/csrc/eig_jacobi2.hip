@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(1024)
 eig_jacobi2_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, TW *__restrict__ S,
                    TW *__restrict__ V, int64_t ldv, TW *__restrict__ W, int64_t ldw,
                    int *__restrict__ info, double tol, int max_sweeps, double *__restrict__ vglob) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     __shared__ J2Smem sm;
     eig_jacobi2_body<TW, false>(n, Mhi, ldm, S, V, ldv, W, ldw, info, tol, max_sweeps, vglob, sm,
                                 lds);
@@ -318,7 +318,7 @@ template <typename TW>
 __global__ void __launch_bounds__(1024)
 eig_jacobi2_log_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, double tol,
                        int max_sweeps, double *__restrict__ work) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     __shared__ J2Smem sm;
     eig_jacobi2_body<TW, true>(n, Mhi, ldm, (TW *)nullptr, (TW *)nullptr, 0, (TW *)nullptr, 0,
                                (int *)nullptr, tol, max_sweeps, work, sm, lds);
@@ -458,7 +458,7 @@ template <typename TW>
 __global__ void __launch_bounds__(1024)
 eig_jacobi2_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order,
                            int batch, double tol, int max_sweeps, int vglobal) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     __shared__ J2Smem sm;
     const BatchMat &d = tab[order[batch - 1 - (int)blockIdx.x]];
     const double t = tol > 0.0 ? tol : (double)d.n * 0x1p-53;

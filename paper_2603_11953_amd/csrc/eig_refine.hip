@@ -1,5 +1,5 @@
 // Two-sided Jacobi on M_h at the Gram precision (Sec. 2.1, Remark 1),
-// preconditioned by Algorithm 2.
+// preconditioned by an FP64 eigenvector basis.
 //
 // Remark 1 bounds the orthogonality of U by O(u) + O(u_h) kappa^2(B) when the
 // eigensolver of Alg. 1 step 3 is the two-sided Jacobi method run at u_h; with
@@ -8,8 +8,11 @@
 // working precision, so its V diagonalises M_h only to O(u kappa(B)) in the
 // scaled sense |x_i^T M_h x_j| <= eps sqrt(lambda_i lambda_j).
 //
-// This stage runs the u_h Jacobi method on the Gram matrix expressed in the
-// basis X that Algorithm 2 returned:
+// This stage runs the u_h Jacobi method on the Gram matrix expressed in a
+// basis X from the FP64 eigensolvers: Algorithm 2's steps with the columns
+// ordered by norm and the one-sided Jacobi run on the transposed Cholesky factor
+// (X by back substitution, accurate in the graded sense), stopped once a sweep
+// rotates no pair whose cosine reaches 2^-10 (single problems):
 //
 //   S = X^T M_h X,  G = X^T X               (double-double, exact products)
 //   lambda_i = s_ii / g_ii                  (Rayleigh quotients)
@@ -17,8 +20,8 @@
 //   f_ii = (1 - g_ii) / 2
 //   X <- X (I + F)                          (double-double)
 //
-// S is diagonal up to the O(u kappa(B)) coupling left by Algorithm 2, so every
-// Jacobi rotation of a sweep on S is tiny.  The antisymmetric part of F holds
+// S is diagonal up to the small coupling that basis leaves, so every Jacobi
+// rotation of a sweep on S is tiny.  The antisymmetric part of F holds
 // the first-order angles of those rotations (tan 2 theta = 2 s_ij /
 // (s_jj - s_ii) gives theta = s_ij / (lambda_j - lambda_i) + O(theta^3)), and
 // rotations by angles of order theta commute up to O(theta^2): the whole sweep
@@ -30,8 +33,9 @@
 // neglected terms are then below 2^-60 relative), a few otherwise.
 //
 // Stopping rule: the sweep whose largest angle is <= 2^-30 is the last.  At most
-// rk sweeps are queued on the stream (2 after the FP64 Algorithm 2, whose angles
-// are about u kappa(B); 3 after an FP32-accurate one); those after convergence
+// rk sweeps are queued on the stream: 3 for single problems (their basis stops at
+// cosines of about 2^-20: two sweeps reach the rule, the third is a margin), 2 for
+// the batched call (its basis is converged to 2^-24); those after convergence
 // return at once.
 // A pair whose angle would exceed 2^-8 (eigenvalues that agree to within the
 // coupling: a cluster) is not rotated (f_ij = -g_ij / 2 only re-orthogonalises);
@@ -551,8 +555,7 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(double *__restrict__ p, 
 }
 
 template <class P>
-hipError_t refine_queue(P probs, int count, int max_n, bool f32, hipStream_t st) {
-    const int rk = f32 ? 3 : 2;
+hipError_t refine_queue(P probs, int count, int max_n, bool f32, int rk, hipStream_t st) {
     const int nt = (max_n + TB - 1) / TB;
     const unsigned nn_blocks = (unsigned)(((size_t)max_n * max_n + 255) / 256);
     const unsigned ablocks = (unsigned)(((size_t)max_n * max_n + FT * AE - 1) / (FT * AE));
@@ -598,12 +601,12 @@ hipError_t refine_launch(int working, int64_t n, const double *Mhi, const double
         return hipErrorInvalidValue;
     OneRef pr;
     pr.p = RefProb{Mhi, Mlo, ldm, X0, ldx0, S, V, W, ldv, ldw, info, (double *)work, (int)n};
-    return refine_queue(pr, 1, (int)n, working == GSVD_F32, st);
+    return refine_queue(pr, 1, (int)n, working == GSVD_F32, 3, st);
 }
 
 hipError_t refine_batched_launch(const BatchMat *tab, int batch, int max_n, hipStream_t st) {
     if (batch < 1 || max_n < 1 || max_n > GSVD_WIDE_MAX_N) return hipErrorInvalidValue;
-    return refine_queue(TabRef{tab}, batch, max_n, false, st);
+    return refine_queue(TabRef{tab}, batch, max_n, false, 2, st);
 }
 
 hipError_t assump_launch(int working, int64_t n, const double *Mhi, int64_t ldm, const void *W,

@@ -49,7 +49,9 @@
 //      row-graded triangular factor the columns of Z are far closer to
 //      orthogonal than those of X', so fewer sweeps are needed (the idea of the
 //      QR-preconditioned Jacobi SVD of Drmac and Veselic).  The rotations
-//      still accumulate in Q.
+//      still accumulate in Q.  The last tournament round is the first whose
+//      rotated pairs all had cosines below 2^-10 (quadratic convergence leaves
+//      cosines of order 2^-20 or less, far inside the next stage's reach).
 //   5'. Z Q = V' Sigma and X' = Q Sigma V'^T give V' = X'^-1 Q Sigma: V' comes
 //      from a back substitution with R' and the exact scalings D~'^-1, which
 //      keeps every column of V' accurate relative to its graded pattern
@@ -73,7 +75,13 @@ constexpr int UT = 1024;     // update-kernel workgroup (32 x 32 tile)
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int MAXWG = 64;    // Jacobi workgroups per step: ceil(512 / 16) / 2 = 16 at most
+constexpr int MAXWG = 64;
+// Preconditioner form: a tournament round whose rotated pairs all had
+// |x_p^T x_q| < TAU_BIG ||x_p|| ||x_q|| is the last.  The Jacobi method converges
+// quadratically, so the cosines it leaves are of order TAU_BIG^2 or smaller (below
+// 1e-7 at the sizes measured), well inside the convergence of the double-double
+// stage, which checks its own.
+constexpr double TAU_BIG = 0x1p-10;    // Jacobi workgroups per step: ceil(512 / 16) / 2 = 16 at most
 
 struct Ctl {
     int bad;      // info code of a failed check (1 or 3), 0 otherwise
@@ -82,7 +90,9 @@ struct Ctl {
     int notconv;  // max_sweeps reached without convergence
     int abort;    // the output kernel must not write
     int nswept;   // tournament rounds checked so far (those that ran)
-    int rot[MAXWG];  // per step workgroup: some rotation in the current tournament round
+    int vpend;    // the round just checked rotated: its products are to be applied to V
+    int rot[MAXWG];  // per step workgroup, this tournament round: 0 no rotation, 1 only
+                     // pairs with cosine < TAU_BIG rotated, 2 a larger one
 };
 
 struct WLayout {
@@ -169,6 +179,7 @@ weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, i
         ctl->notconv = 0;
         ctl->abort = 0;
         ctl->nswept = 0;
+        ctl->vpend = 0;
     }
 }
 
@@ -462,7 +473,7 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6;
-    bool any = false;
+    int any = 0;  // 1: a rotation, 2: one of a pair with cosine >= TAU_BIG
     // one plane rotation of columns x0 (p) and x1 (q), held in registers; also on Q
     auto rotate = [&](double (&x0)[RPL], double (&x1)[RPL], int p, int q) -> bool {
         double al = 0.0, be = 0.0, ga = 0.0;
@@ -489,6 +500,8 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
             Qs[lane + p * QLD] = __builtin_fma(c, u, -(sn * w));
             Qs[lane + q * QLD] = __builtin_fma(c, w, sn * u);
         }
+        if (ga * ga >= (TAU_BIG * TAU_BIG) * (al * be)) any = 2;
+        else if (any == 0) any = 1;
         return true;
     };
     double x0[RPL], x1[RPL];
@@ -508,7 +521,6 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
                 x1[i] = xq[64 * i];
             }
             if (rotate(x0, x1, p, q)) {
-                any = true;
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) {
                     xp[64 * i] = x0[i];
@@ -531,7 +543,6 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
 #pragma unroll
             for (int i = 0; i < RPL; ++i) x1[i] = xq[64 * i];
             if (rotate(x0, x1, p, q)) {
-                any = true;
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) xq[64 * i] = x1[i];
             }
@@ -551,21 +562,26 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
     }
     double *Qo = Qbuf + ((size_t)step * gridDim.x + blockIdx.x) * (JC * JC);
     for (int q = tid; q < JC * JC; q += JT) Qo[q] = Qs[(q / JC) + (q % JC) * QLD];
-    // one plain store per workgroup into its own word (no contended atomics)
-    if (__syncthreads_or(any) && tid == 0) ctl->rot[blockIdx.x] = 1;
+    // one plain store per workgroup into its own word (no contended atomics); the
+    // word holds the largest level of the round's earlier steps (earlier launches)
+    const bool big = __syncthreads_or(any == 2), some = __syncthreads_or(any != 0);
+    const int lvl = big ? 2 : (some ? 1 : 0);
+    if (tid == 0 && lvl > ctl->rot[blockIdx.x]) ctl->rot[blockIdx.x] = lvl;
 }
 
-// end of a tournament round (one wavefront): converged when no workgroup rotated;
-// the flags are cleared for the next round
-__global__ void __launch_bounds__(64) weig_sweep_kernel(Ctl *ctl, int nwg, int last) {
+// end of a tournament round (one wavefront): converged when no workgroup rotated
+// (early: or when no rotated pair had a cosine of TAU_BIG); the flags are cleared for
+// the next round
+__global__ void __launch_bounds__(64) weig_sweep_kernel(Ctl *ctl, int nwg, int last, int early) {
     const int t = threadIdx.x;
     if (ctl->bad || ctl->done) return;  // written by earlier launches only
     const int r = t < nwg ? ctl->rot[t] : 0;
-    const bool anyrot = __any(r != 0);
+    const bool anyrot = __any(r != 0), anybig = __any(r == 2);
     if (t < nwg) ctl->rot[t] = 0;
     if (t == 0) {
         ctl->nswept += 1;
-        if (!anyrot) ctl->done = 1;
+        ctl->vpend = anyrot ? 1 : 0;
+        if (!anyrot || (early && !anybig)) ctl->done = 1;
         else if (last) ctl->notconv = 1;
     }
 }
@@ -587,7 +603,7 @@ weig_vapply_kernel(int n, int nblk, int sweep, const Ctl *ctl, const double *__r
                    double *__restrict__ Vw) {
     constexpr int JC = JGeom<JB>::JC;
     extern __shared__ __attribute__((aligned(16))) double vsm[];  // VRW x n, column-major
-    if (wg_read(&ctl->bad) || wg_read(&ctl->done) || wg_read(&ctl->nswept) != sweep + 1) return;
+    if (wg_read(&ctl->bad) || wg_read(&ctl->nswept) != sweep + 1 || !wg_read(&ctl->vpend)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = blockIdx.x * VRW;
     for (int q = tid; q < VRW * n; q += 1024) {
@@ -871,7 +887,7 @@ hipError_t chol_blocked(int n, Ctl *ctl, double *Hh, double *Hl, hipStream_t st)
 
 template <int RPL, int JB>
 hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double *Qbuf,
-                        double tol2, int max_sweeps, hipStream_t st) {
+                        double tol2, int max_sweeps, bool early, hipStream_t st) {
     constexpr int JC = JGeom<JB>::JC, JT = JGeom<JB>::JT, QLD = JGeom<JB>::QLD;
     const size_t lds = ((size_t)JC * 64 * RPL + JC * QLD) * sizeof(double);
     auto k = weig_step_kernel<RPL, JB>;
@@ -890,7 +906,7 @@ hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double
             if ((err = hipGetLastError()) != hipSuccess) return err;
         }
         hipLaunchKernelGGL(weig_sweep_kernel, dim3(1), dim3(64), 0, st, ctl, nblk / 2,
-                           sw + 1 == max_sweeps ? 1 : 0);
+                           sw + 1 == max_sweeps ? 1 : 0, early ? 1 : 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         hipLaunchKernelGGL(kv, dim3((unsigned)((n + VRW - 1) / VRW)), dim3(1024), lds_v, st, n,
                            nblk, sw, ctl, Qbuf, Vw);
@@ -990,7 +1006,7 @@ hipError_t eig_wide_launch(int64_t n64, const double *Mhi, const double *Mlo, in
     const int rpl = (n + 63) / 64;
     const int nblk = jac_nblk(n);
 #define STEPS(R)                                                                              \
-    case R: err = launch_steps<R, JBW>(n, nblk, ctl, X, Vw, Qbuf, tol2, max_sweeps, st); break;
+    case R: err = launch_steps<R, JBW>(n, nblk, ctl, X, Vw, Qbuf, tol2, max_sweeps, pre, st); break;
     switch (rpl) {
         STEPS(2) STEPS(3) STEPS(4) STEPS(5) STEPS(6) STEPS(7) STEPS(8)
         default: return hipErrorInvalidValue;

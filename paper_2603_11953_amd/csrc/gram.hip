@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(GRAM_MAX_THREADS)
 gram_partial_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int nb, int nblk,
                     int ng, int nblkg, int ks, int kc, int64_t rows_per_split, int64_t nsplit,
                     double *__restrict__ part) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     const int64_t id = blockIdx.x;
     const int64_t split = id / (8 * ng) * 8 + id % 8;
     const int grp = (int)(id / 8 % ng);
@@ -212,7 +212,7 @@ template <typename T, bool DD>
 __global__ void __launch_bounds__(GRAM_MAX_THREADS)
 gram_partial_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order,
                             int first, int nb, int nblk, int ks, int kc) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     const BatchMat &d = tab[order[first + blockIdx.z]];
     if ((int)blockIdx.y >= d.nsplit) return;
     gram_partial_body<T, DD>(reinterpret_cast<const T *>(d.A), d.lda, d.m, d.n, nb, nblk, 0, nblk,

@@ -186,7 +186,7 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
     constexpr int CPP = 4 * sp_prod(NB);            // columns per producer pass
     constexpr int NPASS = (N16 + CPP - 1) / CPP;  // producer passes
     constexpr bool PREF = NPASS * (int)sizeof(T) <= 32;  // next chunk held in registers
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     // [0], [1]: the chunk whose exponents grew, per buffer; [2]: a NaN or Inf was seen
     int *flagc = reinterpret_cast<int *>(smem + NBUF * BB);
     auto planes_of = [&](int b) { return reinterpret_cast<signed char *>(smem + b * BB); };

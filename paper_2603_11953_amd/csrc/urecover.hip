@@ -154,7 +154,7 @@ template <typename T, int NT>
 __global__ void __launch_bounds__(US_THREADS)
 urecover_strip_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__ W, int64_t ldw,
                       T *__restrict__ U, int64_t ldu, int64_t m, int n) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int waves = US_THREADS / 64;
     urecover_strip_body<T, NT>(A, lda, W, ldw, U, ldu, m, n,
                                (int64_t)blockIdx.x * waves + (threadIdx.x >> 6),
@@ -167,7 +167,7 @@ template <typename T, int NT>
 __global__ void __launch_bounds__(US_THREADS)
 urecover_strip_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order,
                               int first) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const BatchMat &d = tab[order[first + blockIdx.z]];
     const int waves = US_THREADS / 64;
     if ((int64_t)blockIdx.x * waves * 16 >= d.m) return;
