@@ -76,7 +76,7 @@ enum {
                                 ordered by decreasing m_jj and the one-sided Jacobi run on
                                 the transposed Cholesky factor (X by back substitution);
                                 its threshold is jacobi_tol (default 2^-24) and its sweep
-                                limit max_sweeps (default 16). */
+                                limit max_sweeps (default 12). */
     GSVD_EIG_CHOL_JACOBI1 = 2 /* Algorithm 2: Cholesky of M_h at u_h, R cast to u,
                                  one-sided Jacobi SVD of R (Thm. 2, Lemma 1); default
                                  threshold sqrt(n) * u.  FP32 working with n > 128: the

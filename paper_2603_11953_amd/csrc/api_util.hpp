@@ -236,8 +236,8 @@ inline double jacobi_tol_of(const gsvd_opts *o, int64_t n) {
 
 inline int sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 30; }
 // sweep limit of the preconditioner before the double-double stage (its sweeps
-// are queued whether needed or not; it converges in 5 to 8 at the sizes measured)
-inline int pre_sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 16; }
+// are queued whether needed or not; it stops after 4 to 6 at the sizes measured)
+inline int pre_sweeps_of(const gsvd_opts *o) { return o->max_sweeps > 0 ? o->max_sweeps : 12; }
 
 // Bound on ||D^-1 dM D^-1|| for the Gram's error dM, for the assumption check:
 // n^2 u_h for the plain Gram (the n^2 eps_M of eq. (thm:assump)); n eps for the

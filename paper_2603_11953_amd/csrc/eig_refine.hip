@@ -486,24 +486,26 @@ struct TabAssump {
 //   c_w u kappa <= 1/2, c_w = n for Algorithm 2 (its O(u) kappa(B) term), else 0;
 // a failed condition sets GSVD_INFO_WARN_ASSUMPTION (Theorem 1's bounds are then
 // not guaranteed).
-template <typename TW, class P>
-__global__ void __launch_bounds__(256)
+// AT lanes per problem (AT / 64 wavefronts, each taking every (AT / 64)-th column).
+template <typename TW, class P, int AT>
+__global__ void __launch_bounds__(AT)
 assump_kernel(P probs, double e_gram, double u_h, double u_w, double c_w) {
+    constexpr int NW = AT / 64;
     const AssumpProb p = probs.get(blockIdx.x);
     const int n = p.n;
     const TW *W = reinterpret_cast<const TW *>(p.W);
     __shared__ double dg[GSVD_WIDE_MAX_N], isq[GSVD_WIDE_MAX_N];
-    __shared__ double red[4], redg[4];
-    for (int r = threadIdx.x; r < n; r += 256) {
+    __shared__ double red[NW], redg[NW];
+    for (int r = threadIdx.x; r < n; r += AT) {
         const double d = p.Mhi[r + (int64_t)r * p.ldm];
         dg[r] = d;
         isq[r] = 1.0 / __builtin_sqrt(d);
     }
     __syncthreads();
-    // wavefront w takes columns w, w + 4, ...; its lanes the rows (coalesced)
+    // wavefront w takes columns w, w + NW, ...; its lanes the rows (coalesced)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double s = 0.0, gmax = 0.0;
-    for (int c = w; c < n; c += 4) {
+    for (int c = w; c < n; c += NW) {
         double rs = 0.0;
         for (int r = lane; r < n; r += 64) {
             const double x = (double)W[r + (int64_t)c * p.ldw];
@@ -525,8 +527,12 @@ assump_kernel(P probs, double e_gram, double u_h, double u_w, double c_w) {
     const int info = *p.info;
     if ((info & 0xff) != 0) return;
     const double dn = (double)n;
-    const double g = fmax(fmax(redg[0], redg[1]), fmax(redg[2], redg[3]));
-    const double kap2 = g * (((red[0] + red[1]) + red[2]) + red[3]);
+    double g = 0.0, sum = 0.0;
+    for (int k = 0; k < NW; ++k) {  // a fixed order
+        g = fmax(g, redg[k]);
+        sum += red[k];
+    }
+    const double kap2 = g * sum;
     const bool hi_ok = 2.0 * (e_gram + dn * u_h) * kap2 <= 0.5;
     const bool w_ok = c_w * u_w * __builtin_sqrt(kap2) <= 0.5;
     if (!(hi_ok && w_ok)) *p.info = info | GSVD_INFO_WARN_ASSUMPTION;
@@ -618,11 +624,11 @@ hipError_t assump_launch(int working, int64_t n, const double *Mhi, int64_t ldm,
     const double u_w = working == GSVD_F64 ? 0x1p-53 : 0x1p-24;
     const double c_w = alg2 ? (double)n : 0.0;
     if (working == GSVD_F64)
-        hipLaunchKernelGGL((assump_kernel<double, OneAssump>), dim3(1), dim3(256), 0, st, a,
+        hipLaunchKernelGGL((assump_kernel<double, OneAssump, 1024>), dim3(1), dim3(1024), 0, st, a,
                            e_gram, u_h, u_w, c_w);
     else
-        hipLaunchKernelGGL((assump_kernel<float, OneAssump>), dim3(1), dim3(256), 0, st, a, e_gram,
-                           u_h, u_w, c_w);
+        hipLaunchKernelGGL((assump_kernel<float, OneAssump, 1024>), dim3(1), dim3(1024), 0, st, a,
+                           e_gram, u_h, u_w, c_w);
     return hipGetLastError();
 }
 
@@ -634,11 +640,11 @@ hipError_t assump_batched_launch(int working, const BatchMat *tab, int batch, do
     // the Algorithm 2 condition with the largest n of the batch (conservative)
     const double c_w = alg2 ? (double)max_n : 0.0;
     if (working == GSVD_F64)
-        hipLaunchKernelGGL((assump_kernel<double, TabAssump>), dim3((unsigned)batch), dim3(256), 0,
-                           st, TabAssump{tab}, e_gram, u_h, u_w, c_w);
+        hipLaunchKernelGGL((assump_kernel<double, TabAssump, 256>), dim3((unsigned)batch), dim3(256),
+                           0, st, TabAssump{tab}, e_gram, u_h, u_w, c_w);
     else
-        hipLaunchKernelGGL((assump_kernel<float, TabAssump>), dim3((unsigned)batch), dim3(256), 0,
-                           st, TabAssump{tab}, e_gram, u_h, u_w, c_w);
+        hipLaunchKernelGGL((assump_kernel<float, TabAssump, 256>), dim3((unsigned)batch), dim3(256),
+                           0, st, TabAssump{tab}, e_gram, u_h, u_w, c_w);
     return hipGetLastError();
 }
 
