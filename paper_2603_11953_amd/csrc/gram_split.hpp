@@ -30,8 +30,8 @@
 // its A operand from columns 16 I .. 16 I + 15 and its B operand from columns
 // 16 J .. 16 J + 15: lane l reads the 16 bytes of rows 16 (l / 16) .. + 15 of
 // column 16 I + l % 16 (resp. 16 J + l % 16); the integer result gives lane l,
-// register q the entry (4 (l / 16) + q, l % 16).  Each wavefront owns one tile
-// I <= J of the upper triangle.
+// register q the entry (4 (l / 16) + q, l % 16).  Each wavefront owns up to five
+// tiles I <= J of the upper triangle and also cuts its share of every chunk.
 //
 // The slab / partial / fixed-order reduction structure is the one of the plain
 // form, so the result is reproducible bit for bit.
@@ -130,30 +130,53 @@ __device__ __forceinline__ void transpose4(unsigned w0, unsigned w1, unsigned w2
     o3 = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
 }
 
-// Tiles of the upper triangle per workgroup: one per wavefront, at most 12
-// wavefronts (three per SIMD, 168 registers each).  Larger triangles are dealt
-// to several workgroups per slab, each slicing the whole chunk.
-__host__ __device__ constexpr int sp_groups(int nb) { return (nb * (nb + 1) / 2 + 11) / 12; }
-__host__ __device__ constexpr int sp_waves(int nb) {
-    return (nb * (nb + 1) / 2 + sp_groups(nb) - 1) / sp_groups(nb);
+// Work split of one slab.  Every wavefront of a workgroup both cuts its share of
+// each chunk into digits and runs the products of its own tiles, so the digits
+// of a chunk are formed once per workgroup (VALU work that outweighs the
+// products).  A wavefront keeps 4 SS accumulator registers per tile, so the
+// tiles per wavefront (TPW), the wavefronts (16, 12 or 8: 4, 3 or 2 per SIMD)
+// and, when even 8 do not hold the whole triangle, the workgroups per slab
+// (each cutting the whole chunk) follow from the register budget of a wavefront
+// (512 per lane and SIMD over the wavefronts it hosts).
+__host__ __device__ constexpr int sp_npair(int nb) { return nb * (nb + 1) / 2; }
+// registers of a wavefront (measured model): per tile the SS accumulators and
+// about 11 of bookkeeping, the B operands of one tile, and the cutting state
+// (more for FP64 entries)
+__host__ __device__ constexpr int sp_regs(int tpw, int ss, int wb) {
+    return (4 * ss + 11) * tpw + 4 * ss + (wb == 8 ? 80 : 64);
 }
-
-// Producer wavefronts per workgroup: they load A, keep the column exponents and
-// write the digit planes; the other wavefronts (one per tile) run the products.
-// The producers fill the workgroup up to 16 wavefronts, at most one per four
-// columns (each producer wavefront takes four columns per pass).
-__host__ __device__ constexpr int sp_prod(int nb) {
-    return (16 - sp_waves(nb)) < 4 * nb ? (16 - sp_waves(nb)) : 4 * nb;
+// a few registers over the share of the register file are left to spill
+__host__ __device__ constexpr int sp_budget(int nw) { return 512 / ((nw + 3) / 4) + 8; }
+__host__ __device__ constexpr int sp_tpw_of(int nb, int g, int nw) {
+    return ((sp_npair(nb) + g - 1) / g + nw - 1) / nw;
 }
+__host__ __device__ constexpr bool sp_fits(int nb, int ss, int wb, int g, int nw) {
+    return sp_regs(sp_tpw_of(nb, g, nw), ss, wb) <= sp_budget(nw);
+}
+// the first (groups, wavefronts) that fits: groups ascending, then 16, 12, 8 wavefronts
+__host__ __device__ constexpr int sp_pick(int nb, int ss, int wb) {
+    for (int g = 1; g <= sp_npair(nb); ++g)
+        for (int nw = 16; nw >= 8; nw -= 4)
+            if (sp_fits(nb, ss, wb, g, nw)) return 64 * g + nw;
+    return 64 * sp_npair(nb) + 8;
+}
+template <typename T>
+__host__ __device__ constexpr int sp_groups(int nb, int ss) {
+    return sp_pick(nb, ss, (int)sizeof(T)) / 64;
+}
+template <typename T>
+__host__ __device__ constexpr int sp_nwave(int nb, int ss) {
+    return sp_pick(nb, ss, (int)sizeof(T)) % 64;
+}
+template <typename T>
+__host__ __device__ constexpr int sp_threads(int nb, int ss) { return 64 * sp_nwave<T>(nb, ss); }
 constexpr int SP_LDS_MAX = 160 * 1024 - 1024;
-
-__host__ __device__ constexpr int sp_threads(int nb) { return 64 * (sp_waves(nb) + sp_prod(nb)); }
 
 // bytes of one plane buffer (all slices of one chunk) plus its exponents
 __host__ __device__ constexpr int sp_buf_bytes(int nb, int ss) {
     return ss * 16 * nb * SP_CS + 16 * nb * 4;
 }
-// two buffers (producers one chunk ahead of the consumers) when they fit LDS
+// two buffers (the digits of chunk i + 1 cut while chunk i is multiplied) when they fit
 __host__ __device__ constexpr int sp_bufs(int nb, int ss) {
     return 2 * sp_buf_bytes(nb, ss) + 64 <= SP_LDS_MAX ? 2 : 1;
 }
@@ -163,28 +186,32 @@ __host__ __device__ constexpr int sp_lds(int nb, int ss) {
 
 // The partial Gram of slab `split` of one matrix, tiles of workgroup `grp`.
 //
-// Producers (the last sp_prod(NB) wavefronts) take chunk i: lane l of producer
-// wavefront w holds rows 4 (l % 16) .. + 3 of column 4 P p + 4 w + l / 16 for
-// every pass p (P producer wavefronts), so the 16 lanes of a DPP row hold one column and agree on its
-// exponent by a DPP max without any barrier.  A column whose exponent grows
-// records the chunk in the buffer's flag (a monotone LDS maximum).  Consumers
-// (one wavefront per tile) take chunk i - 1 from the other buffer: they flush
-// their integer sums when the flag names that chunk (or every 128 chunks),
-// reload their tile's exponents, and run the products.  One barrier per chunk.
-// When two buffers do not fit LDS, producers and consumers alternate on one.
+// Cutting: lane l of wavefront w holds rows 4 (l % 16) .. + 3 of column
+// 4 NW p + 4 w + l / 16 for every pass p, so the 16 lanes of a DPP row hold one
+// column and agree on its exponent by a DPP max without any barrier.  A column
+// whose exponent grows records the chunk in the buffer's flag (a monotone LDS
+// maximum).  Products: tile t of wavefront w is number TPG grp + w + NW t of the
+// upper triangle (TPG tiles per workgroup).  Iteration i cuts chunk i into one
+// buffer and multiplies chunk i - 1 from the other; before multiplying, every
+// tile flushes its integer sums when the flag names that chunk (or every 128
+// chunks) and reloads its exponents.  One barrier per chunk.  When two buffers
+// do not fit LDS, cutting and multiplying alternate on one (two barriers).
 template <typename T, int NB, int SS>
 __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t lda, int64_t m,
                                                 int n, int64_t rows_per_split, int64_t split,
                                                 int grp, double *__restrict__ part) {
     constexpr bool DD = sizeof(T) == 8;
-    constexpr int NW = sp_waves(NB);   // consumer wavefronts
+    constexpr int G = sp_groups<T>(NB, SS);
+    constexpr int NW = sp_nwave<T>(NB, SS);
+    constexpr int NPAIR = sp_npair(NB);
+    constexpr int TPG = (NPAIR + G - 1) / G;   // tiles per workgroup
+    constexpr int TPW = (TPG + NW - 1) / NW;   // tiles per wavefront, at most
     constexpr int N16 = 16 * NB;
-    constexpr int NPAIR = NB * (NB + 1) / 2;
     constexpr int SL = N16 * SP_CS;    // bytes per digit plane
     constexpr int NBUF = sp_bufs(NB, SS);
     constexpr int BB = sp_buf_bytes(NB, SS);
-    constexpr int CPP = 4 * sp_prod(NB);            // columns per producer pass
-    constexpr int NPASS = (N16 + CPP - 1) / CPP;  // producer passes
+    constexpr int CPP = 4 * NW;                   // columns per cutting pass
+    constexpr int NPASS = (N16 + CPP - 1) / CPP;  // cutting passes
     constexpr bool PREF = NPASS * (int)sizeof(T) <= 32;  // next chunk held in registers
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     // [0], [1]: the chunk whose exponents grew, per buffer; [2]: a NaN or Inf was seen
@@ -195,7 +222,6 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wavefront
-    const bool producer = wave >= NW;
     const int64_t r0 = split * rows_per_split;
     const int64_t r1 = (r0 + rows_per_split < m) ? r0 + rows_per_split : m;
     const int nchunk = (int)((r1 - r0 + SP_KT - 1) / SP_KT);
@@ -203,8 +229,8 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
     if (tid < 3) flagc[tid] = 0;
     __syncthreads();
 
-    // ---------------- producer state
-    const int pcol = 4 * (wave - NW) + (lane >> 4);  // + CPP p
+    // ---------------- cutting state
+    const int pcol = 4 * wave + (lane >> 4);  // + CPP p
     const int prow = 4 * (lane & 15);
     T cur[NPASS][4], nxt[PREF ? NPASS : 1][4];
     int er[NPASS];
@@ -285,27 +311,38 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
         }
     };
 
-    // ---------------- consumer state: this wavefront's tile (I, J), I <= J
-    const int pidx = grp * NW + wave;
-    const bool has_tile = !producer && pidx < NPAIR;
-    int bi = 0, bj = 0;
-    if (has_tile) sp_decode_pair(pidx, NB, bi, bj);
-    const int ca = 16 * bi + (lane & 15), cb = 16 * bj + (lane & 15);
+    // ---------------- product state: this wavefront's tiles (I, J), I <= J
+    const int tlo = grp * TPG;
+    const int thi = (tlo + TPG < NPAIR) ? tlo + TPG : NPAIR;
+    bool has[TPW];
+    int ca[TPW], cb[TPW], rowa[TPW];
+    int ei[TPW][4], ej[TPW];
+    v4i diag[TPW][SS];
+    double *dst[TPW];
     const int koff = 16 * (lane >> 4);
-    int ei[4] = {SP_NOEXP, SP_NOEXP, SP_NOEXP, SP_NOEXP}, ej = SP_NOEXP;
-
-    v4i diag[SS];
 #pragma unroll
-    for (int s = 0; s < SS; ++s) diag[s] = v4i{0, 0, 0, 0};
-
-    // partial slot of this slab's tile: [split][tile][lane][q][hi, lo]
-    double *dst = part + (((size_t)split * NPAIR + (has_tile ? pidx : 0)) * 64 + lane) * 8;
-    // flush: add the integer sums (with the exponents in force) to the slot
-    auto flush = [&](bool first) {
+    for (int t = 0; t < TPW; ++t) {
+        const int pidx = tlo + wave + NW * t;
+        has[t] = pidx < thi;  // uniform per wavefront
+        int bi = 0, bj = 0;
+        if (has[t]) sp_decode_pair(pidx, NB, bi, bj);
+        ca[t] = 16 * bi + (lane & 15);
+        cb[t] = 16 * bj + (lane & 15);
+        rowa[t] = 16 * bi + 4 * (lane >> 4);
+        ej[t] = SP_NOEXP;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ei[t][q] = SP_NOEXP;
+#pragma unroll
+        for (int s = 0; s < SS; ++s) diag[t][s] = v4i{0, 0, 0, 0};
+        // partial slot of this slab's tile: [split][tile][lane][q][hi, lo]
+        dst[t] = part + (((size_t)split * NPAIR + (has[t] ? pidx : 0)) * 64 + lane) * 8;
+    }
+    // flush tile t: add the integer sums (with the exponents in force) to its slot
+    auto flush = [&](int t, bool first) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             dd_t tot{0.0, 0.0};
-            if (ei[q] > SP_NOEXP && ej > SP_NOEXP) {
+            if (ei[t][q] > SP_NOEXP && ej[t] > SP_NOEXP) {
                 if (DD) {
 #pragma unroll
                     for (int g0 = 0; g0 < SS; g0 += 3) {
@@ -314,95 +351,88 @@ __device__ __forceinline__ void gram_split_body(const T *__restrict__ A, int64_t
                         double v = 0.0;
 #pragma unroll
                         for (int u = 2; u >= 0; --u)
-                            if (g0 + u < SS) v = v * 0x1p-8 + (double)diag[g0 + u][q];
+                            if (g0 + u < SS) v = v * 0x1p-8 + (double)diag[t][g0 + u][q];
                         tot = dd_add(tot, dd_t{ldexp(v, -8 * (g0 + 2)), 0.0});
                     }
-                    tot.hi = ldexp(tot.hi, ei[q] + ej);
-                    tot.lo = ldexp(tot.lo, ei[q] + ej);
+                    tot.hi = ldexp(tot.hi, ei[t][q] + ej[t]);
+                    tot.lo = ldexp(tot.lo, ei[t][q] + ej[t]);
                 } else {
                     double v = 0.0;
 #pragma unroll
-                    for (int s0 = SS - 1; s0 >= 0; --s0) v = v * 0x1p-8 + (double)diag[s0][q];
-                    tot.hi = ldexp(v, ei[q] + ej - 16);
+                    for (int s0 = SS - 1; s0 >= 0; --s0) v = v * 0x1p-8 + (double)diag[t][s0][q];
+                    tot.hi = ldexp(v, ei[t][q] + ej[t] - 16);
                 }
             }
-            if (!first) tot = dd_add(tot, dd_t{dst[2 * q], dst[2 * q + 1]});
-            dst[2 * q] = tot.hi;
-            dst[2 * q + 1] = tot.lo;
+            if (!first) tot = dd_add(tot, dd_t{dst[t][2 * q], dst[t][2 * q + 1]});
+            dst[t][2 * q] = tot.hi;
+            dst[t][2 * q + 1] = tot.lo;
         }
 #pragma unroll
-        for (int s = 0; s < SS; ++s) diag[s] = v4i{0, 0, 0, 0};
+        for (int s = 0; s < SS; ++s) diag[t][s] = v4i{0, 0, 0, 0};
     };
     bool first_flush = true;
     int since_flush = 0;
     auto consume = [&](int ci, int b) {
         const bool newexp = flagc[b] == ci + 1;
-        if ((newexp || since_flush == SP_FLUSH_EVERY) && since_flush > 0) {
-            flush(first_flush);
+        const bool doflush = (newexp || since_flush == SP_FLUSH_EVERY) && since_flush > 0;
+        const signed char *planes = planes_of(b);
+        const int *expo = expo_of(b);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            if (!has[t]) continue;
+            if (doflush) flush(t, first_flush);
+            if (newexp) {
+                ej[t] = expo[cb[t]];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ei[t][q] = expo[rowa[t] + q];
+            }
+            // the SS B-operand planes in registers; A-operand plane r meets t' <= SS - 1 - r
+            v4i bop[SS];
+#pragma unroll
+            for (int u = 0; u < SS; ++u)
+                bop[u] = *reinterpret_cast<const v4i *>(planes + u * SL + cb[t] * SP_CS + koff);
+#pragma unroll
+            for (int r = 0; r < SS; ++r) {
+                const v4i aop = *reinterpret_cast<const v4i *>(planes + r * SL + ca[t] * SP_CS + koff);
+#pragma unroll
+                for (int u = 0; u < SS - r; ++u)
+                    diag[t][r + u] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, bop[u], diag[t][r + u], 0, 0, 0);
+            }
+        }
+        if (doflush) {
             first_flush = false;
             since_flush = 0;
-        }
-        const signed char *planes = planes_of(b);
-        if (newexp) {
-            const int *expo = expo_of(b);
-            ej = expo[cb];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) ei[q] = expo[16 * bi + 4 * (lane >> 4) + q];
-        }
-        // the SS B-operand planes stay in registers; A-operand plane r meets t <= SS - 1 - r
-        v4i bop[SS];
-#pragma unroll
-        for (int t = 0; t < SS; ++t)
-            bop[t] = *reinterpret_cast<const v4i *>(planes + t * SL + cb * SP_CS + koff);
-#pragma unroll
-        for (int r = 0; r < SS; ++r) {
-            const v4i aop = *reinterpret_cast<const v4i *>(planes + r * SL + ca * SP_CS + koff);
-#pragma unroll
-            for (int t = 0; t < SS - r; ++t)
-                diag[r + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, bop[t], diag[r + t], 0, 0, 0);
         }
         ++since_flush;
     };
 
-    // The two roles run separate loops (so their register state need not
-    // coexist), with the same number of barriers per chunk: NBUF == 2, one
-    // barrier per iteration over nchunk + 1 iterations; NBUF == 1, two per chunk.
-    if (producer) {
-        if constexpr (NBUF == 2) {
-            for (int it = 0; it <= nchunk; ++it) {
-                if (it < nchunk) produce(it, it & 1);
-                __syncthreads();
-            }
-        } else {
-            for (int it = 0; it < nchunk; ++it) {
-                produce(it, 0);
-                __syncthreads();
-                __syncthreads();
-            }
+    if constexpr (NBUF == 2) {
+        for (int it = 0; it <= nchunk; ++it) {
+            if (it < nchunk) produce(it, it & 1);
+            if (it >= 1) consume(it - 1, (it - 1) & 1);
+            __syncthreads();
         }
     } else {
-        if constexpr (NBUF == 2) {
-            for (int it = 0; it <= nchunk; ++it) {
-                if (has_tile && it >= 1) consume(it - 1, (it - 1) & 1);
-                __syncthreads();
-            }
-        } else {
-            for (int it = 0; it < nchunk; ++it) {
-                __syncthreads();
-                if (has_tile) consume(it, 0);
-                __syncthreads();
-            }
+        for (int it = 0; it < nchunk; ++it) {
+            produce(it, 0);
+            __syncthreads();
+            consume(it, 0);
+            __syncthreads();
         }
     }
-    if (has_tile) flush(first_flush);
-    if (has_tile && flagc[2] != 0) {  // set before the last barrier of the producers' loop
 #pragma unroll
-        for (int k = 0; k < 8; ++k) dst[k] = __builtin_nan("");
+    for (int t = 0; t < TPW; ++t) {
+        if (!has[t]) continue;
+        flush(t, first_flush);
+        if (flagc[2] != 0) {  // set before the last barrier of the loop
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dst[t][k] = __builtin_nan("");
+        }
     }
 }
 
 template <typename T, int NB, int SS>
-__global__ void __launch_bounds__(sp_threads(NB))
+__global__ void __launch_bounds__(sp_threads<T>(NB, SS))
 gram_split_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int64_t rows_per_split,
                   double *__restrict__ part) {
     gram_split_body<T, NB, SS>(A, lda, m, n, rows_per_split, blockIdx.y, blockIdx.x, part);
@@ -410,7 +440,7 @@ gram_split_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int64_
 
 // Batched: blockIdx.z picks the problem order[first + z], blockIdx.y its slab.
 template <typename T, int NB, int SS>
-__global__ void __launch_bounds__(sp_threads(NB))
+__global__ void __launch_bounds__(sp_threads<T>(NB, SS))
 gram_split_batched_kernel(const BatchMat *__restrict__ tab, const int *__restrict__ order,
                           int first) {
     const BatchMat &d = tab[order[first + blockIdx.z]];
@@ -429,7 +459,7 @@ static hipError_t split_partial_inst(int64_t m, int64_t n, const T *A, int64_t l
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)p.lds_bytes);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k, dim3(sp_groups(NB), (unsigned)p.nsplit), dim3(sp_threads(NB)),
+    hipLaunchKernelGGL(k, dim3(sp_groups<T>(NB, SS), (unsigned)p.nsplit), dim3(sp_threads<T>(NB, SS)),
                        p.lds_bytes, st, A, lda, m, (int)n, p.rows_per_split, (double *)part);
     return hipGetLastError();
 }
@@ -442,8 +472,8 @@ static hipError_t split_batched_inst(const BatchMat *tab, const int *order, int 
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)p.lds_bytes);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k, dim3(sp_groups(NB), (unsigned)max_nsplit, (unsigned)count),
-                       dim3(sp_threads(NB)), p.lds_bytes, st, tab, order, first);
+    hipLaunchKernelGGL(k, dim3(sp_groups<T>(NB, SS), (unsigned)max_nsplit, (unsigned)count),
+                       dim3(sp_threads<T>(NB, SS)), p.lds_bytes, st, tab, order, first);
     return hipGetLastError();
 }
 
