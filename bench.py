@@ -77,6 +77,9 @@ def parse():
                     help="skip the FP32 leg (m = 4e6, n = 128, sigma error per slice count)")
     ap.add_argument("--f32-m", type=int, default=4_000_000)
     ap.add_argument("--f32-steps", type=int, default=5)
+    ap.add_argument("--only", choices=("tall", "fp32", "batched"), default="",
+                    help="one secondary leg alone, for profiling: prints that leg's record "
+                         "(not the benchmark line)")
     ap.add_argument("--only-headline", action="store_true",
                     help="the headline workload only (no other legs, checks or CPU baseline): "
                          "the command the committed kernel profiles were taken with")
@@ -529,6 +532,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.only:  # one secondary leg alone (profiling runs)
+        leg = {"tall": tall_leg, "fp32": fp32_leg, "batched": batched_leg}[args.only]
+        r = leg(args, torch, gs, g, log)
+        print(json.dumps({args.only: {k: v for k, v in r.items() if not k.startswith("_")}},
+                         default=str))
+        return
+
     # ---- timed legs (no oracle work runs while any of them is timed)
     H = headline_leg(args, torch, gs, g, log)
     legs = {}
@@ -601,7 +611,8 @@ def main():
             "workload": f"FP64 A=BD m={m} n={n} kappa(B)=1e3 kappa(D)=1e12 (log-spaced), the "
                         "largest single-GPU configuration; the library's chosen form: "
                         f"{auto['form']} Gram (GSVD_GRAM_AUTO at the default accuracy target), "
-                        "double-double two-sided Jacobi stage on Algorithm 2's basis, FP64 MFMA U",
+                        "double-double two-sided Jacobi stage on an FP64 preconditioner's basis, "
+                        "FP64 MFMA U",
             "m": m, "n": n, "gram": auto["form"], "eig": "jacobi2-dd (default)",
         },
         "gram_hbm_gbps": round(gram_bytes / (auto["ms_gram"] * 1e-3) / 1e9, 2),
