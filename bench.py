@@ -168,7 +168,7 @@ def timed_on(torch, stream, fn, k, w_):
 
 
 def measure_thin(torch, gs, dA, gram_mode, steps, warmup, stream, log_fn, n_slices=0,
-                 eig=0):
+                 eig=0, u_fp32_mfma=False):
     """Time gsvd_thin on the column-major device matrix dA (working precision = its dtype,
     the default eigensolver unless ``eig`` names one), and its three stages through
     gsvd_gram, gsvd_eig and gsvd_u_recover (same kernels, same shapes)."""
@@ -179,7 +179,7 @@ def measure_thin(torch, gs, dA, gram_mode, steps, warmup, stream, log_fn, n_slic
     dt = dA.dtype
     w = gs.GSVD_F64 if dt == torch.float64 else gs.GSVD_F32
     sp = ctypes.c_void_p(int(stream.cuda_stream))
-    o = gs.opts(w, gram_mode, eig, n_slices=n_slices)
+    o = gs.opts(w, gram_mode, eig, n_slices=n_slices, u_fp32_mfma=u_fp32_mfma)
     ob = ctypes.byref(o)
     cfg = gs.gram_config(m, n, w, gram_mode, n_slices=n_slices)
     S = torch.empty(n, dtype=dt, device=dev)
@@ -232,8 +232,9 @@ def measure_thin(torch, gs, dA, gram_mode, steps, warmup, stream, log_fn, n_slic
 def fp32_leg(args, torch, gs, g, log_fn):
     """The FP32 workload: A = B D stored in FP32, m = 4e6, n = 128, kappa(B) = 1e2,
     kappa(D) = 1e6 (log-spaced).  FP64-accumulated plain Gram against the split Gram at every
-    slice count 1..8, each with the two-sided Jacobi on M_h (the FP32 default) and U on the FP32
-    matrix cores.  ||U^T U - I|| is taken exactly after each run (outside its timed region);
+    slice count 1..8, each with the default eigensolver and the default U (BF16 operand split);
+    the plain form also with U on the FP32 matrix cores.  ||U^T U - I|| is taken exactly after
+    each run (outside its timed region);
     the oracle (dd SVD of the stored FP32 matrix) runs after every timed leg."""
     from tests.exact_gram import orth_exact
     spec = g.spec_tall_f32(m=args.f32_m)
@@ -245,21 +246,22 @@ def fp32_leg(args, torch, gs, g, log_fn):
     m, n = spec.m, spec.n
     log_fn(f"fp32: generated A {m}x{n} on the GPU in {time.time() - t0:.1f}s")
     stream = torch.cuda.current_stream()
-    runs = [("plain", gs.GSVD_GRAM_PLAIN, 0)] + [(f"split-S{S}", gs.GSVD_GRAM_SPLIT, S)
-                                                for S in range(1, 9)]
+    runs = [("plain", gs.GSVD_GRAM_PLAIN, 0, False), ("plain-u-fp32mfma", gs.GSVD_GRAM_PLAIN, 0, True)]
+    runs += [(f"split-S{S}", gs.GSVD_GRAM_SPLIT, S, False) for S in range(1, 9)]
     flops = m * n * (n + 1) + 2 * m * n * n
     out = {"m": m, "n": n,
            "default_form": gs.gram_config(m, n, gs.GSVD_F32)["n_slices"] or "plain",
            "default_split_slices": gs.gram_config(m, n, gs.GSVD_F32,
                                                   gs.GSVD_GRAM_SPLIT)["n_slices"]}
     sig = {}
-    for name, gram, S in runs:
-        r = measure_thin(torch, gs, dA, gram, args.f32_steps, 1, stream, log_fn, S)
+    for name, gram, S, ufp32 in runs:
+        r = measure_thin(torch, gs, dA, gram, args.f32_steps, 1, stream, log_fn, S,
+                         u_fp32_mfma=ufp32)
         orth = orth_exact(r["U"].double())
         sig[name] = r["S"].cpu().numpy().astype(np.float64)
         out[name] = {"ms_per_step": round(r["ms_step"], 4), "ms_gram": round(r["ms_gram"], 4),
                      "value_gflops": round(flops / (r["ms_step"] * 1e-3) / 1e9, 1),
-                     "info": int(r["info"].item()), "u_orth": orth}
+                     "ms_u": round(r["ms_u"], 4), "info": int(r["info"].item()), "u_orth": orth}
         del r
     out["_A_host"] = np.asfortranarray(dA.t().contiguous().cpu().numpy().T)
     out["_sig"] = sig
@@ -278,7 +280,8 @@ def fp32_check(out, log_fn):
     tol = 50 * n * u * oracle.kappa_b
     out.update({"workload": f"FP32 A=BD m={out['m']} n={n} kappa(B)=1e2 kappa(D)=1e6 "
                             "(log-spaced); FP64-accumulated plain Gram vs split int8-slice Gram "
-                            "per slice count, two-sided Jacobi on M_h in FP64, FP32 MFMA U",
+                            "per slice count, the default eigensolver, U on the BF16 matrix cores "
+                            "(exact 3-piece operand split; FP32 matrix cores beside it)",
                 "kappa_b_oracle": oracle.kappa_b, "sigma_tol_50nu_kappaB": tol,
                 "orth_tol_50nu": 50 * n * u})
     for name, Sn in sig.items():

@@ -85,6 +85,12 @@ enum {
 
 /* flags */
 #define GSVD_WANT_U 1u /* form U (otherwise only Sigma and V; dU may be NULL) */
+#define GSVD_U_FP32_MFMA 2u /* FP32 working, n <= 128: U on the FP32 matrix cores instead of
+                               the default BF16 form, which cuts every entry of A and W
+                               exactly into three BF16 pieces and keeps the six piece
+                               products of order up to 2^-16 (FP32 accumulation; the
+                               dropped terms are below 2^-24 |a||w| each).  The batched call
+                               always forms U on the FP32 matrix cores */
 
 /* synchronous status codes (besides 0 and -k) */
 #define GSVD_OK 0

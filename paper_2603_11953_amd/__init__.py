@@ -18,7 +18,8 @@ import os
 
 __all__ = [
     "GSVD_F32", "GSVD_F64", "GSVD_GRAM_AUTO", "GSVD_GRAM_PLAIN", "GSVD_GRAM_SPLIT",
-    "GSVD_EIG_AUTO", "GSVD_EIG_JACOBI2", "GSVD_EIG_CHOL_JACOBI1", "GSVD_WANT_U", "GSVD_MAX_N",
+    "GSVD_EIG_AUTO", "GSVD_EIG_JACOBI2", "GSVD_EIG_CHOL_JACOBI1", "GSVD_WANT_U", "GSVD_U_FP32_MFMA",
+    "GSVD_MAX_N",
     "GsvdOpts", "GsvdError", "lib", "lib_path", "opts", "thin", "gram", "eig", "u_recover",
     "gsvd_opts_default", "gsvd_status_string", "gsvd_thin", "gsvd_thin_workspace_size",
     "gsvd_gram", "gsvd_gram_workspace_size", "gsvd_gram_config", "gram_config", "gsvd_eig", "gsvd_eig_workspace_size",
@@ -30,6 +31,7 @@ GSVD_F32, GSVD_F64 = 0, 1
 GSVD_GRAM_AUTO, GSVD_GRAM_PLAIN, GSVD_GRAM_SPLIT = 0, 1, 2
 GSVD_EIG_AUTO, GSVD_EIG_JACOBI2, GSVD_EIG_CHOL_JACOBI1 = 0, 1, 2
 GSVD_WANT_U = 1
+GSVD_U_FP32_MFMA = 2
 GSVD_MAX_N = 512
 GSVD_ERR_SCRATCH = -102
 GSVD_INFO_WARN_ASSUMPTION, GSVD_INFO_WARN_REFINE = 256, 512
@@ -148,12 +150,12 @@ def gram_config(m: int, n: int, working: int = GSVD_F64, gram: int = GSVD_GRAM_A
 def opts(working: int, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, *,
          want_u: bool = True, jacobi_tol: float = 0.0, max_sweeps: int = 0,
          n_slices: int = 0, slab_rows: int = 0, target_rel_err: float = 0.0,
-         kappa_b: float = 0.0) -> GsvdOpts:
+         kappa_b: float = 0.0, u_fp32_mfma: bool = False) -> GsvdOpts:
     o = GsvdOpts()
     lib.gsvd_opts_default(ctypes.byref(o), int(working))
     o.gram, o.eig, o.n_slices = int(gram), int(eig), int(n_slices)
     o.jacobi_tol, o.max_sweeps = float(jacobi_tol), int(max_sweeps)
-    o.flags = GSVD_WANT_U if want_u else 0
+    o.flags = (GSVD_WANT_U if want_u else 0) | (GSVD_U_FP32_MFMA if u_fp32_mfma else 0)
     o.slab_rows = int(slab_rows)
     o.target_rel_err, o.kappa_b = float(target_rel_err), float(kappa_b)
     return o
@@ -213,7 +215,8 @@ def workspace(nbytes: int, device):
 
 def thin(A, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, want_u: bool = True,
          jacobi_tol: float = 0.0, max_sweeps: int = 0, n_slices: int = 0, slab_rows: int = 0,
-         target_rel_err: float = 0.0, kappa_b: float = 0.0, work=None, stream=None):
+         target_rel_err: float = 0.0, kappa_b: float = 0.0, u_fp32_mfma: bool = False,
+         work=None, stream=None):
     """Thin SVD of a column-major CUDA tensor A (m x n).  Returns (S, V, U, info) tensors;
     info is a one-element int32 device tensor (check it after synchronising)."""
     torch = _torch()
@@ -222,7 +225,7 @@ def thin(A, *, gram: int = GSVD_GRAM_AUTO, eig: int = GSVD_EIG_AUTO, want_u: boo
     lda = _ld(A)
     o = opts(w, gram, eig, want_u=want_u, jacobi_tol=jacobi_tol, max_sweeps=max_sweeps,
              n_slices=n_slices, slab_rows=slab_rows, target_rel_err=target_rel_err,
-             kappa_b=kappa_b)
+             kappa_b=kappa_b, u_fp32_mfma=u_fp32_mfma)
     with _on(stream):
         S = torch.empty(n, dtype=A.dtype, device=A.device)
         V = colmajor_empty(n, n, A.dtype, A.device)
@@ -302,11 +305,12 @@ def eig(Mhi, Mlo, working: int, *, eig: int = GSVD_EIG_AUTO, jacobi_tol: float =
     return S, V, W, info
 
 
-def u_recover(A, W, *, stream=None):
-    """U = A W in the working precision of A."""
+def u_recover(A, W, *, u_fp32_mfma: bool = False, stream=None):
+    """U = A W in the working precision of A (FP32: the BF16 operand-split form unless
+    u_fp32_mfma)."""
     w = _working_of(A)
     m, n = int(A.shape[0]), int(A.shape[1])
-    o = opts(w)
+    o = opts(w, u_fp32_mfma=u_fp32_mfma)
     with _on(stream):
         U = colmajor_empty(m, n, A.dtype, A.device)
         rc = lib.gsvd_u_recover(m, n, A.data_ptr(), _ld(A), W.data_ptr(), _ld(W), U.data_ptr(),

@@ -363,6 +363,9 @@ inline hipError_t urecover_any(const gsvd_opts *o, int64_t m, int64_t n, const v
                                int64_t lda, const void *W, int64_t ldw, void *U, int64_t ldu,
                                hipStream_t st) {
     if (wide_n(n)) return urecover_wide_launch(o->working, m, n, A, lda, W, ldw, U, ldu, st);
+    if (o->working == GSVD_F32 && (o->flags & GSVD_U_FP32_MFMA) == 0)
+        return urecover_bf16_launch(m, n, (const float *)A, lda, (const float *)W, ldw, (float *)U,
+                                    ldu, st);
     return urecover_launch(o->working, m, n, A, lda, W, ldw, U, ldu, st);
 }
 

@@ -217,6 +217,10 @@ hipError_t trsm_rows_launch(int working, int64_t m, int64_t n, const void *A, in
 // U = A W (urecover.hip).
 hipError_t urecover_launch(int working, int64_t m, int64_t n, const void *A, int64_t lda,
                            const void *W, int64_t ldw, void *U, int64_t ldu, hipStream_t st);
+// FP32 working, n <= 128: U = A W on the BF16 matrix cores with every entry of A
+// and W cut exactly into three BF16 pieces (urecover_bf16.hip)
+hipError_t urecover_bf16_launch(int64_t m, int64_t n, const float *A, int64_t lda, const float *W,
+                                int64_t ldw, float *U, int64_t ldu, hipStream_t st);
 // Batched: the problems order[first .. first + count) share nt = ceil(n / 16).
 hipError_t urecover_batched_launch(int working, const BatchMat *tab, const int *order, int first,
                                    int count, int nt, int64_t max_m, hipStream_t st);

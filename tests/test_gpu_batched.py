@@ -67,7 +67,9 @@ def test_batched_parity_with_oracle(dt, ns, m_hi, form):
 @pytest.mark.parametrize("dt,form,slab", [("f64", "plain", 640), ("f64", "split", 256),
                                           ("f32", "plain", 1000), ("f32", "split", 512)])
 def test_batched_equals_single_calls(dt, form, slab):
-    """Same kernels, same slab height: every problem's S, V, U are bitwise those of gsvd_thin."""
+    """Same kernels, same slab height: every problem's S, V, U are bitwise those of gsvd_thin
+    (FP32 working: the batched call forms U on the FP32 matrix cores, the single call's
+    GSVD_U_FP32_MFMA form)."""
     import paper_2603_11953_amd as gs
     gram = gs.GSVD_GRAM_SPLIT if form == "split" else gs.GSVD_GRAM_PLAIN
     specs = _specs(5200, dt, (4, 16, 40, 64, 96), 7, 7000)
@@ -76,7 +78,7 @@ def test_batched_equals_single_calls(dt, form, slab):
     S, V, U, info = _run(As, gram=gram, slab_rows=slab)
     assert np.all(info == 0), info
     for k, A in enumerate(As):
-        s1, v1, u1, i1 = gs.thin(to_dev(A), gram=gram, slab_rows=slab)
+        s1, v1, u1, i1 = gs.thin(to_dev(A), gram=gram, slab_rows=slab, u_fp32_mfma=dt == "f32")
         _torch().cuda.synchronize()
         assert int(i1.item()) == 0
         assert np.array_equal(to_np(s1), S[k]), k

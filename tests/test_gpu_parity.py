@@ -136,19 +136,22 @@ def test_eig_parity(n, dt, mode):
                                     (17, 5, "f32"), (100_001, 64, "f32"), (4001, 128, "f32"),
                                     (50, 33, "f32")])
 def test_u_recover_parity(m, n, dt):
-    """U = A W within eq. (AV-0): |dU| <= (n + 2) u |A| |W|, against the dd product."""
+    """U = A W within eq. (AV-0): |dU| <= (n + 2) u |A| |W|, against the dd product.  FP32
+    working: both the default BF16 operand-split form and the FP32 matrix-core form."""
     import paper_2603_11953_amd as gs
     rng = np.random.default_rng(m + n)
     npdt = np.float64 if dt == "f64" else np.float32
     A = np.asfortranarray(rng.standard_normal((m, n)).astype(npdt))
     Wm = np.asfortranarray((rng.standard_normal((n, n)) * np.logspace(0, 6, n)).astype(npdt))
-    say("u_recover", m, n, dt)
-    Ud = gs.u_recover(to_dev(A), to_dev(Wm))
-    _sync()
-    Ug = to_np(Ud).astype(np.float64)
     Uh, Ul = ref.u_rows_dd(A, Wm.astype(np.float64), np.zeros((n, n)), np.ones(n), np.zeros(n))
     bound = (n + 2) * u_of(A) * (np.abs(A.astype(np.float64)) @ np.abs(Wm.astype(np.float64)))
-    assert np.all(np.abs((Ug - Uh) - Ul) <= bound)
+    for fp32_mfma in ((False, True) if dt == "f32" else (False,)):
+        say("u_recover", m, n, dt, "fp32 mfma" if fp32_mfma else "default")
+        Ud = gs.u_recover(to_dev(A), to_dev(Wm), u_fp32_mfma=fp32_mfma)
+        _sync()
+        Ug = to_np(Ud).astype(np.float64)
+        err = np.abs((Ug - Uh) - Ul)
+        assert np.all(err <= bound), (fp32_mfma, float((err / bound).max()))
 
 
 # ------------------------------------------------------------------ end to end
