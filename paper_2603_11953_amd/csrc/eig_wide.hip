@@ -437,7 +437,14 @@ struct JGeom {
     static constexpr int QLD = JC + 2;
 };
 
-template <int RPL, int JB>
+// TRACK (the preconditioner form): the squared column norms are formed once per step
+// and then carried through the rotations, ||x'||^2 = ||x||^2 - t x^T y and
+// ||y'||^2 = ||y||^2 + t x^T y with t = tan of the angle (exact when x'^T y' = 0; the
+// one-sided Jacobi of LAPACK's xGESVJ keeps its norms the same way), so a round
+// needs one cross-lane sum instead of three; a norm that the update would shrink
+// below 2^-10 of itself is summed again.  Without TRACK (Algorithm 2) every round
+// sums all three inner products.
+template <int RPL, int JB, bool TRACK>
 __global__ void __launch_bounds__(64 * JB)
 weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
                  double *__restrict__ Qbuf, double tol2) {
@@ -446,6 +453,7 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
     constexpr int LDL = 64 * RPL;  // rows of a column in LDS (n rounded up to 64)
     double *Xl = jsm;              // JC columns of X
     double *Qs = jsm + JC * LDL;   // JC x JC rotation product, column-major, stride QLD
+    double *nrm = Qs + JC * QLD;   // TRACK: squared column norms
     if (wg_read(&ctl->bad) || wg_read(&ctl->done)) return;
     int P, Qb;
     rr_pair(step, blockIdx.x, nblk, P, Qb);
@@ -473,18 +481,43 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6;
-    int any = 0;  // 1: a rotation, 2: one of a pair with cosine >= TAU_BIG
-    // one plane rotation of columns x0 (p) and x1 (q), held in registers; also on Q
-    auto rotate = [&](double (&x0)[RPL], double (&x1)[RPL], int p, int q) -> bool {
-        double al = 0.0, be = 0.0, ga = 0.0;
+    auto sq_sum = [&](const double (&x)[RPL]) {
+        double ss = 0.0;
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            al = __builtin_fma(x0[i], x0[i], al);
-            be = __builtin_fma(x1[i], x1[i], be);
-            ga = __builtin_fma(x0[i], x1[i], ga);
+        for (int i = 0; i < RPL; ++i) ss = __builtin_fma(x[i], x[i], ss);
+        return wave_sum(ss);
+    };
+    if constexpr (TRACK) {
+        for (int c = wave; c < JC; c += JT / 64) {
+            double x[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) x[i] = Xl[c * LDL + lane + 64 * i];
+            const double ss = sq_sum(x);
+            if (lane == 0) nrm[c] = ss;
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
+        __syncthreads();
+    }
+    int any = 0;  // 1: a rotation, 2: one of a pair with cosine >= TAU_BIG
+    // one plane rotation of columns x0 (p) and x1 (q), held in registers; also on Q.
+    // TRACK: al, be carry the squared norms in and out.
+    auto rotate = [&](double (&x0)[RPL], double (&x1)[RPL], int p, int q, double &al,
+                      double &be) -> bool {
+        double ga = 0.0;
+        if constexpr (TRACK) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) ga = __builtin_fma(x0[i], x1[i], ga);
+        } else {
+            al = 0.0;
+            be = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                al = __builtin_fma(x0[i], x0[i], al);
+                be = __builtin_fma(x1[i], x1[i], be);
+                ga = __builtin_fma(x0[i], x1[i], ga);
+            }
+            al = wave_sum(al);
+            be = wave_sum(be);
+        }
         ga = wave_sum(ga);
         if (!(ga * ga > tol2 * (al * be))) return false;  // uniform: the sums agree bitwise
         double c, sn;
@@ -502,6 +535,14 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
         }
         if (ga * ga >= (TAU_BIG * TAU_BIG) * (al * be)) any = 2;
         else if (any == 0) any = 1;
+        if constexpr (TRACK) {
+            const double t = sn / c;  // c >= 1/sqrt(2)
+            double a2 = __builtin_fma(-t, ga, al), b2 = __builtin_fma(t, ga, be);
+            if (!(a2 > 0x1p-10 * al)) a2 = sq_sum(x0);  // uniform across the wavefront
+            if (!(b2 > 0x1p-10 * be)) b2 = sq_sum(x1);
+            al = a2;
+            be = b2;
+        }
         return true;
     };
     double x0[RPL], x1[RPL];
@@ -520,11 +561,20 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
                 x0[i] = xp[64 * i];
                 x1[i] = xq[64 * i];
             }
-            if (rotate(x0, x1, p, q)) {
+            double al = 0.0, be = 0.0;
+            if constexpr (TRACK) {
+                al = nrm[p];
+                be = nrm[q];
+            }
+            if (rotate(x0, x1, p, q, al, be)) {
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) {
                     xp[64 * i] = x0[i];
                     xq[64 * i] = x1[i];
+                }
+                if (TRACK && lane == 0) {
+                    nrm[p] = al;
+                    nrm[q] = be;
                 }
             }
             __syncthreads();
@@ -537,14 +587,17 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
         double *xp = Xl + p * LDL + lane;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) x0[i] = xp[64 * i];
+        double al = TRACK ? nrm[p] : 0.0;  // the resident's norm stays in registers
         for (int r = 0; r < JB; ++r) {
             const int q = JB + (wave + r) % JB;
             double *xq = Xl + q * LDL + lane;
 #pragma unroll
             for (int i = 0; i < RPL; ++i) x1[i] = xq[64 * i];
-            if (rotate(x0, x1, p, q)) {
+            double be = TRACK ? nrm[q] : 0.0;
+            if (rotate(x0, x1, p, q, al, be)) {
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) xq[64 * i] = x1[i];
+                if (TRACK && lane == 0) nrm[q] = be;
             }
             __syncthreads();  // the travelers move on
         }
@@ -889,8 +942,8 @@ template <int RPL, int JB>
 hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double *Qbuf,
                         double tol2, int max_sweeps, bool early, hipStream_t st) {
     constexpr int JC = JGeom<JB>::JC, JT = JGeom<JB>::JT, QLD = JGeom<JB>::QLD;
-    const size_t lds = ((size_t)JC * 64 * RPL + JC * QLD) * sizeof(double);
-    auto k = weig_step_kernel<RPL, JB>;
+    const size_t lds = ((size_t)JC * 64 * RPL + JC * QLD + JC) * sizeof(double);
+    auto k = early ? weig_step_kernel<RPL, JB, true> : weig_step_kernel<RPL, JB, false>;
     auto kv = weig_vapply_kernel<JB>;
     const size_t lds_v = (size_t)VRW * n * sizeof(double);
     hipError_t err = hipFuncSetAttribute((const void *)k,
