@@ -89,8 +89,7 @@ struct Ctl {
     int done;     // converged
     int notconv;  // max_sweeps reached without convergence
     int abort;    // the output kernel must not write
-    int nswept;   // tournament rounds checked so far (those that ran)
-    int vpend;    // the round just checked rotated: its products are to be applied to V
+    int qran[2];  // per product slot: the step launch whose rotations ran and were written
     int rot[MAXWG];  // per step workgroup, this tournament round: 0 no rotation, 1 only
                      // pairs with cosine < TAU_BIG rotated, 2 a larger one
 };
@@ -124,7 +123,7 @@ WLayout wlayout(int64_t n) {
     L.x = o;    o = wal(o + nn * sizeof(double));
     L.v = o;    o = wal(o + nn * sizeof(double));
     const int nblk = jac_nblk((int)n);
-    L.qbuf = o; o = wal(o + (size_t)(nblk - 1) * (nblk / 2) * (4 * JBW * JBW) * sizeof(double));
+    L.qbuf = o; o = wal(o + (size_t)2 * (nblk / 2) * (4 * JBW * JBW) * sizeof(double));
     L.dinv = o; o = wal(o + (size_t)((n + 63) / 64) * 64 * 64 * sizeof(double));
     L.total = o;
     return L;
@@ -178,8 +177,8 @@ weig_diag_kernel(int n, const double *__restrict__ Mhi, int64_t ldm, Ctl *ctl, i
         ctl->done = 0;
         ctl->notconv = 0;
         ctl->abort = 0;
-        ctl->nswept = 0;
-        ctl->vpend = 0;
+        ctl->qran[0] = -1;
+        ctl->qran[1] = -1;
     }
 }
 
@@ -444,17 +443,26 @@ struct JGeom {
 // needs one cross-lane sum instead of three; a norm that the update would shrink
 // below 2^-10 of itself is summed again.  Without TRACK (Algorithm 2) every round
 // sums all three inner products.
+// Step launch g (= round * (nblk - 1) + step): workgroups 0 .. nblk/2 - 1 run the
+// step's rotations and write their products to slot g & 1; the rest (one per 16
+// rows of V) apply the products of launch g - 1 to V meanwhile, on other CUs.
 template <int RPL, int JB, bool TRACK>
 __global__ void __launch_bounds__(64 * JB)
-weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
-                 double *__restrict__ Qbuf, double tol2) {
+weig_step_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict__ X,
+                 double *__restrict__ Qbuf, double *__restrict__ Vw, double tol2) {
     extern __shared__ __attribute__((aligned(16))) double jsm[];
     constexpr int JC = JGeom<JB>::JC, JT = JGeom<JB>::JT, QLD = JGeom<JB>::QLD;
     constexpr int LDL = 64 * RPL;  // rows of a column in LDS (n rounded up to 64)
     double *Xl = jsm;              // JC columns of X
     double *Qs = jsm + JC * LDL;   // JC x JC rotation product, column-major, stride QLD
     double *nrm = Qs + JC * QLD;   // TRACK: squared column norms
+    if ((int)blockIdx.x >= nblk / 2) {
+        vapply_prev<JB>(n, nblk, g, ctl, Qbuf, Vw, (int)blockIdx.x - nblk / 2, jsm);
+        return;
+    }
     if (wg_read(&ctl->bad) || wg_read(&ctl->done)) return;
+    // this launch's rotations run (done and bad are the same for all its workgroups)
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->qran[g & 1] = g;
     int P, Qb;
     rr_pair(step, blockIdx.x, nblk, P, Qb);
     const int nbb = (n + JB - 1) / JB;
@@ -613,7 +621,7 @@ weig_step_kernel(int n, int nblk, int step, Ctl *ctl, double *__restrict__ X,
         const int r = q % LDL, g = gcol(q / LDL);
         if (r < n && g < n) X[r + (size_t)g * n] = Xl[q];
     }
-    double *Qo = Qbuf + ((size_t)step * gridDim.x + blockIdx.x) * (JC * JC);
+    double *Qo = Qbuf + ((size_t)(g & 1) * (nblk / 2) + blockIdx.x) * (JC * JC);
     for (int q = tid; q < JC * JC; q += JT) Qo[q] = Qs[(q / JC) + (q % JC) * QLD];
     // one plain store per workgroup into its own word (no contended atomics); the
     // word holds the largest level of the round's earlier steps (earlier launches)
@@ -632,34 +640,26 @@ __global__ void __launch_bounds__(64) weig_sweep_kernel(Ctl *ctl, int nwg, int l
     const bool anyrot = __any(r != 0), anybig = __any(r == 2);
     if (t < nwg) ctl->rot[t] = 0;
     if (t == 0) {
-        ctl->nswept += 1;
-        ctl->vpend = anyrot ? 1 : 0;
         if (!anyrot || (early && !anybig)) ctl->done = 1;
         else if (last) ctl->notconv = 1;
     }
 }
 
-// V <- V Q_s for the steps s of the tournament round just checked, in order (the
-// rotations never feed back into the Jacobi, so V follows a round behind).  One
-// workgroup per 16 rows of V, held in LDS for the whole round; wavefront b applies
-// the product of step workgroup b to the 32 columns of its block pair on the FP64
-// matrix cores (the pairs of a step are disjoint).  Skipped when the round did not
-// run or rotated nothing.
-// Operands (16x16x4): lane l supplies V(l % 16, k0 + l / 16) and Q(k0 + l / 16,
-// c0 + l % 16) (Q row-major: four 128-byte runs per read); result register r is
-// (V Q)(4 r + l / 16, c0 + l % 16).
+// V <- V Q for the products of one step (the rotations never feed back into the
+// Jacobi, so V follows a step behind).  A workgroup of 16 wavefronts holds 16 rows
+// of V in LDS; wavefront b applies the product of step workgroup b to the 32
+// columns of its block pair on the FP64 matrix cores (the pairs of a step are
+// disjoint).  Operands (16x16x4): lane l supplies V(l % 16, k0 + l / 16) and
+// Q(k0 + l / 16, c0 + l % 16) (Q row-major: four 128-byte runs per read); result
+// register r is (V Q)(4 r + l / 16, c0 + l % 16).
 constexpr int VRW = 16;  // rows of V per workgroup
 
 template <int JB>
-__global__ void __launch_bounds__(1024)
-weig_vapply_kernel(int n, int nblk, int sweep, const Ctl *ctl, const double *__restrict__ Qbuf,
-                   double *__restrict__ Vw) {
+__device__ __forceinline__ void vapply_step(int n, int nblk, int st, const double *__restrict__ Qs,
+                                            double *__restrict__ Vw, int r0, double *vsm) {
     constexpr int JC = JGeom<JB>::JC;
-    extern __shared__ __attribute__((aligned(16))) double vsm[];  // VRW x n, column-major
-    if (wg_read(&ctl->bad) || wg_read(&ctl->nswept) != sweep + 1 || !wg_read(&ctl->vpend)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r0 = blockIdx.x * VRW;
-    for (int q = tid; q < VRW * n; q += 1024) {
+    for (int q = tid; q < VRW * n; q += 64 * JB) {
         const int r = q % VRW, c = q / VRW;
         vsm[q] = (r0 + r < n) ? Vw[(r0 + r) + (size_t)c * n] : 0.0;
     }
@@ -667,44 +667,63 @@ weig_vapply_kernel(int n, int nblk, int sweep, const Ctl *ctl, const double *__r
     const int nbb = (n + JB - 1) / JB;
     const int npair = nblk / 2;
     const int li = lane & 15, lk = lane >> 4;
-    for (int st = 0; st < nblk - 1; ++st) {
-        int P = 0, Qb = 0;
-        if (wave < npair) rr_pair(st, wave, nblk, P, Qb);
-        // the step kernel's own early return (a bye block) wrote no product
-        const bool act = wave < npair && !((P >= nbb && Qb >= nbb) ||
-                                            ((P >= nbb || Qb >= nbb) && st != 0));
-        if (act) {  // uniform per wavefront
-            auto gcol = [&](int c) { return c < JB ? JB * P + c : JB * Qb + (c - JB); };
-            const double *Q = Qbuf + ((size_t)st * npair + wave) * (JC * JC);
-            double b0[JC / 4], b1[JC / 4];
+    int P = 0, Qb = 0;
+    if (wave < npair) rr_pair(st, wave, nblk, P, Qb);
+    // the step kernel's own early return (a bye block) wrote no product
+    const bool act = wave < npair && !((P >= nbb && Qb >= nbb) ||
+                                        ((P >= nbb || Qb >= nbb) && st != 0));
+    if (act) {  // uniform per wavefront
+        auto gcol = [&](int c) { return c < JB ? JB * P + c : JB * Qb + (c - JB); };
+        const double *Q = Qs + (size_t)wave * (JC * JC);
+        double b0[JC / 4], b1[JC / 4];
 #pragma unroll
-            for (int k = 0; k < JC / 4; ++k) {  // every operand load issued first
-                b0[k] = Q[li + (4 * k + lk) * JC];
-                b1[k] = Q[(16 + li) + (4 * k + lk) * JC];
-            }
-            f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int k = 0; k < JC / 4; ++k) {
-                const int gk = gcol(4 * k + lk);
-                const double a = gk < n ? vsm[li + gk * VRW] : 0.0;
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0[k], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1[k], acc1, 0, 0, 0);
-            }
-            // (this wavefront alone reads and writes the pair's columns: its reads above
-            // precede these writes)
-            const int g0 = gcol(li), g1 = gcol(16 + li);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (g0 < n) vsm[(4 * r + lk) + g0 * VRW] = acc0[r];
-                if (g1 < n) vsm[(4 * r + lk) + g1 * VRW] = acc1[r];
-            }
+        for (int k = 0; k < JC / 4; ++k) {  // every operand load issued first
+            b0[k] = Q[li + (4 * k + lk) * JC];
+            b1[k] = Q[(16 + li) + (4 * k + lk) * JC];
         }
-        __syncthreads();
+        f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < JC / 4; ++k) {
+            const int gk = gcol(4 * k + lk);
+            const double a = gk < n ? vsm[li + gk * VRW] : 0.0;
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0[k], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1[k], acc1, 0, 0, 0);
+        }
+        // (this wavefront alone reads and writes the pair's columns: its reads above
+        // precede these writes)
+        const int g0 = gcol(li), g1 = gcol(16 + li);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (g0 < n) vsm[(4 * r + lk) + g0 * VRW] = acc0[r];
+            if (g1 < n) vsm[(4 * r + lk) + g1 * VRW] = acc1[r];
+        }
     }
-    for (int q = tid; q < VRW * n; q += 1024) {
+    __syncthreads();
+    for (int q = tid; q < VRW * n; q += 64 * JB) {
         const int r = q % VRW, c = q / VRW;
         if (r0 + r < n) Vw[(r0 + r) + (size_t)c * n] = vsm[q];
     }
+}
+
+// the product of step launch g - 1 (if its rotations ran) applied to the strip of
+// workgroup vb (the V role of step launch g, or the last launch's flush)
+template <int JB>
+__device__ __forceinline__ void vapply_prev(int n, int nblk, int g, const Ctl *ctl,
+                                            const double *__restrict__ Qbuf,
+                                            double *__restrict__ Vw, int vb, double *vsm) {
+    constexpr int JC = JGeom<JB>::JC;
+    if (g == 0 || wg_read(&ctl->bad) || wg_read(&ctl->qran[(g - 1) & 1]) != g - 1) return;
+    const int npair = nblk / 2;
+    vapply_step<JB>(n, nblk, (g - 1) % (nblk - 1),
+                    Qbuf + (size_t)((g - 1) & 1) * npair * (JC * JC), Vw, vb * VRW, vsm);
+}
+
+template <int JB>
+__global__ void __launch_bounds__(64 * JB)
+weig_vflush_kernel(int n, int nblk, int g, const Ctl *ctl, const double *__restrict__ Qbuf,
+                   double *__restrict__ Vw) {
+    extern __shared__ __attribute__((aligned(16))) double vsm[];  // VRW x n, column-major
+    vapply_prev<JB>(n, nblk, g, ctl, Qbuf, Vw, blockIdx.x, vsm);
 }
 
 // ---- 5. sigma, signs, ordering, outputs
@@ -942,30 +961,32 @@ template <int RPL, int JB>
 hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double *Qbuf,
                         double tol2, int max_sweeps, bool early, hipStream_t st) {
     constexpr int JC = JGeom<JB>::JC, JT = JGeom<JB>::JT, QLD = JGeom<JB>::QLD;
+    // the Jacobi role's LDS; the V role needs VRW n <= JC 64 RPL doubles of it
     const size_t lds = ((size_t)JC * 64 * RPL + JC * QLD + JC) * sizeof(double);
     auto k = early ? weig_step_kernel<RPL, JB, true> : weig_step_kernel<RPL, JB, false>;
-    auto kv = weig_vapply_kernel<JB>;
+    auto kf = weig_vflush_kernel<JB>;
     const size_t lds_v = (size_t)VRW * n * sizeof(double);
+    const int vstrips = (n + VRW - 1) / VRW;
     hipError_t err = hipFuncSetAttribute((const void *)k,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    err = hipFuncSetAttribute((const void *)kv, hipFuncAttributeMaxDynamicSharedMemorySize,
+    err = hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_v);
     if (err != hipSuccess) return err;
+    int g = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
-        for (int s = 0; s < nblk - 1; ++s) {
-            hipLaunchKernelGGL(k, dim3((unsigned)(nblk / 2)), dim3(JT), lds, st, n, nblk, s, ctl,
-                               X, Qbuf, tol2);
+        for (int s = 0; s < nblk - 1; ++s, ++g) {
+            hipLaunchKernelGGL(k, dim3((unsigned)(nblk / 2 + vstrips)), dim3(JT), lds, st, n, nblk,
+                               s, g, ctl, X, Qbuf, Vw, tol2);
             if ((err = hipGetLastError()) != hipSuccess) return err;
         }
         hipLaunchKernelGGL(weig_sweep_kernel, dim3(1), dim3(64), 0, st, ctl, nblk / 2,
                            sw + 1 == max_sweeps ? 1 : 0, early ? 1 : 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        hipLaunchKernelGGL(kv, dim3((unsigned)((n + VRW - 1) / VRW)), dim3(1024), lds_v, st, n,
-                           nblk, sw, ctl, Qbuf, Vw);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    return hipSuccess;
+    // the last launch's products, if its rotations ran
+    hipLaunchKernelGGL(kf, dim3((unsigned)vstrips), dim3(JT), lds_v, st, n, nblk, g, ctl, Qbuf, Vw);
+    return hipGetLastError();
 }
 
 // ---- the Cholesky factor alone (mixed precision Cholesky QR, Sec. 3.3)
