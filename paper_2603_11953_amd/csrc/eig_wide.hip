@@ -29,13 +29,14 @@
 //      reduction that leaves bitwise identical sums in every lane; the rotation
 //      parameters use the hardware reciprocal and reciprocal square root
 //      refined by Newton steps, as in the one-workgroup kernel.  The
-//      rotations of a step accumulate in a 32 x 32 product Q, which goes to a
-//      buffer: V never feeds back into the rotations, so after each tournament
-//      round one launch applies that round's products to V in step order, over
-//      16-row strips of V on many workgroups (FP64 matrix cores).  One launch
-//      per step; after each tournament round a one-lane kernel marks
-//      convergence when no rotation passed the test
-//      |x_p^T x_q| > tol ||x_p|| ||x_q||, and later launches return at once.
+//      rotations of a step accumulate in a 32 x 32 product Q, which goes to one of
+//      two buffer slots: V never feeds back into the rotations, so the extra
+//      workgroups of the next step's launch (one per 16 rows of V, on CUs the
+//      rotations leave idle) apply it to V on the FP64 matrix cores, and a last
+//      launch applies the final step's.  One launch per step; after each
+//      tournament round a one-lane kernel marks convergence when no rotation
+//      passed the test |x_p^T x_q| > tol ||x_p|| ||x_q||, and later launches
+//      return at once.
 //   5. sigma_p = ||x_p|| 2^e_max, ordering, sign of the V columns (entry of
 //      largest magnitude positive, lowest index on ties), W = fl(V Sigma^-1).
 //   The same outputs and info codes as the one-workgroup kernel for n <= 96.
