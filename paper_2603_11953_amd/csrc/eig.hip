@@ -102,6 +102,14 @@ __device__ __forceinline__ double dpp_d(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// x of lane l (l uniform), in every lane
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Sum over aligned groups of 8 lanes (half a DPP row).  Steps: xor 1, xor 2
 // (quad permutes), then the half-row mirror (lane i <-> 7 - i).  Every step
 // adds the values of two lanes that hold the same partial sums in swapped
@@ -164,6 +172,7 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
     // ---- 1. scaling exponents and input checks
     for (int j = tid; j < n; j += nthr) {
         const double mjj = Mhi[j + (int64_t)j * ldm];
+        ssig[j] = mjj;  // the diagonal, for the ordering below
         if (!(mjj > 0.0) || !__builtin_isfinite(mjj)) {
             atomicMax(&sh.flag_bad, __builtin_isfinite(mjj) ? 1 : 3);
             sexp[j] = 0;
@@ -185,10 +194,10 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
     int *sperm = sm.sperm;
     if (pre) {  // rank by m_jj descending, ties by index (every m_jj is positive here)
         for (int j = tid; j < n; j += nthr) {
-            const double mj = Mhi[j + (int64_t)j * ldm];
+            const double mj = ssig[j];
             int r = 0;
             for (int q = 0; q < n; ++q) {
-                const double mq = Mhi[q + (int64_t)q * ldm];
+                const double mq = ssig[q];
                 r += (mq > mj) || (mq == mj && q < j);
             }
             sperm[r] = j;
@@ -537,9 +546,8 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
 
     if (pre) {
         // ---- 5'. V' = X'^-1 Q Sigma_Z: T = Q Sigma_Z over Q in Vs, R' (in W) to the Y
-        //      area, back substitution one row per barrier, the reciprocal of R'_kk
-        //      applied to each row once it is final; then V(pi_r, p) = V'(r, p)
-        //      2^-e_pi_r (exact), columns normalised
+        //      area, back substitution; then V(pi_r, p) = V'(r, p) 2^-e_pi_r (exact),
+        //      columns normalised
         for (int p = grp; p < n; p += ngrp) {
             double ss = 0.0;
             for (int r = gl; r < n; r += GRP) {
@@ -554,33 +562,64 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
         double *Rt = reinterpret_cast<double *>(Y);
         for (int q = tid; q < n * n; q += nthr) {
             const int r = q % n, p = q / n;
-            T[r + p * ld] *= ssig[p];
             Rt[r + p * ld] = r <= p ? (double)W[r + (int64_t)p * ldw] : 0.0;
         }
+        for (int k = tid; k < n; k += nthr) ssign[k] = 1.0 / (double)W[k + (int64_t)k * ldw];
         __syncthreads();
-        for (int k = tid; k < n; k += nthr) ssign[k] = 1.0 / Rt[k + k * ld];
-        __syncthreads();
-        for (int k = n - 1; k >= 1; --k) {
-            // rows r < k take row k's contribution; row k is final (not yet scaled)
-            const double rk = ssign[k];
-            for (int q = tid; q < k * n; q += nthr) {
-                const int r = q % k, p = q / k;
-                T[r + p * ld] = __builtin_fma(-Rt[r + k * ld], rk * T[k + p * ld], T[r + p * ld]);
+        // Each wavefront solves its own columns (up to four at a time, lane l holding
+        // rows l and l + 64), with no workgroup barrier: at step k the final (unscaled)
+        // t_k of each column is read from its lane and rows r < k take
+        // -R'_rk t_k / R'_kk.  Then x_r = t_r / R'_rr, the scaling by 2^(emax - e_pi_r),
+        // the column's norm (a butterfly sum: every lane gets the same bits) and the
+        // store into row pi_r of V.
+        const int lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+        for (int p0 = wv; p0 < n; p0 += 4 * nwv) {
+            double t[4][2];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int p = p0 + c * nwv;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int r = lane + 64 * j;
+                    t[c][j] = (p < n && r < n) ? T[r + p * ld] * ssig[p] : 0.0;
+                }
             }
-            __syncthreads();
-        }
-        const int emaxp = emax;
-        for (int q = tid; q < n * n; q += nthr) {
-            const int r = q % n, p = q / n;
-            T[r + p * ld] = ldexp(T[r + p * ld] * ssign[r], emaxp - sexp[sperm[r]]);
-        }
-        __syncthreads();
-        for (int p = grp; p < n; p += ngrp) {
-            double ss = 0.0;
-            for (int r = gl; r < n; r += GRP) ss = __builtin_fma(T[r + p * ld], T[r + p * ld], ss);
-            ss = group_sum(ss);
-            const double inv = 1.0 / __builtin_sqrt(ss);
-            for (int r = gl; r < n; r += GRP) V[sperm[r] + (int64_t)p * ldv] = (TW)(T[r + p * ld] * inv);
+            for (int k = n - 1; k >= 1; --k) {
+                const int kj = k >> 6, kl = k & 63;  // uniform
+                const double rk = ssign[k];
+                double rc[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int r = lane + 64 * j;
+                    rc[j] = r < k ? Rt[r + k * ld] : 0.0;  // rows k and beyond are final
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double tk = rk * readlane_d(kj ? t[c][1] : t[c][0], kl);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) t[c][j] = __builtin_fma(-rc[j], tk, t[c][j]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int p = p0 + c * nwv;
+                if (p >= n) break;  // uniform
+                double x[2], ss = 0.0;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int r = lane + 64 * j;
+                    x[j] = r < n ? ldexp(t[c][j] * ssign[r], emax - sexp[sperm[r]]) : 0.0;
+                    ss = __builtin_fma(x[j], x[j], ss);
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
+                const double inv = 1.0 / __builtin_sqrt(ss);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int r = lane + 64 * j;
+                    if (r < n) V[sperm[r] + (int64_t)p * ldv] = (TW)(x[j] * inv);
+                }
+            }
         }
         if (tid == 0) *info = 0;
         return;

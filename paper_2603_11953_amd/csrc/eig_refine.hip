@@ -62,7 +62,6 @@ namespace {
 constexpr double TAU_STOP = 0x1p-30;   // last sweep: every angle at most this
 constexpr double TAU_CLUSTER = 0x1p-8; // larger angles: a cluster pair, not rotated
 constexpr int TB = 32;                 // output tile edge of the products
-constexpr int KC = 16;                 // k-chunk staged through LDS
 constexpr int FT = 1024;               // lanes of the per-problem kernels
 
 struct RefCtrl {
@@ -182,14 +181,19 @@ __global__ void __launch_bounds__(256) ref_init_kernel(P probs, int rk) {
 }
 
 // MODE 0: T = M X.  MODE 1: [S | G] = X^T [T | X].  MODE 2: X' = X + X F.
-// One workgroup per 32 x 32 output tile; each lane owns a 2 x 2 block (rows
-// tx, tx + 16 and columns ty, ty + 16 of the tile).
-template <int MODE, class P>
+// One workgroup per TBT x TBT output tile (32, or 16 for a single problem whose
+// 32 x 32 tiles would leave most of the chip idle); each lane owns a TBT / 16
+// square block of it (rows tx + 16 a, columns ty + 16 b).  Every output is
+// accumulated over k = 0 .. n - 1 in order, whatever the tile: the two tile sizes
+// give the same bits.
+template <int MODE, class P, int TBT>
 __global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter) {
+    constexpr int RB = TBT / 16;         // outputs per lane along each dimension
+    constexpr int KCT = 16 * 32 / TBT;   // k-chunk: the LDS tiles keep one size
     const RefProb p = probs.get(blockIdx.z);
     const int n = p.n;
     const int ncol = MODE == 1 ? 2 * n : n;
-    const int i0 = blockIdx.x * TB, j0 = blockIdx.y * TB;
+    const int i0 = blockIdx.x * TBT, j0 = blockIdx.y * TBT;
     if (i0 >= n || j0 >= ncol) return;
     RefBufs B = ref_bufs(p.rw, n);
     if (iter > B.ctrl->stop_iter) return;
@@ -212,19 +216,23 @@ __global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter) {
         }
     }
 
-    __shared__ double Ah[TB][KC + 1], Al[TB][KC + 1], Bh[KC][TB + 1], Bl[KC][TB + 1];
+    __shared__ double Ah[TBT][KCT + 1], Al[TBT][KCT + 1], Bh[KCT][TBT + 1], Bl[KCT][TBT + 1];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    double ch[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, cl[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    double ch[RB][RB], cl[RB][RB];
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+        for (int b = 0; b < RB; ++b) ch[a][b] = cl[a][b] = 0.0;
 
-    for (int k0 = 0; k0 < n; k0 += KC) {
-        for (int e = tid; e < TB * KC; e += 256) {
+    for (int k0 = 0; k0 < n; k0 += KCT) {
+        for (int e = tid; e < TBT * KCT; e += 256) {
             int i, k;
             if (MODE == 1) {  // A = X^T: contiguous along k
-                k = e % KC;
-                i = e / KC;
+                k = e % KCT;
+                i = e / KCT;
             } else {          // A = M or X: contiguous along i
-                i = e % TB;
-                k = e / TB;
+                i = e % TBT;
+                k = e / TBT;
             }
             const int gi = i0 + i, gk = k0 + k;
             double ah = 0.0, al = 0.0;
@@ -244,8 +252,8 @@ __global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter) {
             Ah[i][k] = ah;
             Al[i][k] = al;
         }
-        for (int e = tid; e < TB * KC; e += 256) {
-            const int k = e % KC, j = e / KC;
+        for (int e = tid; e < TBT * KCT; e += 256) {
+            const int k = e % KCT, j = e / KCT;
             const int gk = k0 + k, gj = j0 + j;
             double bh = 0.0, bl = 0.0;
             if (gk < n && gj < ncol) {
@@ -269,22 +277,26 @@ __global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter) {
         }
         __syncthreads();
 #pragma unroll 4
-        for (int k = 0; k < KC; ++k) {
-            const double a0h = Ah[tx][k], a0l = Al[tx][k];
-            const double a1h = Ah[tx + 16][k], a1l = Al[tx + 16][k];
-            const double b0h = Bh[k][ty], b0l = Bl[k][ty];
-            const double b1h = Bh[k][ty + 16], b1l = Bl[k][ty + 16];
-            mac_dd(ch[0][0], cl[0][0], a0h, a0l, b0h, b0l);
-            mac_dd(ch[1][0], cl[1][0], a1h, a1l, b0h, b0l);
-            mac_dd(ch[0][1], cl[0][1], a0h, a0l, b1h, b1l);
-            mac_dd(ch[1][1], cl[1][1], a1h, a1l, b1h, b1l);
+        for (int k = 0; k < KCT; ++k) {
+            double ah[RB], al[RB], bh[RB], bl[RB];
+#pragma unroll
+            for (int a = 0; a < RB; ++a) {
+                ah[a] = Ah[tx + 16 * a][k];
+                al[a] = Al[tx + 16 * a][k];
+                bh[a] = Bh[k][ty + 16 * a];
+                bl[a] = Bl[k][ty + 16 * a];
+            }
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int a = 0; a < RB; ++a) mac_dd(ch[a][b], cl[a][b], ah[a], al[a], bh[b], bl[b]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < RB; ++a) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < RB; ++b) {
             const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * b;
             if (gi >= n || gj >= ncol) continue;
             dd_t c = two_sum(ch[a][b], cl[a][b]);
@@ -569,15 +581,30 @@ hipError_t refine_queue(P probs, int count, int max_n, bool f32, int rk, hipStre
                        probs, rk);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
+    // a single problem with fewer than 256 tiles of 32 x 32 takes 16 x 16 tiles
+    const bool t16 = count == 1 && nt * nt < 256;
+    const unsigned ns = (unsigned)((max_n + 15) / 16);
     for (int it = 0; it < rk; ++it) {
-        hipLaunchKernelGGL((ref_gemm_kernel<0, P>), dim3(nt, nt, count), dim3(256), 0, st, probs,
-                           it);
-        hipLaunchKernelGGL((ref_gemm_kernel<1, P>), dim3(nt, 2 * nt, count), dim3(256), 0, st,
-                           probs, it);
+        if (t16)
+            hipLaunchKernelGGL((ref_gemm_kernel<0, P, 16>), dim3(ns, ns, count), dim3(256), 0, st,
+                               probs, it);
+        else
+            hipLaunchKernelGGL((ref_gemm_kernel<0, P, TB>), dim3(nt, nt, count), dim3(256), 0, st,
+                               probs, it);
+        if (t16)
+            hipLaunchKernelGGL((ref_gemm_kernel<1, P, 16>), dim3(ns, 2 * ns, count), dim3(256), 0,
+                               st, probs, it);
+        else
+            hipLaunchKernelGGL((ref_gemm_kernel<1, P, TB>), dim3(nt, 2 * nt, count), dim3(256), 0,
+                               st, probs, it);
         hipLaunchKernelGGL(ref_angles_kernel<P>, dim3(ablocks, (unsigned)count), dim3(FT), 0, st,
                            probs, it);
-        hipLaunchKernelGGL((ref_gemm_kernel<2, P>), dim3(nt, nt, count), dim3(256), 0, st, probs,
-                           it);
+        if (t16)
+            hipLaunchKernelGGL((ref_gemm_kernel<2, P, 16>), dim3(ns, ns, count), dim3(256), 0, st,
+                               probs, it);
+        else
+            hipLaunchKernelGGL((ref_gemm_kernel<2, P, TB>), dim3(nt, nt, count), dim3(256), 0, st,
+                               probs, it);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     const unsigned cblocks = (unsigned)((max_n + FT / 64 - 1) / (FT / 64));

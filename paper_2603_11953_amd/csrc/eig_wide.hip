@@ -444,6 +444,11 @@ struct JGeom {
 // needs one cross-lane sum instead of three; a norm that the update would shrink
 // below 2^-10 of itself is summed again.  Without TRACK (Algorithm 2) every round
 // sums all three inner products.
+template <int JB>
+__device__ __forceinline__ void vapply_prev(int n, int nblk, int g, const Ctl *ctl,
+                                            const double *__restrict__ Qbuf,
+                                            double *__restrict__ Vw, int vb, double *vsm);
+
 // Step launch g (= round * (nblk - 1) + step): workgroups 0 .. nblk/2 - 1 run the
 // step's rotations and write their products to slot g & 1; the rest (one per 16
 // rows of V) apply the products of launch g - 1 to V meanwhile, on other CUs.
