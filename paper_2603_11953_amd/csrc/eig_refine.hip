@@ -162,24 +162,6 @@ __device__ __forceinline__ void mac_dd(double &h, double &l, double ah, double a
     l += err + e;
 }
 
-template <class P>
-__global__ void __launch_bounds__(256) ref_init_kernel(P probs, int rk) {
-    const RefProb p = probs.get(blockIdx.y);
-    const int n = p.n;
-    const int nn = n * n;
-    RefBufs B = ref_bufs(p.rw, n);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        B.ctrl->stop_iter = (*p.info != 0) ? -1 : rk - 1;
-        B.ctrl->warn = 0;
-        B.ctrl->pad[0] = rk;
-    }
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= nn) return;
-    const int r = idx % n, c = idx / n;
-    B.xh[0][idx] = p.X0[r + (int64_t)c * p.ldx0];
-    B.xl[0][idx] = 0.0;
-}
-
 // MODE 0: T = M X.  MODE 1: [S | G] = X^T [T | X].  MODE 2: X' = X + X F.
 // One workgroup per TBT x TBT output tile (32, or 16 for a single problem whose
 // 32 x 32 tiles would leave most of the chip idle); each lane owns a TBT / 16
@@ -187,7 +169,7 @@ __global__ void __launch_bounds__(256) ref_init_kernel(P probs, int rk) {
 // accumulated over k = 0 .. n - 1 in order, whatever the tile: the two tile sizes
 // give the same bits.
 template <int MODE, class P, int TBT>
-__global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter) {
+__global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter, int rk) {
     constexpr int RB = TBT / 16;         // outputs per lane along each dimension
     constexpr int KCT = 16 * 32 / TBT;   // k-chunk: the LDS tiles keep one size
     const RefProb p = probs.get(blockIdx.z);
@@ -196,20 +178,33 @@ __global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter) {
     const int i0 = blockIdx.x * TBT, j0 = blockIdx.y * TBT;
     if (i0 >= n || j0 >= ncol) return;
     RefBufs B = ref_bufs(p.rw, n);
-    if (iter > B.ctrl->stop_iter) return;
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+    // the first product of the first sweep sets the stage up: sweeps 0 .. rk - 1
+    // queued (none if the preconditioner failed), X_0 = the preconditioner's basis
+    // (copied by the workgroups of the first tile row as they stage it)
+    const bool first = MODE == 0 && iter == 0;
+    if (first) {
+        const bool failed = *p.info != 0;
+        if (lead) {
+            B.ctrl->stop_iter = failed ? -1 : rk - 1;
+            B.ctrl->warn = 0;
+        }
+        if (failed) return;
+    } else if (iter > B.ctrl->stop_iter) {
+        return;
+    }
     const int cur = iter & 1;
     const double *__restrict__ Xh = B.xh[cur];
     const double *__restrict__ Xl = B.xl[cur];
-    if (MODE == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (MODE == 0 && lead) {
         B.ctrl->maxbits = 0ull;  // the angle kernel of this sweep reduces into these
         B.ctrl->clus = 0;
     }
-    if (MODE == 2 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (MODE == 2 && lead) {
         // the decision of this sweep (its angles are all in): the last sweep if every
         // angle is below TAU_STOP, or if it is the last one queued.  Other workgroups
         // of this launch read stop_iter as iter or rk - 1, both >= iter: they all run.
         const double mx = __longlong_as_double((long long)B.ctrl->maxbits);
-        const int rk = B.ctrl->pad[0];
         if (mx <= TAU_STOP || iter == rk - 1) {
             B.ctrl->stop_iter = iter;
             B.ctrl->warn = (mx <= TAU_STOP ? 0 : 1) | (B.ctrl->clus ? 2 : 0);
@@ -257,7 +252,13 @@ __global__ void __launch_bounds__(256) ref_gemm_kernel(P probs, int iter) {
             const int gk = k0 + k, gj = j0 + j;
             double bh = 0.0, bl = 0.0;
             if (gk < n && gj < ncol) {
-                if (MODE == 0) {
+                if (first) {
+                    bh = p.X0[gk + (int64_t)gj * p.ldx0];
+                    if (blockIdx.x == 0) {
+                        B.xh[0][gk + gj * n] = bh;
+                        B.xl[0][gk + gj * n] = 0.0;
+                    }
+                } else if (MODE == 0) {
                     bh = Xh[gk + gj * n];
                     bl = Xl[gk + gj * n];
                 } else if (MODE == 1) {
@@ -385,20 +386,25 @@ __global__ void __launch_bounds__(FT) ref_angles_kernel(P probs, int iter) {
     }
 }
 
-// sigma_c = sqrt(lambda_c) and the sign of column c of the final X (its entry of
-// largest magnitude made positive, the lowest index on ties): grid (groups of 16
-// columns, problems), one wavefront per column; written to the T planes (free once
-// the last sweep has run).
-template <class P>
-__global__ void __launch_bounds__(FT) ref_colstat_kernel(P probs) {
+// sigma_c = sqrt(lambda_c) (every workgroup forms all n, for the ordering), the
+// sign of column c of the final X (its entry of largest magnitude made positive,
+// the lowest index on ties), ordering (sigma descending, stable), cast, W: grid
+// (groups of 16 columns, problems), one wavefront per column.
+template <typename TW, class P>
+__global__ void __launch_bounds__(FT) ref_write_kernel(P probs) {
     const RefProb p = probs.get(blockIdx.y);
     const int n = p.n;
-    const int c = blockIdx.x * (FT / 64) + (threadIdx.x >> 6);
-    if (c >= n) return;
+    const int c0 = blockIdx.x * (FT / 64);
+    if (c0 >= n) return;
     RefBufs B = ref_bufs(p.rw, n);
     const int stop = B.ctrl->stop_iter;
     if (stop < 0) return;
     const double *__restrict__ Xh = B.xh[(stop + 1) & 1];
+    __shared__ double sig[GSVD_WIDE_MAX_N];
+    for (int q = threadIdx.x; q < n; q += FT) sig[q] = dd_sqrt(dd_t{B.lh[q], B.ll[q]}).hi;
+    __syncthreads();
+    const int c = c0 + (threadIdx.x >> 6);
+    if (c >= n) return;
     const int lane = threadIdx.x & 63;
     double best = -1.0;
     int barg = 0;
@@ -418,36 +424,12 @@ __global__ void __launch_bounds__(FT) ref_colstat_kernel(P probs) {
             barg = oa;
         }
     }
-    if (lane == 0) {
-        B.th[c] = dd_sqrt(dd_t{B.lh[c], B.ll[c]}).hi;         // sigma_c
-        B.tl[c] = Xh[barg + c * n] < 0.0 ? -1.0 : 1.0;     // sign of column c
-    }
-}
-
-// Ordering (sigma descending, stable), cast, W: grid (groups of 16 columns,
-// problems), one wavefront per column.
-template <typename TW, class P>
-__global__ void __launch_bounds__(FT) ref_write_kernel(P probs) {
-    const RefProb p = probs.get(blockIdx.y);
-    const int n = p.n;
-    const int c0 = blockIdx.x * (FT / 64);
-    if (c0 >= n) return;
-    RefBufs B = ref_bufs(p.rw, n);
-    const int stop = B.ctrl->stop_iter;
-    if (stop < 0) return;
-    const double *__restrict__ Xh = B.xh[(stop + 1) & 1];
-    __shared__ double sig[GSVD_WIDE_MAX_N];
-    for (int q = threadIdx.x; q < n; q += FT) sig[q] = B.th[q];
-    __syncthreads();
-    const int c = c0 + (threadIdx.x >> 6);
-    if (c >= n) return;
-    const int lane = threadIdx.x & 63;
+    const double sg = Xh[barg + c * n] < 0.0 ? -1.0 : 1.0;
     const double sc = sig[c];
     int rk = 0;
     for (int q = lane; q < n; q += 64) rk += (sig[q] > sc) || (sig[q] == sc && q < c);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) rk += __shfl_xor(rk, off, 64);
-    const double sg = B.tl[c];
     TW *S = reinterpret_cast<TW *>(p.S);
     TW *V = reinterpret_cast<TW *>(p.V);
     TW *W = reinterpret_cast<TW *>(p.W);
@@ -575,41 +557,35 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(double *__restrict__ p, 
 template <class P>
 hipError_t refine_queue(P probs, int count, int max_n, bool f32, int rk, hipStream_t st) {
     const int nt = (max_n + TB - 1) / TB;
-    const unsigned nn_blocks = (unsigned)(((size_t)max_n * max_n + 255) / 256);
     const unsigned ablocks = (unsigned)(((size_t)max_n * max_n + FT * AE - 1) / (FT * AE));
-    hipLaunchKernelGGL(ref_init_kernel<P>, dim3(nn_blocks, (unsigned)count), dim3(256), 0, st,
-                       probs, rk);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
+    hipError_t err;
     // a single problem with fewer than 256 tiles of 32 x 32 takes 16 x 16 tiles
     const bool t16 = count == 1 && nt * nt < 256;
     const unsigned ns = (unsigned)((max_n + 15) / 16);
     for (int it = 0; it < rk; ++it) {
         if (t16)
             hipLaunchKernelGGL((ref_gemm_kernel<0, P, 16>), dim3(ns, ns, count), dim3(256), 0, st,
-                               probs, it);
+                               probs, it, rk);
         else
             hipLaunchKernelGGL((ref_gemm_kernel<0, P, TB>), dim3(nt, nt, count), dim3(256), 0, st,
-                               probs, it);
+                               probs, it, rk);
         if (t16)
             hipLaunchKernelGGL((ref_gemm_kernel<1, P, 16>), dim3(ns, 2 * ns, count), dim3(256), 0,
-                               st, probs, it);
+                               st, probs, it, rk);
         else
             hipLaunchKernelGGL((ref_gemm_kernel<1, P, TB>), dim3(nt, 2 * nt, count), dim3(256), 0,
-                               st, probs, it);
+                               st, probs, it, rk);
         hipLaunchKernelGGL(ref_angles_kernel<P>, dim3(ablocks, (unsigned)count), dim3(FT), 0, st,
                            probs, it);
         if (t16)
             hipLaunchKernelGGL((ref_gemm_kernel<2, P, 16>), dim3(ns, ns, count), dim3(256), 0, st,
-                               probs, it);
+                               probs, it, rk);
         else
             hipLaunchKernelGGL((ref_gemm_kernel<2, P, TB>), dim3(nt, nt, count), dim3(256), 0, st,
-                               probs, it);
+                               probs, it, rk);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     const unsigned cblocks = (unsigned)((max_n + FT / 64 - 1) / (FT / 64));
-    hipLaunchKernelGGL(ref_colstat_kernel<P>, dim3(cblocks, (unsigned)count), dim3(FT), 0, st,
-                       probs);
     if (f32)
         hipLaunchKernelGGL((ref_write_kernel<float, P>), dim3(cblocks, (unsigned)count), dim3(FT),
                            0, st, probs);
