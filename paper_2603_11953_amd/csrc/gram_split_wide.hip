@@ -7,11 +7,13 @@
 // 512 a workgroup that sliced the columns it needs would repeat that work for
 // every panel pair.  So the rows are processed in passes of up to about 1 GiB
 // of digit planes:
-//   slice  grid (64-column groups, 2048-row slabs): the exact column maxima of
-//          the slab give E_j = ilogb(max) + 4 (so |a| < 2^(E_j - 3)), then every
-//          entry is written as SS int8 digit planes, plane-major, 64 bytes per
-//          (chunk of 64 rows, column);
-//   syrk   grid (64-column panel pairs I <= J, groups of 4 slabs): 16
+//   slice  one wavefront per (column, 2048-row slab), the slab's column in its
+//          registers (A is read once): the exact maximum gives
+//          E_j = ilogb(max) + 4 (so |a| < 2^(E_j - 3)), then every entry is
+//          written as SS int8 digit planes, plane-major, 64 bytes per (chunk of
+//          64 rows, column);
+//   syrk   one workgroup per (64-column panel pair I <= J, group of 4 slabs),
+//          the pairs of a group on one XCD (they read the same planes): 16
 //          wavefronts, one 16 x 16 tile each (a diagonal pair uses the upper
 //          ten), load the chunk's planes of both panels straight into LDS (the
 //          next chunk's loads in flight meanwhile) and accumulate the digit-pair
@@ -67,76 +69,69 @@ __device__ __forceinline__ double sw_finite_abs(double a, bool &bad) {
     return fin ? x : 0.0;
 }
 
+// grid (npad / 4, slabs of the pass); 4 wavefronts, one column of the slab each.
+// Lane l holds rows 4 (l % 16) .. + 3 of chunks l / 16, 4 + l / 16, ... of the
+// slab: the column's 2048 rows sit in registers, so A is read once for both the
+// exact maximum and the digits.
 template <typename T, int SS>
 __global__ void __launch_bounds__(256)
 sw_slice_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int npad, int64_t row0,
                 int nchp, signed char *__restrict__ planes, int *__restrict__ expo,
                 int *__restrict__ nonfinite) {
-    __shared__ int Es[SW_P];
-    const int cg = blockIdx.x, sl = blockIdx.y;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int IT = SW_SR / 256;  // chunk quadruples of a slab
+    const int lane = threadIdx.x & 63;
+    const int c = 4 * blockIdx.x + (threadIdx.x >> 6);  // < npad
+    const int sl = blockIdx.y;
     const int64_t r0 = row0 + (int64_t)sl * SW_SR;
     const int64_t r1 = (r0 + SW_SR < m) ? r0 + SW_SR : m;
+    const int prow = 4 * (lane & 15);
+    const T *col = A + (int64_t)c * lda;
     bool bad = false;
-    // exact column maxima of the slab: wavefront w takes columns 16 w .. 16 w + 15
-    for (int j = 0; j < 16; ++j) {
-        const int cl = 16 * w + j, c = SW_P * cg + cl;
-        double mx = 0.0;
-        if (c < n)
-            for (int64_t r = r0 + lane; r < r1; r += 64)
-                mx = fmax(mx, sw_finite_abs((double)A[r + (int64_t)c * lda], bad));
+    double v[IT][4];
+    double mx = 0.0;
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-        if (lane == 0) {
-            const int e = need_exp(mx);
-            Es[cl] = e;
-            expo[(int64_t)sl * npad + c] = e;
+    for (int it = 0; it < IT; ++it) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = r0 + 256 * it + 64 * (lane >> 4) + prow + q;
+            const double x = (c < n && r < r1) ? (double)col[r] : 0.0;
+            // a NaN or Inf entry counts as zero (the flag is set below)
+            const double ax = sw_finite_abs(x, bad);
+            v[it][q] = ax == 0.0 ? 0.0 : x;
+            mx = fmax(mx, ax);
         }
     }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    const int E = need_exp(mx);
+    if (lane == 0) expo[(int64_t)sl * npad + c] = E;
     if (bad) *nonfinite = 1;
-    __syncthreads();
-    // digits: lane l holds rows 4 (l % 16) .. + 3 of column 16 s + 4 w + l / 16
     constexpr int NW3 = (SS + 3) / 4;
-    const int prow = 4 * (lane & 15);
-    for (int k = 0; k < SW_CPS; ++k) {
-        const int64_t rb = r0 + (int64_t)k * SP_KT + prow;
-        const int chl = sl * SW_CPS + k;  // chunk within the pass
+    const int64_t plane_stride = (int64_t)nchp * npad * SP_KT;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int cl = 16 * s + 4 * w + (lane >> 4), c = SW_P * cg + cl;
-            const int E = Es[cl];
-            double v[4];
+    for (int it = 0; it < IT; ++it) {
+        unsigned wd[3][4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t r = rb + q;
-                v[q] = (c < n && r < r1) ? (double)A[r + (int64_t)c * lda] : 0.0;
-                bool nf = false;
-                sw_finite_abs(v[q], nf);
-                if (nf) v[q] = 0.0;  // digits only for finite values (the flag is set above)
+        for (int q = 0; q < 4; ++q) {
+            if (E > SP_NOEXP) {
+                balanced96<NW3>(v[it][q], E, wd[0][q], wd[1][q], wd[2][q]);
+            } else {  // an all-zero column: zero digits
+                wd[0][q] = 0u;
+                wd[1][q] = 0u;
+                wd[2][q] = 0u;
             }
-            unsigned wd[3][4];
+        }
+        const int chl = sl * SW_CPS + 4 * it + (lane >> 4);  // chunk within the pass
+        signed char *pd = planes + ((int64_t)chl * npad + c) * SP_KT + prow;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (E > SP_NOEXP) {
-                    balanced96<NW3>(v[q], E, wd[0][q], wd[1][q], wd[2][q]);
-                } else {  // an all-zero column: zero digits
-                    wd[0][q] = 0u;
-                    wd[1][q] = 0u;
-                    wd[2][q] = 0u;
-                }
-            }
-            signed char *pd = planes + ((int64_t)chl * npad + c) * SP_KT + prow;
-            const int64_t plane_stride = (int64_t)nchp * npad * SP_KT;
+        for (int kw = 0; kw < NW3; ++kw) {
+            unsigned o[4];
+            transpose4(wd[kw][0], wd[kw][1], wd[kw][2], wd[kw][3], o[0], o[1], o[2], o[3]);
+            // word kw holds digits 4 kw + 1 (top byte) .. 4 kw + 4 (low byte)
 #pragma unroll
-            for (int kw = 0; kw < NW3; ++kw) {
-                unsigned o[4];
-                transpose4(wd[kw][0], wd[kw][1], wd[kw][2], wd[kw][3], o[0], o[1], o[2], o[3]);
-                // word kw holds digits 4 kw + 1 (top byte) .. 4 kw + 4 (low byte)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int r = 4 * kw + (3 - j);
-                    if (r < SS) *reinterpret_cast<unsigned *>(pd + r * plane_stride) = o[j];
-                }
+            for (int j = 0; j < 4; ++j) {
+                const int r = 4 * kw + (3 - j);
+                if (r < SS) *reinterpret_cast<unsigned *>(pd + r * plane_stride) = o[j];
             }
         }
     }
@@ -148,19 +143,26 @@ sw_slice_kernel(const T *__restrict__ A, int64_t lda, int64_t m, int n, int npad
 // consecutive columns, one part) hit 16 distinct groups of four banks.
 __device__ __forceinline__ int sw_part(int k, int part) { return part ^ ((k >> 2) & 3); }
 
-// grid (npair, groups of the pass); 16 wavefronts, one tile each.  The planes
+// grid 8 x ceil(npair groups / 8) (the order below); 16 wavefronts, one tile each.  The planes
 // of a chunk move from global memory straight into LDS (global_load_lds, 16
 // bytes per lane, no staging registers), two buffers when they fit.
 template <int SS, bool DD>
 __global__ void __launch_bounds__(SW_THR)
 sw_syrk_kernel(const signed char *__restrict__ planes, const int *__restrict__ expo, int npad,
-               int np, int nchp, int nch_valid, int first, double *__restrict__ slots) {
+               int np, int npair, int groups, int nchp, int nch_valid, int first,
+               double *__restrict__ slots) {
     extern __shared__ __attribute__((aligned(16))) unsigned char swsm[];
     constexpr int PL = 2 * SW_P * SP_KT;             // LDS bytes per plane (8 KiB)
     constexpr int BUFB = SS * PL;                    // one chunk
     constexpr int NBUF = 2 * BUFB <= 160 * 1024 ? 2 : 1;
     constexpr int NLD = SS * 8;                      // 1 KiB wavefront loads per chunk
-    const int pair = blockIdx.x, grp = blockIdx.y, npair = gridDim.x;
+    // Workgroup b runs on XCD b % 8.  The (group, pair) items are taken in group-major
+    // order and XCD x works through the x-th eighth of that order, so the pairs that
+    // read one group's planes share an L2.
+    const int per = (int)(((int64_t)groups * npair + 7) / 8);
+    const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (item >= groups * npair) return;
+    const int grp = item / npair, pair = item % npair;
     int I, J;
     sw_pair(pair, np, I, J);
     const int tid = threadIdx.x, lane = tid & 63;
@@ -338,12 +340,13 @@ hipError_t sw_run(int64_t m, int64_t n, const T *A, int64_t lda, double *Mhi, do
         const int64_t rows = (m - row0 < p.rows_per_pass) ? m - row0 : p.rows_per_pass;
         const unsigned slabs = (unsigned)((rows + SW_SR - 1) / SW_SR);
         const unsigned groups = (unsigned)((rows + SW_RW - 1) / SW_RW);
-        hipLaunchKernelGGL((sw_slice_kernel<T, SS>), dim3((unsigned)p.np, slabs), dim3(256), 0, st,
-                           A, lda, m, (int)n, p.npad, row0, nchp, planes, expo, nonfinite);
+        hipLaunchKernelGGL((sw_slice_kernel<T, SS>), dim3((unsigned)(p.npad / 4), slabs), dim3(256),
+                           0, st, A, lda, m, (int)n, p.npad, row0, nchp, planes, expo, nonfinite);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        hipLaunchKernelGGL(ks, dim3((unsigned)p.npair, groups), dim3(SW_THR), lds, st, planes,
-                           expo, p.npad, p.np, nchp, (int)((rows + SP_KT - 1) / SP_KT),
-                           ps == 0 ? 1 : 0, slots);
+        const unsigned items = (unsigned)p.npair * groups;
+        hipLaunchKernelGGL(ks, dim3(8 * ((items + 7) / 8)), dim3(SW_THR), lds, st, planes, expo,
+                           p.npad, p.np, p.npair, (int)groups, nchp,
+                           (int)((rows + SP_KT - 1) / SP_KT), ps == 0 ? 1 : 0, slots);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     const int64_t entries = (int64_t)p.npair * 16 * 64 * 4;
