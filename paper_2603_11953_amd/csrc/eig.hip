@@ -121,6 +121,79 @@ __device__ __forceinline__ double group_sum(double x) {
     return x;
 }
 
+// Back substitution of the preconditioner form, V' = X'^-1 T with T = Q Sigma_Z
+// (columns scaled by ssig), X' upper triangular: Rs holds R'_rk / R'_kk above the
+// diagonal (zeros elsewhere), rinv 1 / R'_kk.  Each wavefront solves its own
+// columns, up to four at a time, lane l holding rows l + 64 j (j < NR, n <= 64 NR),
+// with no workgroup barrier: at step k the final (not yet divided) t_k of each
+// column is read from its lane and the rows r < k take -(R'_rk / R'_kk) t_k; the
+// next column of Rs is read one step ahead.  Then x_r = t_r / R'_rr, the scaling
+// by 2^(emax - e_pi_r),
+// the column's norm (a butterfly sum: every lane gets the same bits) and the
+// store into row pi_r of V.
+template <int NR, typename TW>
+__device__ __forceinline__ void pre_backsub(int n, const double *T, const double *Rs, int ld,
+                                            const double *ssig, const double *rinv,
+                                            const int *sexp, const int *sperm, int emax,
+                                            TW *__restrict__ V, int64_t ldv) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    for (int p0 = wv; p0 < n; p0 += 4 * nwv) {
+        double t[4][NR];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int p = p0 + c * nwv;
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const int r = lane + 64 * j;
+                t[c][j] = (p < n && r < n) ? T[r + p * ld] * ssig[p] : 0.0;
+            }
+        }
+        // column k of Rs, one step ahead (rows k and beyond read zeros)
+        double rn[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const int r = lane + 64 * j;
+            rn[j] = r < n ? Rs[r + (n - 1) * ld] : 0.0;
+        }
+        for (int k = n - 1; k >= 1; --k) {
+            double rc[NR];
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                rc[j] = rn[j];
+                const int r = lane + 64 * j;
+                rn[j] = r < n ? Rs[r + (k - 1) * ld] : 0.0;
+            }
+            const int kl = k & 63;  // uniform
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double tk = readlane_d(NR == 1 || k < 64 ? t[c][0] : t[c][NR - 1], kl);
+#pragma unroll
+                for (int j = 0; j < NR; ++j) t[c][j] = __builtin_fma(-rc[j], tk, t[c][j]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int p = p0 + c * nwv;
+            if (p >= n) break;  // uniform
+            double x[NR], ss = 0.0;
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const int r = lane + 64 * j;
+                x[j] = r < n ? ldexp(t[c][j] * rinv[r], emax - sexp[sperm[r]]) : 0.0;
+                ss = __builtin_fma(x[j], x[j], ss);
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
+            const double inv = 1.0 / __builtin_sqrt(ss);
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const int r = lane + 64 * j;
+                if (r < n) V[sperm[r] + (int64_t)p * ldv] = (TW)(x[j] * inv);
+            }
+        }
+    }
+}
+
 // Workgroup-shared state of the eigensolver besides the dynamic LDS square.
 struct EigSmem {
     EigShared sh;
@@ -560,67 +633,18 @@ __device__ __forceinline__ void eig_body(int n, const double *__restrict__ Mhi,
         __syncthreads();
         double *T = reinterpret_cast<double *>(Vs);  // TS = double in this form
         double *Rt = reinterpret_cast<double *>(Y);
+        // R'_rk / R'_kk (r < k) into the Y area, 1 / R'_kk into ssign
         for (int q = tid; q < n * n; q += nthr) {
-            const int r = q % n, p = q / n;
-            Rt[r + p * ld] = r <= p ? (double)W[r + (int64_t)p * ldw] : 0.0;
+            const int r = q % n, k = q / n;
+            Rt[r + k * ld] = r < k ? (double)W[r + (int64_t)k * ldw] / (double)W[k + (int64_t)k * ldw]
+                                   : 0.0;
         }
         for (int k = tid; k < n; k += nthr) ssign[k] = 1.0 / (double)W[k + (int64_t)k * ldw];
         __syncthreads();
-        // Each wavefront solves its own columns (up to four at a time, lane l holding
-        // rows l and l + 64), with no workgroup barrier: at step k the final (unscaled)
-        // t_k of each column is read from its lane and rows r < k take
-        // -R'_rk t_k / R'_kk.  Then x_r = t_r / R'_rr, the scaling by 2^(emax - e_pi_r),
-        // the column's norm (a butterfly sum: every lane gets the same bits) and the
-        // store into row pi_r of V.
-        const int lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
-        for (int p0 = wv; p0 < n; p0 += 4 * nwv) {
-            double t[4][2];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int p = p0 + c * nwv;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int r = lane + 64 * j;
-                    t[c][j] = (p < n && r < n) ? T[r + p * ld] * ssig[p] : 0.0;
-                }
-            }
-            for (int k = n - 1; k >= 1; --k) {
-                const int kj = k >> 6, kl = k & 63;  // uniform
-                const double rk = ssign[k];
-                double rc[2];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int r = lane + 64 * j;
-                    rc[j] = r < k ? Rt[r + k * ld] : 0.0;  // rows k and beyond are final
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const double tk = rk * readlane_d(kj ? t[c][1] : t[c][0], kl);
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) t[c][j] = __builtin_fma(-rc[j], tk, t[c][j]);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int p = p0 + c * nwv;
-                if (p >= n) break;  // uniform
-                double x[2], ss = 0.0;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int r = lane + 64 * j;
-                    x[j] = r < n ? ldexp(t[c][j] * ssign[r], emax - sexp[sperm[r]]) : 0.0;
-                    ss = __builtin_fma(x[j], x[j], ss);
-                }
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
-                const double inv = 1.0 / __builtin_sqrt(ss);
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int r = lane + 64 * j;
-                    if (r < n) V[sperm[r] + (int64_t)p * ldv] = (TW)(x[j] * inv);
-                }
-            }
-        }
+        if (n <= 64)
+            pre_backsub<1>(n, T, Rt, ld, ssig, ssign, sexp, sperm, emax, V, ldv);
+        else
+            pre_backsub<2>(n, T, Rt, ld, ssig, ssign, sexp, sperm, emax, V, ldv);
         if (tid == 0) *info = 0;
         return;
     }
