@@ -660,6 +660,203 @@ __global__ void __launch_bounds__(64) weig_sweep_kernel(Ctl *ctl, int nwg, int l
 // register r is (V Q)(4 r + l / 16, c0 + l % 16).
 constexpr int VRW = 16;  // rows of V per workgroup
 
+// Preconditioner form of a step: the same rotations, taken on the block pair's Gram
+// matrix.  G = X_b^T X_b (JC x JC) comes from the FP64 matrix cores; each round's
+// rotations J then act on both sides, G <- J^T G J, and on Q <- Q J, one entry per
+// lane (an entry of G from the same four-term formula for (a, b) and (b, a), so G
+// stays exactly symmetric); at the end X_b <- X_b Q on the matrix cores.  A round
+// costs two short LDS passes instead of sums over the n rows of both columns.  The
+// inner products are those of the current columns up to the rounding of the
+// two-sided updates, the accuracy a preconditioner needs (the dd stage then works
+// at u_h).
+template <int RPL, int JB>
+__global__ void __launch_bounds__(64 * JB)
+weig_gstep_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict__ X,
+                  double *__restrict__ Qbuf, double *__restrict__ Vw, double tol2) {
+    extern __shared__ __attribute__((aligned(16))) double jsm[];
+    constexpr int JC = JGeom<JB>::JC, JT = JGeom<JB>::JT;
+    static_assert(JT >= JC * JC && JT >= 3 * 64, "one lane per entry of G and Q");
+    constexpr int LDL = 64 * RPL;  // rows of a column (n rounded up to 64)
+    constexpr int LDP = LDL + 1;   // column stride in LDS: a row's columns in distinct banks
+    double *Xl = jsm;              // JC columns of X
+    double *G = Xl + JC * LDP;     // JC x JC, column-major, two buffers (rounds alternate)
+    double *Qm = G + 2 * JC * JC;  // JC x JC rotation product, row-major
+    double *cr = Qm + JC * JC;     // per column: the cosine of its pair this round
+    double *tr = cr + JC;          // per column: the coefficient of its partner
+    int *pr = reinterpret_cast<int *>(tr + JC);  // per column: its partner this round
+    if ((int)blockIdx.x >= nblk / 2) {
+        vapply_prev<JB>(n, nblk, g, ctl, Qbuf, Vw, (int)blockIdx.x - nblk / 2, jsm);
+        return;
+    }
+    if (wg_read(&ctl->bad) || wg_read(&ctl->done)) return;
+    // this launch's rotations run (done and bad are the same for all its workgroups)
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->qran[g & 1] = g;
+    int P, Qb;
+    rr_pair(step, blockIdx.x, nblk, P, Qb);
+    const int nbb = (n + JB - 1) / JB;
+    if ((P >= nbb && Qb >= nbb) || ((P >= nbb || Qb >= nbb) && step != 0)) return;
+    const int tid = threadIdx.x;
+    auto gcol = [&](int c) { return c < JB ? JB * P + c : JB * Qb + (c - JB); };
+    constexpr int NLD = JC * LDL / JT;  // block values per lane
+    {
+        double v[NLD];
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int q = tid + k * JT;
+            const int r = q % LDL, gc = gcol(q / LDL);
+            v[k] = (r < n && gc < n) ? X[r + (size_t)gc * n] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int q = tid + k * JT;
+            Xl[(q / LDL) * LDP + q % LDL] = v[k];
+        }
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // G: wavefronts 0 .. 5 form the tiles (0, 0), (0, 1), (1, 1) (tile = w mod 3) over
+    // the two halves of the rows (w / 3), four accumulators each (k mod 16 in steps of
+    // 4); the second halves' partial tiles pass through the Q area, and the first
+    // halves' wavefronts add them, in that order
+    const int gtile = wave % 3, ghalf = wave / 3;
+    f64x4 gacc = {0.0, 0.0, 0.0, 0.0};
+    if (wave < 6) {
+        const int I = gtile == 2 ? 1 : 0, J = gtile == 0 ? 0 : 1;
+        const double *xa = Xl + (16 * I + li) * LDP + lk;
+        const double *xb = Xl + (16 * J + li) * LDP + lk;
+        f64x4 acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = ghalf * (LDL / 2); k0 < (ghalf + 1) * (LDL / 2); k0 += 16) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0 + 4 * u], xb[k0 + 4 * u],
+                                                              acc[u], 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            gacc[r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+            if (ghalf == 1) Qm[(gtile * 4 + r) * 64 + lane] = gacc[r];  // 768 <= JC JC doubles
+        }
+    }
+    __syncthreads();
+    if (wave < 3) {
+        const int I = gtile == 2 ? 1 : 0, J = gtile == 0 ? 0 : 1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double v = gacc[r] + Qm[(gtile * 4 + r) * 64 + lane];
+            const int i = 16 * I + 4 * r + lk, j = 16 * J + li;
+            if (i <= j) {
+                G[i + JC * j] = v;
+                G[j + JC * i] = v;
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < JC * JC; q += JT) Qm[q] = (q / JC == q % JC) ? 1.0 : 0.0;
+    __syncthreads();
+
+    int any = 0;  // 1: a rotation, 2: one of a pair with cosine >= TAU_BIG
+    // lane (a, b) of G (a = tid % JC) and (i, j) of Q (j = tid % JC; row i of Q lies in
+    // one wavefront, so Q is updated in place: its reads come before its writes).  Entry (a, b) of
+    // J^T G J is formed from (a0, b0) = (min, max) in one order, for both triangles;
+    // its four inputs G(x, y), x in {a, pa}, y in {b, pb}, are read as G[x + JC y]
+    // (G is symmetric), so the lanes of a wavefront read along columns
+    const bool ent = tid < JC * JC;
+    const int ga_ = tid % JC, gb_ = tid / JC;
+    const bool low = ga_ > gb_;  // (a0, b0) = (b, a)
+    const int a0 = low ? gb_ : ga_, b0 = low ? ga_ : gb_;
+    const int qi = tid / JC, qj = tid % JC;
+    // one round: pair k (k < JB) of the round is (p, q); p's partner enters with -s
+    int cur = 0;  // G's buffer of this round
+    auto round = [&](auto pair_of) {
+        const double *Gc = G + cur * (JC * JC);
+        double *Gn = G + (cur ^ 1) * (JC * JC);
+        if (wave == 0 && lane < JB) {
+            int p, q;
+            pair_of(lane, p, q);
+            const double al = Gc[p + JC * p], be = Gc[q + JC * q], gpq = Gc[p + JC * q];
+            double c = 1.0, sn = 0.0;
+            if (gpq * gpq > tol2 * (al * be)) {
+                jacobi_cs(al, be, gpq, c, sn);
+                const int lv = gpq * gpq >= (TAU_BIG * TAU_BIG) * (al * be) ? 2 : 1;
+                any = any > lv ? any : lv;
+            }
+            cr[p] = c;
+            tr[p] = -sn;
+            pr[p] = q;
+            cr[q] = c;
+            tr[q] = sn;
+            pr[q] = p;
+        }
+        __syncthreads();
+        if (ent) {
+            const int pa = pr[ga_], pb = pr[gb_];  // partners of a and b
+            const double ca = cr[a0], ta = tr[a0], cb = cr[b0], tb = tr[b0];
+            // G(a0, b0), G(a0, p b0), G(p a0, b0), G(p a0, p b0)
+            const double g00 = Gc[ga_ + JC * gb_];
+            const double g01 = low ? Gc[pa + JC * gb_] : Gc[ga_ + JC * pb];
+            const double g10 = low ? Gc[ga_ + JC * pb] : Gc[pa + JC * gb_];
+            const double g11 = Gc[pa + JC * pb];
+            Gn[ga_ + JC * gb_] = __builtin_fma(ta * tb, g11, __builtin_fma(ta * cb, g10,
+                                               __builtin_fma(ca * tb, g01, (ca * cb) * g00)));
+            const int pj = pr[qj];
+            const double q0 = Qm[qi * JC + qj], q1 = Qm[qi * JC + pj];
+            Qm[qi * JC + qj] = __builtin_fma(tr[qj], q1, cr[qj] * q0);
+        }
+        cur ^= 1;
+        __syncthreads();
+    };
+    if (step == 0) {  // the pairs inside block P and inside block Q
+        for (int r = 0; r < JB - 1; ++r)
+            round([&](int k, int &p, int &q) {
+                const int h = k / (JB / 2);
+                rr_pair(r, k % (JB / 2), JB, p, q);
+                p += JB * h;
+                q += JB * h;
+            });
+    }
+    for (int r = 0; r < JB; ++r)  // the cross pairs (k, JB + (k + r) mod JB)
+        round([&](int k, int &p, int &q) {
+            p = k;
+            q = JB + (k + r) % JB;
+        });
+
+    // X <- X Q: wavefront w takes row tiles w, w + JT / 64, ... (all JC columns), and
+    // writes its rows back in place once it has read them
+    for (int ti = wave; ti < LDL / 16; ti += JT / 64) {
+        f64x4 acc[JC / 16];
+#pragma unroll
+        for (int t = 0; t < JC / 16; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k0 = 0; k0 < JC; k0 += 4) {
+            const double av = Xl[(k0 + lk) * LDP + 16 * ti + li];
+#pragma unroll
+            for (int t = 0; t < JC / 16; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Qm[(k0 + lk) * JC + 16 * t + li],
+                                                              acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < JC / 16; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Xl[(16 * t + li) * LDP + 16 * ti + 4 * r + lk] = acc[t][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int q = tid + k * JT;
+        const int r = q % LDL, gc = gcol(q / LDL);
+        if (r < n && gc < n) X[r + (size_t)gc * n] = Xl[(q / LDL) * LDP + r];
+    }
+    double *Qo = Qbuf + ((size_t)(g & 1) * (nblk / 2) + blockIdx.x) * (JC * JC);
+    for (int q = tid; q < JC * JC; q += JT) Qo[q] = Qm[q];
+    const bool big = __syncthreads_or(any == 2), some = __syncthreads_or(any != 0);
+    const int lvl = big ? 2 : (some ? 1 : 0);
+    if (tid == 0 && lvl > ctl->rot[blockIdx.x]) ctl->rot[blockIdx.x] = lvl;
+}
+
 template <int JB>
 __device__ __forceinline__ void vapply_step(int n, int nblk, int st, const double *__restrict__ Qs,
                                             double *__restrict__ Vw, int r0, double *vsm) {
@@ -968,8 +1165,9 @@ hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double
                         double tol2, int max_sweeps, bool early, hipStream_t st) {
     constexpr int JC = JGeom<JB>::JC, JT = JGeom<JB>::JT, QLD = JGeom<JB>::QLD;
     // the Jacobi role's LDS; the V role needs VRW n <= JC 64 RPL doubles of it
-    const size_t lds = ((size_t)JC * 64 * RPL + JC * QLD + JC) * sizeof(double);
-    auto k = early ? weig_step_kernel<RPL, JB, true> : weig_step_kernel<RPL, JB, false>;
+    const size_t lds = early ? ((size_t)JC * (64 * RPL + 1) + 3 * JC * JC + 3 * JC) * sizeof(double)
+                             : ((size_t)JC * 64 * RPL + JC * QLD + JC) * sizeof(double);
+    auto k = early ? weig_gstep_kernel<RPL, JB> : weig_step_kernel<RPL, JB, false>;
     auto kf = weig_vflush_kernel<JB>;
     const size_t lds_v = (size_t)VRW * n * sizeof(double);
     const int vstrips = (n + VRW - 1) / VRW;
