@@ -716,20 +716,22 @@ weig_gstep_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict
 
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    // G: wavefronts 0 .. 5 form the tiles (0, 0), (0, 1), (1, 1) (tile = w mod 3) over
-    // the two halves of the rows (w / 3), four accumulators each (k mod 16 in steps of
-    // 4); the second halves' partial tiles pass through the Q area, and the first
-    // halves' wavefronts add them, in that order
-    const int gtile = wave % 3, ghalf = wave / 3;
-    f64x4 gacc = {0.0, 0.0, 0.0, 0.0};
-    if (wave < 6) {
+    // G: wavefronts 0 .. 11 form the tiles (0, 0), (0, 1), (1, 1) (tile = w mod 3) over
+    // the four quarters of the rows (w / 3), four accumulators each (k mod 16 in steps
+    // of 4); the quarters' partial tiles pass through the second G buffer and Q, and
+    // are summed in a fixed order, (q0 + q1) + (q2 + q3)
+    static_assert(JT >= 12 * 64 && 3 * JC * JC >= 2 * 768 + JC * JC, "G's wavefronts and scratch");
+    const int gtile = wave % 3, gq = wave / 3;
+    double gv[4] = {0.0, 0.0, 0.0, 0.0};
+    double *gpart = G + JC * JC;  // 2 x 768 doubles over the second G buffer and Q
+    if (wave < 12) {
         const int I = gtile == 2 ? 1 : 0, J = gtile == 0 ? 0 : 1;
         const double *xa = Xl + (16 * I + li) * LDP + lk;
         const double *xb = Xl + (16 * J + li) * LDP + lk;
         f64x4 acc[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
-        for (int k0 = ghalf * (LDL / 2); k0 < (ghalf + 1) * (LDL / 2); k0 += 16) {
+        for (int k0 = gq * (LDL / 4); k0 < (gq + 1) * (LDL / 4); k0 += 16) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0 + 4 * u], xb[k0 + 4 * u],
@@ -737,16 +739,26 @@ weig_gstep_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            gacc[r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
-            if (ghalf == 1) Qm[(gtile * 4 + r) * 64 + lane] = gacc[r];  // 768 <= JC JC doubles
+            gv[r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+            if (gq & 1) gpart[(gq >> 1) * 768 + (gtile * 4 + r) * 64 + lane] = gv[r];
         }
+    }
+    __syncthreads();
+    if (wave < 12 && !(gq & 1)) {  // q0 + q1, q2 + q3
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gv[r] += gpart[(gq >> 1) * 768 + (gtile * 4 + r) * 64 + lane];
+    }
+    __syncthreads();
+    if (wave < 12 && gq == 2) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gpart[(gtile * 4 + r) * 64 + lane] = gv[r];
     }
     __syncthreads();
     if (wave < 3) {
         const int I = gtile == 2 ? 1 : 0, J = gtile == 0 ? 0 : 1;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double v = gacc[r] + Qm[(gtile * 4 + r) * 64 + lane];
+            const double v = gv[r] + gpart[(gtile * 4 + r) * 64 + lane];
             const int i = 16 * I + 4 * r + lk, j = 16 * J + li;
             if (i <= j) {
                 G[i + JC * j] = v;
