@@ -49,8 +49,12 @@
 //   3'. X' = R' D~' 2^-emax as before, and the Jacobi runs on Z = X'^T: for a
 //      row-graded triangular factor the columns of Z are far closer to
 //      orthogonal than those of X', so fewer sweeps are needed (the idea of the
-//      QR-preconditioned Jacobi SVD of Drmac and Veselic).  The rotations
-//      still accumulate in Q.  The last tournament round is the first whose
+//      QR-preconditioned Jacobi SVD of Drmac and Veselic).  A step takes its
+//      rotations on the block pair's Gram matrix G = X_b^T X_b (formed on the
+//      FP64 matrix cores) as two-sided rotations G <- J^T G J, accumulates them in
+//      Q and applies X_b <- X_b Q at the end (matrix cores again): the same
+//      pairs and angles as the one-sided step, with the inner products updated
+//      instead of summed over the n rows.  The last tournament round is the first whose
 //      rotated pairs all had cosines below 2^-10 (quadratic convergence leaves
 //      cosines of order 2^-20 or less, far inside the next stage's reach).
 //   5'. Z Q = V' Sigma and X' = Q Sigma V'^T give V' = X'^-1 Q Sigma: V' comes
@@ -437,22 +441,16 @@ struct JGeom {
     static constexpr int QLD = JC + 2;
 };
 
-// TRACK (the preconditioner form): the squared column norms are formed once per step
-// and then carried through the rotations, ||x'||^2 = ||x||^2 - t x^T y and
-// ||y'||^2 = ||y||^2 + t x^T y with t = tan of the angle (exact when x'^T y' = 0; the
-// one-sided Jacobi of LAPACK's xGESVJ keeps its norms the same way), so a round
-// needs one cross-lane sum instead of three; a norm that the update would shrink
-// below 2^-10 of itself is summed again.  Without TRACK (Algorithm 2) every round
-// sums all three inner products.
 template <int JB>
 __device__ __forceinline__ void vapply_prev(int n, int nblk, int g, const Ctl *ctl,
                                             const double *__restrict__ Qbuf,
                                             double *__restrict__ Vw, int vb, double *vsm);
 
-// Step launch g (= round * (nblk - 1) + step): workgroups 0 .. nblk/2 - 1 run the
-// step's rotations and write their products to slot g & 1; the rest (one per 16
-// rows of V) apply the products of launch g - 1 to V meanwhile, on other CUs.
-template <int RPL, int JB, bool TRACK>
+// Step launch g (= round * (nblk - 1) + step) of Algorithm 2: workgroups 0 ..
+// nblk/2 - 1 run the step's one-sided rotations (every round sums the three inner
+// products of its pair afresh) and write their products to slot g & 1; the rest (one
+// per 16 rows of V) apply the products of launch g - 1 to V meanwhile, on other CUs.
+template <int RPL, int JB>
 __global__ void __launch_bounds__(64 * JB)
 weig_step_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict__ X,
                  double *__restrict__ Qbuf, double *__restrict__ Vw, double tol2) {
@@ -461,7 +459,6 @@ weig_step_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict_
     constexpr int LDL = 64 * RPL;  // rows of a column in LDS (n rounded up to 64)
     double *Xl = jsm;              // JC columns of X
     double *Qs = jsm + JC * LDL;   // JC x JC rotation product, column-major, stride QLD
-    double *nrm = Qs + JC * QLD;   // TRACK: squared column norms
     if ((int)blockIdx.x >= nblk / 2) {
         vapply_prev<JB>(n, nblk, g, ctl, Qbuf, Vw, (int)blockIdx.x - nblk / 2, jsm);
         return;
@@ -495,43 +492,18 @@ weig_step_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict_
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6;
-    auto sq_sum = [&](const double (&x)[RPL]) {
-        double ss = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) ss = __builtin_fma(x[i], x[i], ss);
-        return wave_sum(ss);
-    };
-    if constexpr (TRACK) {
-        for (int c = wave; c < JC; c += JT / 64) {
-            double x[RPL];
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) x[i] = Xl[c * LDL + lane + 64 * i];
-            const double ss = sq_sum(x);
-            if (lane == 0) nrm[c] = ss;
-        }
-        __syncthreads();
-    }
     int any = 0;  // 1: a rotation, 2: one of a pair with cosine >= TAU_BIG
-    // one plane rotation of columns x0 (p) and x1 (q), held in registers; also on Q.
-    // TRACK: al, be carry the squared norms in and out.
-    auto rotate = [&](double (&x0)[RPL], double (&x1)[RPL], int p, int q, double &al,
-                      double &be) -> bool {
-        double ga = 0.0;
-        if constexpr (TRACK) {
+    // one plane rotation of columns x0 (p) and x1 (q), held in registers; also on Q
+    auto rotate = [&](double (&x0)[RPL], double (&x1)[RPL], int p, int q) -> bool {
+        double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) ga = __builtin_fma(x0[i], x1[i], ga);
-        } else {
-            al = 0.0;
-            be = 0.0;
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                al = __builtin_fma(x0[i], x0[i], al);
-                be = __builtin_fma(x1[i], x1[i], be);
-                ga = __builtin_fma(x0[i], x1[i], ga);
-            }
-            al = wave_sum(al);
-            be = wave_sum(be);
+        for (int i = 0; i < RPL; ++i) {
+            al = __builtin_fma(x0[i], x0[i], al);
+            be = __builtin_fma(x1[i], x1[i], be);
+            ga = __builtin_fma(x0[i], x1[i], ga);
         }
+        al = wave_sum(al);
+        be = wave_sum(be);
         ga = wave_sum(ga);
         if (!(ga * ga > tol2 * (al * be))) return false;  // uniform: the sums agree bitwise
         double c, sn;
@@ -549,14 +521,6 @@ weig_step_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict_
         }
         if (ga * ga >= (TAU_BIG * TAU_BIG) * (al * be)) any = 2;
         else if (any == 0) any = 1;
-        if constexpr (TRACK) {
-            const double t = sn / c;  // c >= 1/sqrt(2)
-            double a2 = __builtin_fma(-t, ga, al), b2 = __builtin_fma(t, ga, be);
-            if (!(a2 > 0x1p-10 * al)) a2 = sq_sum(x0);  // uniform across the wavefront
-            if (!(b2 > 0x1p-10 * be)) b2 = sq_sum(x1);
-            al = a2;
-            be = b2;
-        }
         return true;
     };
     double x0[RPL], x1[RPL];
@@ -575,20 +539,11 @@ weig_step_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict_
                 x0[i] = xp[64 * i];
                 x1[i] = xq[64 * i];
             }
-            double al = 0.0, be = 0.0;
-            if constexpr (TRACK) {
-                al = nrm[p];
-                be = nrm[q];
-            }
-            if (rotate(x0, x1, p, q, al, be)) {
+            if (rotate(x0, x1, p, q)) {
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) {
                     xp[64 * i] = x0[i];
                     xq[64 * i] = x1[i];
-                }
-                if (TRACK && lane == 0) {
-                    nrm[p] = al;
-                    nrm[q] = be;
                 }
             }
             __syncthreads();
@@ -601,17 +556,14 @@ weig_step_kernel(int n, int nblk, int step, int g, Ctl *ctl, double *__restrict_
         double *xp = Xl + p * LDL + lane;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) x0[i] = xp[64 * i];
-        double al = TRACK ? nrm[p] : 0.0;  // the resident's norm stays in registers
         for (int r = 0; r < JB; ++r) {
             const int q = JB + (wave + r) % JB;
             double *xq = Xl + q * LDL + lane;
 #pragma unroll
             for (int i = 0; i < RPL; ++i) x1[i] = xq[64 * i];
-            double be = TRACK ? nrm[q] : 0.0;
-            if (rotate(x0, x1, p, q, al, be)) {
+            if (rotate(x0, x1, p, q)) {
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) xq[64 * i] = x1[i];
-                if (TRACK && lane == 0) nrm[q] = be;
             }
             __syncthreads();  // the travelers move on
         }
@@ -1179,7 +1131,7 @@ hipError_t launch_steps(int n, int nblk, Ctl *ctl, double *X, double *Vw, double
     // the Jacobi role's LDS; the V role needs VRW n <= JC 64 RPL doubles of it
     const size_t lds = early ? ((size_t)JC * (64 * RPL + 1) + 3 * JC * JC + 3 * JC) * sizeof(double)
                              : ((size_t)JC * 64 * RPL + JC * QLD + JC) * sizeof(double);
-    auto k = early ? weig_gstep_kernel<RPL, JB> : weig_step_kernel<RPL, JB, false>;
+    auto k = early ? weig_gstep_kernel<RPL, JB> : weig_step_kernel<RPL, JB>;
     auto kf = weig_vflush_kernel<JB>;
     const size_t lds_v = (size_t)VRW * n * sizeof(double);
     const int vstrips = (n + VRW - 1) / VRW;
