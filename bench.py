@@ -338,7 +338,14 @@ def headline_leg(args, torch, gs, g, log_fn):
     if not args.no_plain:
         res["plain"] = measure_thin(torch, gs, dA, gs.GSVD_GRAM_PLAIN, max(2, args.steps // 3),
                                     1, stream, log_fn)
-    return dict(spec=spec, dA=dA, Y=Y, res=res, m=m, n=n)
+    # the vendor library's FP64 GEMM on U's shape (A times an n x n matrix): the matrix-core
+    # rate a tuned GEMM sustains on this part, the reference ceiling for U
+    Wr = torch.randn(n, n, dtype=dA.dtype, device=dev)
+    vendor_ms = timed_on(torch, stream, lambda: torch.matmul(dA, Wr), 5, 2)
+    del Wr
+    torch.cuda.empty_cache()
+    log_fn(f"headline: vendor FP64 GEMM on U's shape {vendor_ms:.3f} ms")
+    return dict(spec=spec, dA=dA, Y=Y, res=res, m=m, n=n, vendor_gemm_ms=vendor_ms)
 
 
 def headline_check(H, torch, gs, log_fn):
@@ -577,9 +584,14 @@ def main():
                            "(A read, U written, W)",
             "ms_per_launch": round(auto["ms_u"], 4),
             "hbm_gbps": round(u_bytes / (auto["ms_u"] * 1e-3) / 1e9, 1)}
+    if H.get("vendor_gemm_ms"):
+        vend = u_flops / (H["vendor_gemm_ms"] * 1e-3) / 1e12
+        roof["measured_peak"] = round(vend, 2)
+        roof["measured_peak_source"] = ("the vendor FP64 GEMM (torch.matmul) on U's shape, "
+                                        "timed in this run")
+        roof["frac_of_measured_peak"] = round(u_tf / vend, 4)
     if "fp64_mfma_tflops" in peaks:
-        roof["measured_peak"] = peaks["fp64_mfma_tflops"]
-        roof["frac_of_measured_peak"] = round(u_tf / peaks["fp64_mfma_tflops"], 4)
+        roof["probe_peak"] = peaks["fp64_mfma_tflops"]
     S_ = auto["n_slices"]
     if S_:
         i8 = 2 * m * (n * (n + 1) // 2) * (S_ * (S_ + 1) // 2)
