@@ -74,9 +74,10 @@ enum {
                                 restores X^T X = I), until the largest angle is <= 2^-30.
                                 X comes from Algorithm 2's steps in FP64 with the columns
                                 ordered by decreasing m_jj and the one-sided Jacobi run on
-                                the transposed Cholesky factor (X by back substitution);
-                                its threshold is jacobi_tol (default 2^-24) and its sweep
-                                limit max_sweeps (default 12). */
+                                the transposed Cholesky factor (for n > 96 each block step
+                                takes the same rotations on its block pair's Gram matrix;
+                                X by back substitution); its threshold is jacobi_tol
+                                (default 2^-24) and its sweep limit max_sweeps (default 12). */
     GSVD_EIG_CHOL_JACOBI1 = 2 /* Algorithm 2: Cholesky of M_h at u_h, R cast to u,
                                  one-sided Jacobi SVD of R (Thm. 2, Lemma 1); default
                                  threshold sqrt(n) * u.  FP32 working with n > 128: the
