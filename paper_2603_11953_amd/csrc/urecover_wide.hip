@@ -3,11 +3,12 @@
 //
 // A workgroup of 16 wavefronts owns 256 rows of U (one 16-row strip per
 // wavefront) and one group of 128 columns.  The k range 0 .. n is walked in
-// chunks of 32: the chunk's 32 x 128 block of W is staged in LDS (two buffers,
-// the next one filled while the current one is used), and each wavefront loads
-// its 16 x 32 slice of A straight into MFMA operand registers (one load
-// instruction reads 16 consecutive rows of 4 columns) and runs 8 k-steps
-// against the 8 column tiles:
+// chunks of 16: the chunk's 16 x 128 block of W is staged in LDS (two buffers; the
+// next chunk's loads are issued into registers before the current chunk's products
+// and stored to the other buffer after them, so no wave waits on them), and each
+// wavefront loads its 16 x 16 slice of A straight into MFMA operand registers (one
+// load instruction reads 16 consecutive rows of 4 columns, the next chunk's issued
+// a chunk ahead) and runs 4 k-steps against the 8 column tiles:
 //   A operand (i = l % 16, k = l / 16): W(k0 + 4 s + k, 16 t + i)   from LDS
 //   B operand (k = l / 16, j = l % 16): A(r0 + j, k0 + 4 s + k)     registers
 // computing U^T = W^T A^T, so result register r of lane l is
@@ -52,7 +53,8 @@ constexpr int UW_THREADS = 64 * UW_WAVES;
 constexpr int UW_ROWS = 16 * UW_WAVES;  // rows per workgroup
 constexpr int UW_NT = 8;                // 16-column tiles per group
 constexpr int UW_COLS = 16 * UW_NT;     // columns per group
-constexpr int UW_KC = 32;               // k per chunk
+constexpr int UW_KC = 16;               // k per chunk
+constexpr int UW_KS = UW_KC / 4;        // k-steps (MFMA depth 4) per chunk
 constexpr int UW_LDW = UW_COLS + 16;    // LDS row stride: the 4 rows of one read in distinct banks
 constexpr int UW_XCD = 8;
 
@@ -78,19 +80,32 @@ urecover_wide_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__
     const bool rv = row < m;
     const int nkc = (n + UW_KC - 1) / UW_KC;
 
-    auto stage = [&](T *dst, int kc) {
-        for (int q = threadIdx.x; q < UW_KC * UW_COLS; q += UW_THREADS) {
+    // the W chunk passes through registers: its loads are issued a chunk ahead and
+    // land in LDS after the chunk's products, so no wave waits for them
+    constexpr int WPL = UW_KC * UW_COLS / UW_THREADS;  // W values per lane
+    T wr[WPL];
+    auto loadw = [&](int kc) {
+#pragma unroll
+        for (int e = 0; e < WPL; ++e) {
+            const int q = threadIdx.x + e * UW_THREADS;
             const int k = q / UW_COLS, j = q % UW_COLS;
             const int kk = UW_KC * kc + k, jj = c0 + j;
-            dst[k * UW_LDW + j] = (kk < n && jj < n) ? W[kk + (int64_t)jj * ldw] : (T)0;
+            wr[e] = (kk < n && jj < n) ? W[kk + (int64_t)jj * ldw] : (T)0;
         }
     };
-    // A(row, 32 kc + 4 s + lk), s = 0..7
-    T a[8], b[8];
+    auto storew = [&](T *dst) {
+#pragma unroll
+        for (int e = 0; e < WPL; ++e) {
+            const int q = threadIdx.x + e * UW_THREADS;
+            dst[(q / UW_COLS) * UW_LDW + q % UW_COLS] = wr[e];
+        }
+    };
+    // A(row, UW_KC kc + 4 s + lk), s < UW_KS
+    T a[UW_KS], b[UW_KS];
     auto load = [&](T *dst, int kc) {
         const T *p = A + row + (int64_t)(UW_KC * kc + lk) * lda;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
+        for (int s = 0; s < UW_KS; ++s) {
             const int k = UW_KC * kc + 4 * s + lk;
             dst[s] = (rv && k < n) ? p[(int64_t)(4 * s) * lda] : (T)0;
         }
@@ -100,23 +115,25 @@ urecover_wide_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__
 #pragma unroll
     for (int t = 0; t < UW_NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
 
-    stage(Wbuf, 0);
+    loadw(0);
     load(a, 0);
+    storew(Wbuf);
     __syncthreads();
     for (int kc = 0; kc < nkc; ++kc) {
         const bool more = kc + 1 < nkc;
         if (more) {
-            stage(Wbuf + ((kc + 1) & 1) * UW_KC * UW_LDW, kc + 1);
+            loadw(kc + 1);
             load(b, kc + 1);
         }
         const T *w = Wbuf + (kc & 1) * UW_KC * UW_LDW + lk * UW_LDW + li;
 #pragma unroll
-        for (int s = 0; s < 8; ++s)
+        for (int s = 0; s < UW_KS; ++s)
 #pragma unroll
             for (int t = 0; t < UW_NT; ++t)
                 acc[t] = WMfma<T>::step(w[4 * s * UW_LDW + 16 * t], a[s], acc[t]);
+        if (more) storew(Wbuf + ((kc + 1) & 1) * UW_KC * UW_LDW);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) a[s] = b[s];
+        for (int s = 0; s < UW_KS; ++s) a[s] = b[s];
         __syncthreads();
     }
     if (rv) {
