@@ -4,7 +4,7 @@
  * A plain, slow, CPU-only double-double (dd) reference for the mixed precision
  * Gram-based thin SVD of Carson, Ma and Shao, "Mixed precision thin SVD
  * algorithms based on the Gram matrix" (arXiv 2603.11953).  It exists so that
- * tests, the smoke check and the CPU-baseline leg of the benchmark can judge the
+ * tests, the smoke check and the CPU-baseline leg of the benchmark can check the
  * GPU path; the product path never loads it, and it shares no code, header or
  * table with the GPU library.
  *
